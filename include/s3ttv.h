@@ -1,0 +1,170 @@
+/*
+ * s3ttv.h — C ABI of the MI355X (gfx950) S3TTV denoising/destriping solver.
+ *
+ * The solver computes Alg. 1 of Takemoto, Naganuma and Ono, "Spatio-Spectral Structure
+ * Tensor Total Variation for Hyperspectral Image Denoising and Destriping" (arXiv
+ * 2404.03313): preconditioned primal-dual splitting (P-PDS) for Prob. (18)
+ *
+ *     min_{u,s,t}  sum_l || P_l D D_s u ||_*
+ *     s.t. ||s||_1 <= alpha,  ||t||_1 <= beta,  D_v t = 0,
+ *          ||u + s + t - v||_2 <= eps,  mu_min <= u <= mu_max,
+ *
+ * with the block expansion P_l of Sec. III-A (eq. SSST, eq. rewrite_Lu), the proximity
+ * operators of eqs. prox_box_constraint, prox_zeroset, prox_l2ball_constraint,
+ * prox_nuclear_norm (the latter through the Moreau identity, eq. ProxConjugate) and an
+ * exact l1-ball projection (Sec. III-C).
+ *
+ * Conventions used by every entry point
+ *  - Cubes are float32, C-contiguous, shape (N1, N2, N3) = (rows i, columns j, bands b),
+ *    band fastest: x[(i*N2 + j)*N3 + b]. D_v, D_h, D_s are periodic forward differences
+ *    along i, j and b (Sec. II-A).
+ *  - Blocks: one k1 x k2 window per pixel anchor (p, q) on the torus, L = N1*N2 blocks;
+ *    block row r = a*k2 + c covers pixel ((p+a) mod N1, (q+c) mod N2). Supported K = k1*k2
+ *    is 1..16.
+ *  - Array arguments named "device" must be device pointers (hipMalloc / torch CUDA
+ *    tensors) on the current HIP device; "host" arguments are host memory. The caller owns
+ *    every buffer; the library never allocates device memory and keeps no state between
+ *    calls. Device arrays must be 16-byte aligned and must not alias unless stated.
+ *  - stream is a hipStream_t passed as void* (NULL = default stream). Every call enqueues
+ *    its work on that stream and returns after that work has completed.
+ *  - Return codes: 0 success, S3TTV_NOT_CONVERGED (solve ran max_iter iterations without
+ *    meeting rel_tol; outputs are valid), negative values are errors (outputs unspecified).
+ */
+#ifndef S3TTV_H
+#define S3TTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  S3TTV_OK = 0,
+  S3TTV_NOT_CONVERGED = 1,
+  S3TTV_EINVAL = -1,       /* bad shape, radius, box, step size, null pointer */
+  S3TTV_EUNSUPPORTED = -2, /* valid for the method but outside this build (e.g. K > 16) */
+  S3TTV_EWORKSPACE = -3,   /* workspace smaller than the queried size */
+  S3TTV_EHIP = -4,         /* HIP runtime error */
+  S3TTV_ENONFINITE = -5    /* NaN/Inf met in the input or in the iterates */
+};
+
+/* Image and block geometry. n1, n2, n3 >= 2; 1 <= k1 <= n1; 1 <= k2 <= n2; k1*k2 <= 16. */
+typedef struct {
+  int32_t n1, n2, n3, k1, k2;
+} s3ttv_shape;
+
+/* Problem and iteration parameters.
+ *  eps, alpha, beta: radii of the v-centred l2 ball (eq. constraint_fidel) and of the
+ *    zero-centred l1 balls of s and t (eqs. constraint_sparse, constraint_stripe); > 0.
+ *  mu_min < mu_max: box of u (eq. constraint_box); [0, 1] for normalised images.
+ *  gamma_*: diagonal step sizes of Alg. 1 (eq. stepsize_denoising). If all six are 0 the
+ *    Lemma-2 values of the stacked operator are used: gamma_u = 1/(8*k1*k2 + 1),
+ *    gamma_s = 1, gamma_t = 1/3, gamma_Y = 1/4, gamma_y2 = 1/2, gamma_y3 = 1/3.
+ *  max_iter >= 1 iterations at most.
+ *  rel_tol: 0 runs exactly max_iter iterations; > 0 stops after the first iteration
+ *    k >= 2 with ||u^(k) - u^(k-1)|| / ||u^(k-1)|| < rel_tol (eq. StopCri_simulated).
+ *  check_every: iterations between host checks of the stop flag (<= 0 means 16). The
+ *    iterate returned is always the one at which the rule fired.
+ *  timing_mask: bit c set => time every launch of kernel class c with HIP events and
+ *    report the totals in s3ttv_stats (classes: see S3TTV_K_*). 0 for no timing. */
+typedef struct {
+  double eps, alpha, beta;
+  double mu_min, mu_max;
+  double gamma_u, gamma_s, gamma_t, gamma_Y, gamma_y2, gamma_y3;
+  int32_t max_iter;
+  double rel_tol;
+  int32_t check_every;
+  int32_t timing_mask;
+} s3ttv_params;
+
+/* Kernel classes for timing_mask / s3ttv_stats.kernel_ms. */
+enum {
+  S3TTV_K_PRIMAL = 0, /* u, s, t primal step + first l1 histogram (Alg. 1 steps 2-4) */
+  S3TTV_K_L1 = 1,     /* l1 threshold refinement passes and selections */
+  S3TTV_K_GRAD = 2,   /* D_v D_s u', D_h D_s u' (steps 5, 9) */
+  S3TTV_K_GRAM = 3,   /* Y' = Y + gamma_Y P_l D D_s u', Gram Y' Y'^T on MFMA (step 9) */
+  S3TTV_K_EIG = 4,    /* Jacobi eigen-solve, spectral clip matrix (step 10) */
+  S3TTV_K_APPLY = 5,  /* Y+ = W Y' on MFMA, overlap-add partials (steps 10, 2) */
+  S3TTV_K_ZSUM = 6,   /* sum of overlap-add partials (P_l^T of step 2) */
+  S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) */
+  S3TTV_K_FINAL = 8,  /* scalar reductions, stop rule */
+  S3TTV_K_COUNT = 9
+};
+
+typedef struct {
+  int32_t iters;        /* iterations run */
+  int32_t converged;    /* 1 if rel_tol fired */
+  double rel_change;    /* ||u^(k) - u^(k-1)|| / ||u^(k-1)|| of the last iteration */
+  double l1_s, l1_t;    /* ||s||_1, ||t||_1 of the result */
+  double fid;           /* ||u + s + t - v||_2 of the result */
+  double dv_t;          /* ||D_v t||_2 of the result */
+  int32_t eig_max_sweeps; /* largest Jacobi sweep count used by any block */
+  float ms;             /* wall time of the iteration loop (HIP events) */
+  float kernel_ms[S3TTV_K_COUNT];     /* summed durations of timed classes */
+  int32_t kernel_calls[S3TTV_K_COUNT];
+} s3ttv_stats;
+
+/* Bytes of device workspace s3ttv_solve needs for this shape (host out-pointer bytes). */
+int32_t s3ttv_workspace_bytes(const s3ttv_shape *shape, const s3ttv_params *params,
+                              size_t *bytes);
+
+/* Solve Prob. (18) by Alg. 1 starting from u0 (device, nullable: zero start), all other
+ * variables zero. v (device, input, not modified), u, s, t (device, outputs, N1*N2*N3
+ * floats each), workspace (device, >= s3ttv_workspace_bytes), stats (host, nullable). */
+int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                    const float *u0, float *u, float *s, float *t, void *workspace,
+                    size_t workspace_bytes, void *stream, s3ttv_stats *stats);
+
+/* Static description of a return code. */
+const char *s3ttv_strerror(int32_t code);
+
+/* ---------------- Operator-level entry points (same kernels as the solver) ---------------- */
+
+enum {
+  S3TTV_OP_GRAD = 0,
+  S3TTV_OP_GRAD_ADJ = 1,
+  S3TTV_OP_CLIP = 2,
+  S3TTV_OP_DUAL_BLOCKS = 3,
+  S3TTV_OP_L1 = 4
+};
+
+/* Workspace bytes for an operator entry point. shape is used by GRAD, GRAD_ADJ and
+ * DUAL_BLOCKS; n is the vector length for L1 and the block count for CLIP (with the block
+ * geometry passed as k1 = K rows and n3 = ncols in shape for CLIP). */
+int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n, size_t *bytes);
+
+/* Second-order spatio-spectral differences of Sec. II-A: gv = D_v D_s u, gh = D_h D_s u.
+ * u, gv, gh device cubes. */
+int32_t s3ttv_op_grad(const s3ttv_shape *shape, const float *u, float *gv, float *gh,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* Adjoint: w = D_s^T (D_v^T zv + D_h^T zh). zv, zh, w device cubes. */
+int32_t s3ttv_op_grad_adj(const s3ttv_shape *shape, const float *zv, const float *zh, float *w,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* Projection of each of nblk matrices (K x ncols, row-major, K <= 16) onto the unit
+ * spectral-norm ball, U diag(min(sigma, 1)) V^T — the value of Alg. 1 step 10 for any
+ * gamma_Y by eq. ProxConjugate. yin, yout device arrays of nblk*K*ncols floats. */
+int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const float *yin,
+                               float *yout, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Alg. 1 steps 9-10 for every block plus the overlap-add of step 2:
+ *   Y+_l = Y_l + g P_l D D_s up - g prox_{(1/g) nuclear}((Y_l + g P_l D D_s up)/g),
+ *   zv, zh = sum_l P_l^T Y+_l.
+ * up (device cube), yin / yout (device, L x K x 2*N3, block column 2b = D_v part, 2b+1 = D_h
+ * part, as eq. SSST), zv, zh device cubes. */
+int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const float *up,
+                             const float *yin, float *yout, float *zv, float *zh,
+                             void *workspace, size_t workspace_bytes, void *stream);
+
+/* Projection of x (device, n floats) onto {||w||_1 <= radius}; out (device, n floats);
+ * tau (host, nullable) receives the soft threshold (0 when x is inside the ball). */
+int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out, double *tau,
+                            void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* S3TTV_H */

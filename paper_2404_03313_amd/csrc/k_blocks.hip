@@ -1,0 +1,371 @@
+// Block kernels of Alg. 1 steps 9-10 (arXiv 2404.03313, Sec. III-A and III-C) for gfx950.
+//
+// For every block l (one torus window per pixel anchor) the dual step is
+//   Y'_l = Y_l + g_Y T_l,       T_l = P_l D D_s u'                 (step 9, eq. rewrite_Lu)
+//   Y+_l = Y'_l - g_Y prox_{||.||_*/g_Y}(Y'_l / g_Y)               (step 10)
+// which by eq. ProxConjugate and eq. prox_nuclear_norm equals U diag(min(sigma, 1)) V^T,
+// the projection of Y'_l onto the unit spectral-norm ball. With K <= 2B rows this is
+//   Y+_l = W_l Y'_l,   W_l = I - sum_{lambda_k > 1} (1 - lambda_k^{-1/2}) v_k v_k^T,
+// where (lambda_k, v_k) are the eigenpairs of the K x K Gram matrix G_l = Y'_l Y'_l^T.
+// Three kernels: Gram on MFMA (k_gram), a per-lane Jacobi eigen-solve (k_eig), and W_l Y'_l on MFMA with a deterministic overlap-add of the result (k_apply).
+//
+// Block storage ("apply layout", 16 rows x ncol columns per block, ncol = 2*Bp, column
+// c = comp*Bp + band): column tile t holds columns 16t..16t+15 as 64 lanes x 4 floats,
+// lane L = 16*g + tc, slot s <-> element (row 4g+s, column 16t+tc). This is the B-operand /
+// result layout of v_mfma_f32_16x16x4_f32, so k_apply streams it with 16-byte accesses.
+#include "s3ttv_internal.h"
+
+namespace s3ttv {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Pixel offset (into the [pixel][ncol] field) of block row `row` of anchor l, or -1.
+__device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
+  if (row >= a.K) return -1;
+  const int p = (int)(l / a.n2), q = (int)(l - (long long)(l / a.n2) * a.n2);
+  const int ar = row / a.k2, cr = row - (row / a.k2) * a.k2;
+  int i = p + ar;
+  if (i >= a.n1) i -= a.n1;
+  int j = q + cr;
+  if (j >= a.n2) j -= a.n2;
+  return i * a.n2 + j;
+}
+
+// ---------------------------------------------------------------- Gram on MFMA
+
+// One wavefront per block. In MFMA step (t, s) lane (r = lane&15, kk = lane>>4) supplies
+// Y'[r][16t + 4kk + s] as both operands, so the 16x16x4 products accumulate
+// G = sum_c Y'[:, c] Y'[:, c]^T. Result lane (j, g) register v = G[4g+v][j].
+__global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
+  if (a.sc && a.sc->done) return;
+  const int lane = threadIdx.x & 63;
+  const long long l = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (l >= a.nblk) return;
+  const int r = lane & 15, kk = lane >> 4;
+  const int pix = a.gradf ? row_pixel(a, l, r) : -1;
+  const float *Yl = a.Y + (size_t)l * kRows * a.ncol;
+  const float *Tp = pix >= 0 ? a.gradf + (size_t)pix * a.ncol + 4 * kk : nullptr;
+  const int yoff = (16 * (r >> 2) + 4 * kk) * 4 + (r & 3);
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < a.ntile; ++t) {
+    const float *Yt = Yl + t * 256 + yoff;
+    f4 T = {0.f, 0.f, 0.f, 0.f};
+    if (Tp) T = *(const f4 *)(Tp + 16 * t);
+    const float y0 = fmaf(a.gY, T[0], Yt[0]);
+    const float y1 = fmaf(a.gY, T[1], Yt[4]);
+    const float y2 = fmaf(a.gY, T[2], Yt[8]);
+    const float y3 = fmaf(a.gY, T[3], Yt[12]);
+    acc = mfma4(y0, y0, acc);
+    acc = mfma4(y1, y1, acc);
+    acc = mfma4(y2, y2, acc);
+    acc = mfma4(y3, y3, acc);
+  }
+  float *Gl = a.G + (size_t)l * 256 + (4 * (lane >> 4)) * 16 + (lane & 15);
+  Gl[0] = acc[0];
+  Gl[16] = acc[1];
+  Gl[32] = acc[2];
+  Gl[48] = acc[3];
+}
+
+// ---------------------------------------------------------------- Jacobi eigen-solve
+
+// One lane per block: the lane holds the upper triangle of its symmetric Gram matrix (136
+// floats) and the eigenvector matrix V (256 floats) in registers, and runs cyclic Jacobi
+// sweeps (row order p < q). All register indices are compile-time constants (the sweep is
+// fully unrolled). A rotation whose pivot |G_pq| is at most thr = kJacobiTol * ||G||_F in
+// every lane of the wavefront is skipped; the solve stops when no pivot exceeds thr.
+// Output: W = I - sum_k (1 - min(1, lambda_k^{-1/2})) v_k v_k^T, row-major.
+
+constexpr int kMaxSweeps = 16;
+constexpr float kJacobiTol = 1e-7f;
+
+__host__ __device__ constexpr int tri(int p, int q) { return p * 16 - p * (p - 1) / 2 + (q - p); }
+
+template <int P, int Q>
+__device__ __forceinline__ void jrot(float (&A)[136], float (&V)[256], float thr) {
+  const float apq = A[tri(P, Q)];
+  if (!__any(fabsf(apq) > thr)) return;
+  const float app = A[tri(P, P)], aqq = A[tri(Q, Q)];
+  float t = 0.f;
+  if (fabsf(apq) > thr) {
+    const float zeta = __fdividef(aqq - app, 2.f * apq);
+    t = copysignf(__frcp_rn(fabsf(zeta) + sqrtf(fmaf(zeta, zeta, 1.f))), zeta);
+  }
+  const float c = rsqrtf(fmaf(t, t, 1.f)), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k == P || k == Q) continue;
+    const int ip = k < P ? tri(k, P) : tri(P, k);
+    const int iq = k < Q ? tri(k, Q) : tri(Q, k);
+    const float g = A[ip], h = A[iq];
+    A[ip] = fmaf(c, g, -s * h);
+    A[iq] = fmaf(s, g, c * h);
+  }
+  A[tri(P, P)] = fmaf(-t, apq, app);
+  A[tri(Q, Q)] = fmaf(t, apq, aqq);
+  A[tri(P, Q)] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float g = V[k * 16 + P], h = V[k * 16 + Q];
+    V[k * 16 + P] = fmaf(c, g, -s * h);
+    V[k * 16 + Q] = fmaf(s, g, c * h);
+  }
+}
+
+template <int P, int Q>
+__device__ __forceinline__ void jsweep(float (&A)[136], float (&V)[256], float thr) {
+  if constexpr (P < 15) {
+    jrot<P, Q>(A, V, thr);
+    if constexpr (Q < 15)
+      jsweep<P, Q + 1>(A, V, thr);
+    else
+      jsweep<P + 1, P + 2>(A, V, thr);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
+  if (a.sc && a.sc->done) return;
+  long long blk = (long long)blockIdx.x * 64 + threadIdx.x;
+  const bool valid = blk < a.nblk;
+  if (!valid) blk = a.nblk - 1;  // duplicate a real block so every lane runs the same sweeps
+  const f4 *g4 = (const f4 *)(a.G + (size_t)blk * 256);
+  float Gf[256];
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    const f4 v = g4[k];
+    Gf[4 * k] = v[0];
+    Gf[4 * k + 1] = v[1];
+    Gf[4 * k + 2] = v[2];
+    Gf[4 * k + 3] = v[3];
+  }
+  float A[136], V[256];
+  float fro = 0.f;
+#pragma unroll
+  for (int p = 0; p < 16; ++p)
+#pragma unroll
+    for (int q = p; q < 16; ++q) {
+      const float x = 0.5f * (Gf[p * 16 + q] + Gf[q * 16 + p]);
+      A[tri(p, q)] = x;
+      fro = fmaf(p == q ? x : 2.f * x, x, fro);
+    }
+#pragma unroll
+  for (int k = 0; k < 256; ++k) V[k] = (k / 16 == k % 16) ? 1.f : 0.f;
+  const float thr = kJacobiTol * sqrtf(fro);
+  int sweeps = 0;
+  for (; sweeps < kMaxSweeps; ++sweeps) {
+    float off = 0.f;
+#pragma unroll
+    for (int p = 0; p < 16; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 16; ++q) off = fmaxf(off, fabsf(A[tri(p, q)]));
+    if (!__any(off > thr)) break;
+    jsweep<0, 1>(A, V, thr);
+  }
+  float h[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const float lam = A[tri(k, k)];
+    h[k] = lam > 1.f ? 1.f - rsqrtf(lam) : 0.f;
+  }
+  float Wt[136];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    float hv[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) hv[k] = h[k] * V[p * 16 + k];
+#pragma unroll
+    for (int q = p; q < 16; ++q) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc = fmaf(hv[k], V[q * 16 + k], acc);
+      Wt[tri(p, q)] = (p == q ? 1.f : 0.f) - acc;
+    }
+  }
+  if (valid) {
+    f4 *w4 = (f4 *)(a.W + (size_t)blk * 256);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      f4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = (4 * k + e) / 16, c = (4 * k + e) % 16;
+        v[e] = r <= c ? Wt[tri(r, c)] : Wt[tri(c, r)];
+      }
+      w4[k] = v;
+    }
+    if (a.sc) atomicMax(&a.sc->max_sweeps, sweeps);
+  }
+}
+
+// ---------------------------------------------------------------- apply on MFMA + overlap-add
+
+// Workgroup = one TA x TB tile of anchors, `waves` wavefronts; wavefront w owns column tiles
+// t = w, w + waves, ... of every block of the tile, so the overlap-add accumulators in LDS
+// (extA x extB pixels x ncol columns) are private per column and summed in a fixed order.
+// MFMA step s: A = W[r][4g+s] (lane r + 16g), B = Y'[4g+s][tc] (lane tc + 16g);
+// result lane (tc, g) register v = (W Y')[4g+v][tc] is written back in place.
+__global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
+  extern __shared__ float zacc[];
+  if (a.sc && a.sc->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tc = lane & 15, g = lane >> 4;
+  const int ta = blockIdx.x / a.ntB, tb = blockIdx.x - (blockIdx.x / a.ntB) * a.ntB;
+  const int p0 = ta * a.TA, q0 = tb * a.TB;
+  const int np = min(a.TA, a.n1 - p0), nq = min(a.TB, a.n2 - q0);
+  const bool doz = a.zpart != nullptr;
+  const int next = a.extA * a.extB;
+  if (doz) {
+    for (int t = wave; t < a.ntile; t += a.waves)
+      for (int e = g; e < next; e += 4) zacc[(size_t)e * a.ncol + 16 * t + tc] = 0.f;
+  }
+  for (int da = 0; da < np; ++da)
+    for (int db = 0; db < nq; ++db) {
+      const long long l = (long long)(p0 + da) * a.n2 + (q0 + db);
+      const f4 wv = *(const f4 *)(a.W + (size_t)l * 256 + tc * 16 + 4 * g);
+      int pix[4], zo[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = 4 * g + s;
+        pix[s] = a.gradf ? row_pixel(a, l, row) : -1;
+        if (row < a.K) {
+          const int ar = row / a.k2, cr = row - (row / a.k2) * a.k2;
+          zo[s] = ((da + ar) * a.extB + (db + cr)) * a.ncol;
+        } else {
+          zo[s] = -1;
+        }
+      }
+      float *Yl = a.Y + (size_t)l * kRows * a.ncol + lane * 4;
+      for (int t = wave; t < a.ntile; t += a.waves) {
+        f4 *Yt = (f4 *)(Yl + t * 256);
+        const f4 y = *Yt;
+        float yp[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float T = pix[s] >= 0 ? a.gradf[(size_t)pix[s] * a.ncol + 16 * t + tc] : 0.f;
+          yp[s] = fmaf(a.gY, T, y[s]);
+        }
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma4(wv[0], yp[0], acc);
+        acc = mfma4(wv[1], yp[1], acc);
+        acc = mfma4(wv[2], yp[2], acc);
+        acc = mfma4(wv[3], yp[3], acc);
+        *Yt = acc;
+        if (doz) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (zo[v] >= 0) zacc[zo[v] + 16 * t + tc] += acc[v];
+        }
+      }
+    }
+  if (doz) {
+    float *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
+    for (int t = wave; t < a.ntile; t += a.waves)
+      for (int e = g; e < next; e += 4) {
+        const size_t o = (size_t)e * a.ncol + 16 * t + tc;
+        zp[o] = zacc[o];
+      }
+  }
+}
+
+// ---------------------------------------------------------------- layout converters
+
+// src: nblk blocks of K rows x ncols_src (row-major). paper_cols: column 2b+comp <-> internal
+// comp*Bp + b; otherwise column c <-> c. Internal padding (rows >= K, extra columns) is zero.
+__global__ void k_pack_blocks(const float *src, float *Y, long long nblk, int K, int ncols_src,
+                              int ncol, int paper_cols, int Bp) {
+  const long long total = nblk * kRows * ncol;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long l = e / (kRows * ncol);
+    const int rem = (int)(e - l * kRows * ncol);
+    const int t = rem / 256, w = rem - t * 256;
+    const int L = w >> 2, s = w & 3;
+    const int row = 4 * (L >> 4) + s, c = 16 * t + (L & 15);
+    int cs;
+    if (paper_cols) {
+      const int comp = c / Bp, b = c - comp * Bp;
+      cs = 2 * b + comp;
+    } else {
+      cs = c;
+    }
+    float val = 0.f;
+    if (row < K && cs < ncols_src) val = src[(l * K + row) * ncols_src + cs];
+    Y[e] = val;
+  }
+}
+
+__global__ void k_unpack_blocks(const float *Y, float *dst, long long nblk, int K, int ncols_src,
+                                int ncol, int paper_cols, int Bp) {
+  const long long total = nblk * K * ncols_src;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long l = e / ((long long)K * ncols_src);
+    const int rem = (int)(e - l * K * ncols_src);
+    const int row = rem / ncols_src, cs = rem - row * ncols_src;
+    int c;
+    if (paper_cols) {
+      c = (cs & 1) * Bp + (cs >> 1);
+    } else {
+      c = cs;
+    }
+    const int t = c >> 4, tc = c & 15;
+    const int L = 16 * (row >> 2) + tc, s = row & 3;
+    dst[e] = Y[l * kRows * ncol + t * 256 + L * 4 + s];
+  }
+}
+
+inline int grid_for(long long n, int nt, int per) {
+  long long g = (n + (long long)nt * per - 1) / ((long long)nt * per);
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_gram(const BlockArgs &a, hipStream_t st) {
+  const long long g = (a.nblk + 3) / 4;
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)g), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig(const BlockArgs &a, hipStream_t st) {
+  const long long g = (a.nblk + 63) / 64;
+  hipLaunchKernelGGL(k_eig, dim3((unsigned)g), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const BlockArgs &a, hipStream_t st) {
+  const unsigned g = (unsigned)(a.ntA * a.ntB);
+  if (a.zpart && a.lds > 0) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_apply,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_apply, dim3(g), dim3(64 * a.waves), a.zpart ? a.lds : 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_blocks(const float *src, float *Y, long long nblk, int K, int ncols_src,
+                              int ncol, int paper_cols, int n3, int Bp, hipStream_t st) {
+  (void)n3;
+  hipLaunchKernelGGL(k_pack_blocks, dim3(grid_for(nblk * kRows * ncol, 256, 4)), dim3(256), 0, st,
+                     src, Y, nblk, K, ncols_src, ncol, paper_cols, Bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_blocks(const float *Y, float *dst, long long nblk, int K, int ncols_src,
+                                int ncol, int paper_cols, int n3, int Bp, hipStream_t st) {
+  (void)n3;
+  hipLaunchKernelGGL(k_unpack_blocks, dim3(grid_for(nblk * K * ncols_src, 256, 4)), dim3(256), 0,
+                     st, Y, dst, nblk, K, ncols_src, ncol, paper_cols, Bp);
+  return hipGetLastError();
+}
+
+}  // namespace s3ttv

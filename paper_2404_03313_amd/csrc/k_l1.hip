@@ -1,0 +1,234 @@
+// Exact projection onto the zero-centred l1 ball {||w||_1 <= r} (Alg. 1 steps 3-4,
+// eqs. constraint_sparse / constraint_stripe) for gfx950.
+//
+// The projection is w = sign(x) max(|x| - tau, 0) where tau solves
+//   phi(tau) = sum_i max(|x_i| - tau, 0) = r           (phi decreasing, piecewise linear).
+// The paper cites a sort-based fast algorithm; here tau is found without sorting by a
+// three-level multisection over the IEEE-754 bit pattern of |x| (a non-negative float orders
+// like its bit pattern): level 1 bins bits 30..20, level 2 bits 19..9 inside the chosen
+// level-1 bin, level 3 bits 8..0, where every bin is a single float value. At each level
+// phi is evaluated at every bin edge at once from per-bin counts and sums, and the last
+// edge with phi >= r selects the bin that brackets tau. All values of one level-1 bin share
+// the exponent, so per-bin sums of the 24-bit significands are exact in 64-bit integers;
+// edge sums are formed in FP64 in a fixed order. After level 3 the active set is known
+// exactly and tau = (sum of |x| above the bin - r) / (their count).
+#include "s3ttv_internal.h"
+
+namespace s3ttv {
+
+namespace {
+
+constexpr int kNT = 256;
+
+__device__ inline int level_shift(int level) {
+  return level == 1 ? kL1Shift1 : (level == 2 ? kL1Shift2 : kL1Shift3);
+}
+__device__ inline int level_bins(int level) {
+  return level == 1 ? kL1Bins1 : (level == 2 ? kL1Bins2 : kL1Bins3);
+}
+// Bits above this level (the parent prefix), as a shift: level 2 -> 20, level 3 -> 9.
+__device__ inline int parent_shift(int level) { return level == 2 ? kL1Shift1 : kL1Shift2; }
+
+__global__ __launch_bounds__(kNT) void k_l1_hist(const float *x0, const float *x1, long long n,
+                                                 int nballs, int level, L1Hist *hist,
+                                                 DevScalars *sc) {
+  __shared__ unsigned long long h[2][kL1MaxBins];
+  if (sc->done) return;
+  const int shift = level_shift(level), nb = level_bins(level);
+  int use[2] = {1, nballs > 1};
+  uint32_t pref[2] = {0u, 0u};
+  const int ps = level > 1 ? parent_shift(level) : 31;
+  for (int k = 0; k < 2; ++k) {
+    if (level > 1) use[k] = use[k] && sc->active[k];
+    pref[k] = sc->prefix[k] >> ps;
+  }
+  if (!use[0] && !use[1]) return;
+  for (int k = threadIdx.x; k < 2 * kL1MaxBins; k += kNT) (&h[0][0])[k] = 0ull;
+  __syncthreads();
+  const uint32_t mask = (uint32_t)nb - 1u;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kNT) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!use[k]) continue;
+      const float x = (k == 0 ? x0 : x1)[e];
+      const uint32_t bits = __float_as_uint(x) & 0x7fffffffu;
+      if (level > 1 && (bits >> ps) != pref[k]) continue;
+      const uint32_t ex = bits >> 23;
+      const uint32_t sig = ex ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
+      atomicAdd(&h[k][(bits >> shift) & mask], (1ull << 40) | (unsigned long long)sig);
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < 2; ++k) {
+    if (!use[k]) continue;
+    uint32_t *gc = hist->cnt[k][level - 1];
+    unsigned long long *gs = hist->sig[k][level - 1];
+    for (int bi = threadIdx.x; bi < nb; bi += kNT) {
+      const unsigned long long v = h[k][bi];
+      if (v) {
+        atomicAdd(&gc[bi], (uint32_t)(v >> 40));
+        atomicAdd(&gs[bi], v & ((1ull << 40) - 1));
+      }
+    }
+  }
+}
+
+// One workgroup per ball. Scans the level's bins from the top, finds the bracketing bin and
+// updates the carry; after level 3 writes tau. Clears the consumed histogram.
+__global__ __launch_bounds__(kNT) void k_l1_select(int level, double r0, double r1, L1Hist *hist,
+                                                   DevScalars *sc) {
+  __shared__ double sS[kNT];
+  __shared__ double sC[kNT];
+  __shared__ int best;
+  const int ball = blockIdx.x;
+  const double radius = ball == 0 ? r0 : r1;
+  uint32_t *gc = hist->cnt[ball][level - 1];
+  unsigned long long *gs = hist->sig[ball][level - 1];
+  const int nb = level_bins(level), shift = level_shift(level);
+  const int per = nb / kNT;  // 8 or 2 bins per thread
+  const bool skip = sc->done || (level > 1 && !sc->active[ball]);
+  if (skip) {
+    for (int k = threadIdx.x; k < nb; k += kNT) {
+      gc[k] = 0u;
+      gs[k] = 0ull;
+    }
+    return;
+  }
+  const uint32_t parent = level == 1 ? 0u : (sc->prefix[ball] >> parent_shift(level)) << parent_shift(level);
+  // thread t owns bins [nb - per*(t+1), nb - per*t), i.e. thread 0 the highest bins
+  const int hi = nb - per * threadIdx.x;
+  double val[8];
+  double cnt[8];
+  double lo_edge[8];
+  double S = 0, C = 0;
+  for (int m = 0; m < per; ++m) {
+    const int k = hi - 1 - m;  // descending
+    const uint32_t bits = parent | ((uint32_t)k << shift);
+    const int ex = (int)(bits >> 23);
+    const double scale = ldexp(1.0, (ex > 0 ? ex : 1) - 150);
+    val[m] = (double)gs[k] * scale;
+    cnt[m] = (double)gc[k];
+    lo_edge[m] = (double)__uint_as_float(bits);
+    S += val[m];
+    C += cnt[m];
+  }
+  // exclusive prefix over threads (fixed Hillis-Steele order)
+  sS[threadIdx.x] = S;
+  sC[threadIdx.x] = C;
+  __syncthreads();
+  for (int off = 1; off < kNT; off <<= 1) {
+    double s2 = 0, c2 = 0;
+    if (threadIdx.x >= off) {
+      s2 = sS[threadIdx.x - off];
+      c2 = sC[threadIdx.x - off];
+    }
+    __syncthreads();
+    sS[threadIdx.x] += s2;
+    sC[threadIdx.x] += c2;
+    __syncthreads();
+  }
+  const double S_carry = level == 1 ? 0.0 : sc->S_above[ball];
+  const double C_carry = level == 1 ? 0.0 : (double)sc->C_above[ball];
+  double Sx = S_carry + (threadIdx.x ? sS[threadIdx.x - 1] : 0.0);
+  double Cx = C_carry + (threadIdx.x ? sC[threadIdx.x - 1] : 0.0);
+  const double total = S_carry + sS[kNT - 1];
+  if (threadIdx.x == 0) best = -1;
+  __syncthreads();
+  if (level == 1 && total <= radius) {
+    // already inside the ball: the projection is the identity
+    if (threadIdx.x == 0) {
+      sc->active[ball] = 0;
+      sc->tau[ball] = 0.0;
+    }
+  } else {
+    int mine = -1;
+    double Sa = 0, Ca = 0;  // sums strictly above the candidate bin
+    for (int m = 0; m < per; ++m) {
+      const double Sb = Sx, Cb = Cx;
+      Sx += val[m];
+      Cx += cnt[m];
+      if (Sx - Cx * lo_edge[m] >= radius) {
+        mine = hi - 1 - m;
+        Sa = Sb;
+        Ca = Cb;
+        break;
+      }
+    }
+    if (mine >= 0) atomicMax(&best, mine);
+    __syncthreads();
+    int kstar = best;
+    const bool owner = (kstar >= 0) ? (mine == kstar) : (threadIdx.x == kNT - 1);
+    if (kstar < 0 && owner) {
+      // rounding left no edge with phi >= r: take the lowest bin, carry = everything above it
+      kstar = 0;
+      Sa = Sx - val[per - 1];
+      Ca = Cx - cnt[per - 1];
+    }
+    if (owner) {
+      const uint32_t bits = parent | ((uint32_t)kstar << shift);
+      if (level == 1) sc->active[ball] = 1;
+      if (level < 3) {
+        sc->prefix[ball] = bits;
+        sc->S_above[ball] = Sa;
+        sc->C_above[ball] = (unsigned long long)Ca;
+      } else {
+        const double vstar = (double)__uint_as_float(bits);
+        sc->tau[ball] = Ca > 0 ? (Sa - radius) / Ca : vstar;
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nb; k += kNT) {
+    gc[k] = 0u;
+    gs[k] = 0ull;
+  }
+}
+
+__global__ void k_l1_apply(const float *x, float *out, long long n, int ball, DevScalars *sc) {
+  const int act = sc->active[ball];
+  const double tau = sc->tau[ball];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float v = x[e];
+    if (!act) {
+      out[e] = v;
+    } else {
+      const double a = fabs((double)v) - tau;
+      out[e] = a > 0 ? copysignf((float)a, v) : 0.0f;
+    }
+  }
+}
+
+}  // namespace
+
+int l1_grid(long long n) {
+  long long g = (n + 8191) / 8192;
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  return (int)g;
+}
+
+hipError_t launch_l1_hist(const float *x0, const float *x1, long long n, int nballs, int level,
+                          L1Hist *hist, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_l1_hist, dim3(l1_grid(n)), dim3(kNT), 0, st, x0, x1 ? x1 : x0, n, nballs,
+                     level, hist, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_select(int nballs, int level, double r0, double r1, L1Hist *hist,
+                            DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_l1_select, dim3(nballs), dim3(kNT), 0, st, level, r0, r1, hist, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_apply(const float *x, float *out, long long n, int ball, DevScalars *sc,
+                           hipStream_t st) {
+  long long g = (n + 2047) / 2048;
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_l1_apply, dim3((int)g), dim3(kNT), 0, st, x, out, n, ball, sc);
+  return hipGetLastError();
+}
+
+}  // namespace s3ttv

@@ -1,0 +1,547 @@
+// Voxel-wise and stencil kernels of Alg. 1 (arXiv 2404.03313) for gfx950.
+//
+// Layouts: cubes are (N1, N2, N3) band fastest; the two-component gradient / overlap-add
+// fields are [pixel][ncol] with column c = comp*Bp + band (comp 0 = D_v D_s, 1 = D_h D_s),
+// padded bands zero. All global sums are accumulated in FP64 per workgroup and reduced in a
+// fixed order by one workgroup, so every run is bitwise reproducible.
+#include "s3ttv_internal.h"
+
+namespace s3ttv {
+
+namespace {
+
+constexpr int kNT = 256;  // threads per workgroup of the voxel kernels
+
+__device__ inline int wrap_up(int a, int n) { return a >= n ? a - n : a; }
+__device__ inline int wrap_dn(int a, int n) { return a < 0 ? a + n : a; }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over a 256-thread workgroup in a fixed order; result valid in thread 0.
+__device__ inline double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return r;
+}
+
+__device__ inline float box(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// Soft threshold with an FP64 threshold; the difference is formed in double and rounded once.
+__device__ inline float soft(float x, double tau) {
+  const double a = fabs((double)x) - tau;
+  return a > 0 ? copysignf((float)a, x) : 0.0f;
+}
+
+// Histogram key of |x| for the level-1 l1 selection: bin = bits 30..20, significand of the
+// value (implicit bit included for normal numbers).
+__device__ inline void l1_acc(unsigned long long *h, float x) {
+  const uint32_t bits = __float_as_uint(x) & 0x7fffffffu;
+  const uint32_t e = bits >> 23;
+  const uint32_t sig = e ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
+  atomicAdd(&h[bits >> kL1Shift1], (1ull << 40) | (unsigned long long)sig);
+}
+
+__device__ inline void l1_flush(const unsigned long long *h, int nb, uint32_t *gcnt,
+                                unsigned long long *gsig) {
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+    const unsigned long long v = h[k];
+    if (v) {
+      atomicAdd(&gcnt[k], (uint32_t)(v >> 40));
+      atomicAdd(&gsig[k], v & ((1ull << 40) - 1));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- primal step
+
+struct PrimalArgs {
+  int n1, n2, n3, Bp, ncol;
+  long long N;
+  float g_u, g_s, g_t, lo, hi;
+  const float *u, *s, *t, *y2, *w, *Z;
+  float *un, *xs, *xt;
+  double *red;
+  DevScalars *sc;
+  L1Hist *hist;
+};
+
+// Alg. 1 steps 2-4 before the l1 projections:
+//   u+ = P_box(u - g_u (D_s^T (D_v^T Zv + D_h^T Zh) + y3))        (eq. prox_box_constraint)
+//   xs = s - g_s y3,   xt = t - g_t (D_v^T y2 + y3),   y3 = kappa * w.
+__global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
+  __shared__ unsigned long long h[2][kL1Bins1];
+  __shared__ double sh[4];
+  if (a.sc->done) return;
+  for (int k = threadIdx.x; k < 2 * kL1Bins1; k += kNT) (&h[0][0])[k] = 0ull;
+  __syncthreads();
+  const float kappa = (float)a.sc->kappa;
+  double du2 = 0, u2 = 0, bad = 0;
+  const int n2 = a.n2, n3 = a.n3, ncol = a.ncol, Bp = a.Bp;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < a.N;
+       e += (long long)gridDim.x * kNT) {
+    const uint32_t pix = (uint32_t)(e / n3);
+    const int b = (int)(e - (long long)pix * n3);
+    const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
+    const int bm = wrap_dn(b - 1, n3);
+    const uint32_t pim = (uint32_t)(wrap_dn(i - 1, a.n1) * n2 + j);
+    const uint32_t pjm = (uint32_t)(i * n2 + wrap_dn(j - 1, n2));
+    const float *Zp = a.Z + (size_t)pix * ncol;
+    const float *Zi = a.Z + (size_t)pim * ncol;
+    const float *Zj = a.Z + (size_t)pjm * ncol;
+    // q(b) = (D_v^T Zv + D_h^T Zh)(b); adjoint of D_s: q(b-1) - q(b)
+    const float q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
+    const float q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+    const float adj = q1 - q0;
+    const float y3 = kappa * a.w[e];
+    const float uo = a.u[e];
+    const float un = box(uo - a.g_u * (adj + y3), a.lo, a.hi);
+    const float xs = a.s[e] - a.g_s * y3;
+    const size_t em = (size_t)pim * n3 + b;
+    const float xt = a.t[e] - a.g_t * ((a.y2[em] - a.y2[e]) + y3);
+    a.un[e] = un;
+    a.xs[e] = xs;
+    a.xt[e] = xt;
+    const double d = (double)un - (double)uo;
+    du2 += d * d;
+    u2 += (double)uo * (double)uo;
+    if (!(isfinite(un) && isfinite(xs) && isfinite(xt))) bad = 1;
+    l1_acc(h[0], xs);
+    l1_acc(h[1], xt);
+  }
+  du2 = block_sum(du2, sh);
+  u2 = block_sum(u2, sh);
+  bad = block_sum(bad, sh);
+  if (threadIdx.x == 0) {
+    a.red[blockIdx.x * 4 + 0] = du2;
+    a.red[blockIdx.x * 4 + 1] = u2;
+    a.red[blockIdx.x * 4 + 2] = bad;
+  }
+  __syncthreads();
+  l1_flush(h[0], kL1Bins1, a.hist->cnt[0][0], a.hist->sig[0][0]);
+  l1_flush(h[1], kL1Bins1, a.hist->cnt[1][0], a.hist->sig[1][0]);
+}
+
+// ---------------------------------------------------------------- gradient field
+
+struct GradArgs {
+  int n1, n2, n3, Bp, ncol;
+  long long P;
+  const float *a, *b;
+  float ca, cb;
+  float *g;
+  DevScalars *sc;
+};
+
+// u' = ca*a + cb*b;  g[pix][b] = (D_v D_s u')(pix, b),  g[pix][Bp + b] = (D_h D_s u')(pix, b).
+__global__ __launch_bounds__(kNT) void k_grad(GradArgs a) {
+  if (a.sc && a.sc->done) return;
+  const int Bp = a.Bp, n3 = a.n3, n2 = a.n2;
+  const long long total = a.P * Bp;
+  for (long long idx = (long long)blockIdx.x * kNT + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * kNT) {
+    const uint32_t pix = (uint32_t)(idx / Bp);
+    const int b = (int)(idx - (long long)pix * Bp);
+    float gv = 0.f, gh = 0.f;
+    if (b < n3) {
+      const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
+      const int b1 = wrap_up(b + 1, n3);
+      const size_t o00 = (size_t)pix * n3;
+      const size_t o10 = ((size_t)wrap_up(i + 1, a.n1) * n2 + j) * n3;
+      const size_t o01 = ((size_t)i * n2 + wrap_up(j + 1, n2)) * n3;
+#define UP(o, bb) (a.ca * a.a[(o) + (bb)] + a.cb * a.b[(o) + (bb)])
+      const float d00 = UP(o00, b1) - UP(o00, b);
+      const float d10 = UP(o10, b1) - UP(o10, b);
+      const float d01 = UP(o01, b1) - UP(o01, b);
+#undef UP
+      gv = d10 - d00;
+      gh = d01 - d00;
+    }
+    a.g[(size_t)pix * a.ncol + b] = gv;
+    a.g[(size_t)pix * a.ncol + Bp + b] = gh;
+  }
+}
+
+// Plain adjoint w = D_s^T (D_v^T Zv + D_h^T Zh) of a [pixel][ncol] field.
+__global__ __launch_bounds__(kNT) void k_grad_adj(int n1, int n2, int n3, int Bp, int ncol,
+                                                  long long N, const float *Z, float *w) {
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < N;
+       e += (long long)gridDim.x * kNT) {
+    const uint32_t pix = (uint32_t)(e / n3);
+    const int b = (int)(e - (long long)pix * n3);
+    const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
+    const int bm = wrap_dn(b - 1, n3);
+    const float *Zp = Z + (size_t)pix * ncol;
+    const float *Zi = Z + ((size_t)wrap_dn(i - 1, n1) * n2 + j) * ncol;
+    const float *Zj = Z + ((size_t)i * n2 + wrap_dn(j - 1, n2)) * ncol;
+    const float q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
+    const float q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+    w[e] = q1 - q0;
+  }
+}
+
+// ---------------------------------------------------------------- overlap-add partial sum
+
+struct ZsumArgs {
+  int n1, n2, ncol, k1, k2, TA, TB, ntA, ntB, extA, extB;
+  const float *zpart;
+  float *Z;
+  DevScalars *sc;
+};
+
+// Slots (tile, ext index) of the partial buffers that hold contributions to pixel row x:
+// tiles of the anchors x - a (a < k), every ext index congruent to x inside those tiles.
+// Writes at most 32 slots to LDS arrays; returns the count.
+__device__ inline int zslots(int x, int n, int k, int TT, int ext, int *tile, int *ext_idx) {
+  int ns = 0;
+  int last_tile = -1, first_tile = -1;
+  for (int off = 0; off < k; ++off) {
+    const int anchor = wrap_dn(x - off, n);
+    const int tt = anchor / TT;
+    // tiles of consecutive anchors form at most two runs (wrap), so comparing with the
+    // previous and first tile visited removes every duplicate
+    if (tt == last_tile || tt == first_tile) continue;
+    if (first_tile < 0) first_tile = tt;
+    last_tile = tt;
+    int e0 = x - tt * TT;
+    if (e0 < 0) e0 += n;
+    for (int e = e0; e < ext && ns < 32; e += n) {
+      tile[ns] = tt;
+      ext_idx[ns] = e;
+      ++ns;
+    }
+  }
+  return ns;
+}
+
+__global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
+  __shared__ int rt[32], re[32], ct[32], ce[32];
+  __shared__ int nsl[2];
+  if (a.sc && a.sc->done) return;
+  const int pix = blockIdx.x;
+  if (threadIdx.x == 0) {
+    const int i = pix / a.n2, j = pix - (pix / a.n2) * a.n2;
+    nsl[0] = zslots(i, a.n1, a.k1, a.TA, a.extA, rt, re);
+    nsl[1] = zslots(j, a.n2, a.k2, a.TB, a.extB, ct, ce);
+  }
+  __syncthreads();
+  const int nr = nsl[0], nc = nsl[1];
+  for (int c = threadIdx.x; c < a.ncol; c += blockDim.x) {
+    float acc = 0.f;
+    for (int r = 0; r < nr; ++r)
+      for (int q = 0; q < nc; ++q) {
+        const size_t slot = (((size_t)rt[r] * a.ntB + ct[q]) * a.extA + re[r]) * a.extB + ce[q];
+        acc += a.zpart[slot * a.ncol + c];
+      }
+    a.Z[(size_t)pix * a.ncol + c] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- dual step
+
+struct DualArgs {
+  int n1, n2, n3;
+  long long N;
+  float g_y2, g_y3;
+  const float *un, *uo, *xs, *xt, *to, *v;
+  float *s, *tn, *y2, *w;
+  double *red;
+  DevScalars *sc;
+};
+
+// Alg. 1 steps 3-7 (apply the l1 thresholds), 12 (y2) and 13 (y3' kept as w = y3' - g_y3 v).
+__global__ __launch_bounds__(kNT) void k_dual(DualArgs a) {
+  __shared__ double sh[4];
+  if (a.sc->done) return;
+  const int act_s = a.sc->active[0], act_t = a.sc->active[1];
+  const double tau_s = a.sc->tau[0], tau_t = a.sc->tau[1];
+  const float kappa = (float)a.sc->kappa;
+  const int n2 = a.n2, n3 = a.n3;
+  double w2 = 0;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < a.N;
+       e += (long long)gridDim.x * kNT) {
+    const uint32_t pix = (uint32_t)(e / n3);
+    const int b = (int)(e - (long long)pix * n3);
+    const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
+    const size_t ep = ((size_t)wrap_up(i + 1, a.n1) * n2 + j) * n3 + b;
+    const float xs = a.xs[e];
+    const float sn = act_s ? soft(xs, tau_s) : xs;
+    const float xt0 = a.xt[e], xt1 = a.xt[ep];
+    const float tn0 = act_t ? soft(xt0, tau_t) : xt0;
+    const float tn1 = act_t ? soft(xt1, tau_t) : xt1;
+    const float tp0 = 2.f * tn0 - a.to[e];
+    const float tp1 = 2.f * tn1 - a.to[ep];
+    const float sp = 2.f * sn - a.s[e];
+    const float up = 2.f * a.un[e] - a.uo[e];
+    a.y2[e] = a.y2[e] + a.g_y2 * (tp1 - tp0);
+    const float wn = kappa * a.w[e] + a.g_y3 * (((up + sp) + tp0) - a.v[e]);
+    a.w[e] = wn;
+    a.s[e] = sn;
+    a.tn[e] = tn0;
+    w2 += (double)wn * (double)wn;
+  }
+  w2 = block_sum(w2, sh);
+  if (threadIdx.x == 0) a.red[blockIdx.x] = w2;
+}
+
+// ---------------------------------------------------------------- scalar finalisation
+
+struct FinalArgs {
+  int nblk;
+  const double *red_primal, *red_dual;
+  double eps_g3;  // eps * gamma_y3
+  DevScalars *sc;
+};
+
+__global__ __launch_bounds__(kNT) void k_finalize(FinalArgs a) {
+  __shared__ double sh[4];
+  if (a.sc->done) return;
+  double du2 = 0, u2 = 0, bad = 0, w2 = 0;
+  for (int k = threadIdx.x; k < a.nblk; k += kNT) {
+    du2 += a.red_primal[k * 4 + 0];
+    u2 += a.red_primal[k * 4 + 1];
+    bad += a.red_primal[k * 4 + 2];
+    w2 += a.red_dual[k];
+  }
+  du2 = block_sum(du2, sh);
+  u2 = block_sum(u2, sh);
+  bad = block_sum(bad, sh);
+  w2 = block_sum(w2, sh);
+  if (threadIdx.x == 0) {
+    DevScalars *sc = a.sc;
+    const double wn = sqrt(w2);
+    sc->kappa = wn > a.eps_g3 ? 1.0 - a.eps_g3 / wn : 0.0;
+    sc->wnorm2 = w2;
+    sc->unorm2 = u2;
+    sc->rel_change = u2 > 0 ? sqrt(du2) / sqrt(u2) : INFINITY;
+    sc->iters += 1;
+    if (bad != 0) {
+      sc->nonfinite = 1;
+      sc->done = 1;
+    }
+    if (sc->rel_tol > 0 && sc->iters >= 2 && u2 > 0 && sc->rel_change < sc->rel_tol) sc->done = 1;
+  }
+}
+
+// ---------------------------------------------------------------- small utilities
+
+__global__ void k_fill(float *p, long long n, float val) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    p[e] = val;
+}
+
+__global__ void k_copy(float *dst, const float *src, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+__global__ void k_zero_words(uint32_t *p, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    p[e] = 0u;
+}
+
+__global__ void k_init_scalars(DevScalars *sc, double rel_tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    DevScalars z = {};
+    z.rel_tol = rel_tol;
+    *sc = z;
+  }
+}
+
+__global__ void k_check_finite(const float *x, long long n, DevScalars *sc) {
+  bool bad = false;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    bad |= !isfinite(x[e]);
+  if (bad) atomicOr(&sc->nonfinite, 1);
+}
+
+__global__ void k_field_to_cubes(const float *f, float *c0, float *c1, long long P, int n3, int Bp) {
+  const long long total = P * n3;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long pix = e / n3;
+    const int b = (int)(e - pix * n3);
+    c0[e] = f[pix * 2 * Bp + b];
+    c1[e] = f[pix * 2 * Bp + Bp + b];
+  }
+}
+
+__global__ void k_cubes_to_field(const float *c0, const float *c1, float *f, long long P, int n3,
+                                 int Bp) {
+  const long long total = P * Bp;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long pix = e / Bp;
+    const int b = (int)(e - pix * Bp);
+    f[pix * 2 * Bp + b] = b < n3 ? c0[pix * n3 + b] : 0.f;
+    f[pix * 2 * Bp + Bp + b] = b < n3 ? c1[pix * n3 + b] : 0.f;
+  }
+}
+
+// Diagnostics: partial sums of |s|, |t|, (u+s+t-v)^2, (D_v t)^2.
+__global__ __launch_bounds__(kNT) void k_diag_partial(int n1, int n2, int n3, long long N,
+                                                      const float *u, const float *s,
+                                                      const float *t, const float *v,
+                                                      double *red) {
+  __shared__ double sh[4];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < N;
+       e += (long long)gridDim.x * kNT) {
+    const long long pix = e / n3;
+    const int b = (int)(e - pix * n3);
+    const int i = (int)(pix / n2), j = (int)(pix - (long long)i * n2);
+    const size_t ep = ((size_t)wrap_up(i + 1, n1) * n2 + j) * n3 + b;
+    a0 += fabs((double)s[e]);
+    a1 += fabs((double)t[e]);
+    const double r = (double)u[e] + (double)s[e] + (double)t[e] - (double)v[e];
+    a2 += r * r;
+    const double dv = (double)t[ep] - (double)t[e];
+    a3 += dv * dv;
+  }
+  a0 = block_sum(a0, sh);
+  a1 = block_sum(a1, sh);
+  a2 = block_sum(a2, sh);
+  a3 = block_sum(a3, sh);
+  if (threadIdx.x == 0) {
+    red[blockIdx.x * 4 + 0] = a0;
+    red[blockIdx.x * 4 + 1] = a1;
+    red[blockIdx.x * 4 + 2] = a2;
+    red[blockIdx.x * 4 + 3] = a3;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_diag_final(int nblk, const double *red, double *out) {
+  __shared__ double sh[4];
+  double a[4] = {0, 0, 0, 0};
+  for (int k = threadIdx.x; k < nblk; k += kNT)
+    for (int c = 0; c < 4; ++c) a[c] += red[k * 4 + c];
+  for (int c = 0; c < 4; ++c) {
+    const double r = block_sum(a[c], sh);
+    if (threadIdx.x == 0) out[c] = r;
+  }
+}
+
+inline int grid_for(long long n, int per_thread, int nt = kNT) {
+  long long g = (n + (long long)nt * per_thread - 1) / ((long long)nt * per_thread);
+  if (g < 1) g = 1;
+  if (g > 65535) g = 65535;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill(float *p, long long n, float val, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 8)), dim3(kNT), 0, st, p, n, val);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 8)), dim3(kNT), 0, st, dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st) {
+  const long long n = (long long)(bytes / 4);
+  hipLaunchKernelGGL(k_zero_words, dim3(grid_for(n, 8)), dim3(kNT), 0, st, (uint32_t *)p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_scalars(const Plan &pl, double rel_tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, pl.sc, rel_tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float *x, long long n, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n, 16)), dim3(kNT), 0, st, x, n, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const float *t_cur,
+                         hipStream_t st) {
+  PrimalArgs a;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.Bp = pl.Bp; a.ncol = pl.ncol; a.N = pl.N;
+  a.g_u = pl.g_u; a.g_s = pl.g_s; a.g_t = pl.g_t; a.lo = pl.mu_min; a.hi = pl.mu_max;
+  a.u = u_cur; a.s = pl.s; a.t = t_cur; a.y2 = pl.y2; a.w = pl.w; a.Z = pl.Z;
+  a.un = u_new; a.xs = pl.xs; a.xt = pl.xt; a.red = pl.red_primal; a.sc = pl.sc; a.hist = pl.hist;
+  hipLaunchKernelGGL(k_primal, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const Plan &pl, const float *x, const float *y, float ca, float cb,
+                       float *gout, hipStream_t st) {
+  GradArgs a;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.Bp = pl.Bp; a.ncol = pl.ncol; a.P = pl.P;
+  a.a = x; a.b = y; a.ca = ca; a.cb = cb; a.g = gout ? gout : pl.gradf; a.sc = pl.sc;
+  hipLaunchKernelGGL(k_grad, dim3(grid_for(pl.P * pl.Bp, 4)), dim3(kNT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_adj(const Plan &pl, const float *Z, float *w, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_adj, dim3(grid_for(pl.N, 4)), dim3(kNT), 0, st, pl.n1, pl.n2, pl.n3,
+                     pl.Bp, pl.ncol, pl.N, Z, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_zsum(const Plan &pl, hipStream_t st) {
+  ZsumArgs a;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.ncol = pl.ncol; a.k1 = pl.k1; a.k2 = pl.k2;
+  a.TA = pl.TA; a.TB = pl.TB; a.ntA = pl.ntA; a.ntB = pl.ntB; a.extA = pl.extA; a.extB = pl.extB;
+  a.zpart = pl.zpart; a.Z = pl.Z; a.sc = pl.sc;
+  const int nt = pl.ncol >= 256 ? 256 : pl.ncol;
+  hipLaunchKernelGGL(k_zsum, dim3((unsigned)pl.P), dim3(nt), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, const float *t_cur,
+                       float *t_new, const float *v, hipStream_t st) {
+  DualArgs a;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.N = pl.N; a.g_y2 = pl.g_y2; a.g_y3 = pl.g_y3;
+  a.un = u_new; a.uo = u_cur; a.xs = pl.xs; a.xt = pl.xt; a.to = t_cur; a.v = v;
+  a.s = pl.s; a.tn = t_new; a.y2 = pl.y2; a.w = pl.w; a.red = pl.red_dual; a.sc = pl.sc;
+  hipLaunchKernelGGL(k_dual, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Plan &pl, hipStream_t st) {
+  FinalArgs a;
+  a.nblk = pl.red_blocks; a.red_primal = pl.red_primal; a.red_dual = pl.red_dual;
+  a.eps_g3 = pl.eps * (double)pl.g_y3; a.sc = pl.sc;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kNT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_to_cubes(const float *f, float *c0, float *c1, long long P, int n3, int Bp,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_field_to_cubes, dim3(grid_for(P * n3, 4)), dim3(kNT), 0, st, f, c0, c1, P,
+                     n3, Bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_cubes_to_field(const float *c0, const float *c1, float *f, long long P, int n3,
+                                 int Bp, hipStream_t st) {
+  hipLaunchKernelGGL(k_cubes_to_field, dim3(grid_for(P * Bp, 4)), dim3(kNT), 0, st, c0, c1, f, P,
+                     n3, Bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const Plan &pl, const float *u, const float *s, const float *t,
+                              const float *v, double *out4, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_partial, dim3(pl.red_blocks), dim3(kNT), 0, st, pl.n1, pl.n2, pl.n3,
+                     pl.N, u, s, t, v, pl.red_primal);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kNT), 0, st, pl.red_blocks, pl.red_primal, out4);
+  return hipGetLastError();
+}
+
+}  // namespace s3ttv

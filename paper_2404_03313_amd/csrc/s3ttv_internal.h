@@ -1,0 +1,136 @@
+// Internal declarations shared by the gfx950 kernels and the C-ABI driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace s3ttv {
+
+// Number of float32 columns per block tile handled by one 16x16 MFMA step group.
+constexpr int kTile = 16;
+// Rows of the padded block (K <= 16 rows of the structure tensor, zero padded).
+constexpr int kRows = 16;
+
+// l1-ball threshold selection: radix selection on the IEEE bits of |x| in three levels
+// (bits 30..20, 19..9, 8..0). All values in one level-1 bin share an exponent, so per-bin
+// sums of the 24-bit significands are exact in 64-bit integers.
+constexpr int kL1Bins1 = 2048, kL1Shift1 = 20;
+constexpr int kL1Bins2 = 2048, kL1Shift2 = 9;
+constexpr int kL1Bins3 = 512, kL1Shift3 = 0;
+constexpr int kL1MaxBins = 2048;
+
+// Device-resident scalars of one solve.
+struct DevScalars {
+  double kappa;          // y3 = kappa * w, kappa in [0, 1)
+  double tau[2];         // soft thresholds of the s (0) and t (1) l1 balls
+  double S_above[2];     // l1 selection carry: sum of |x| above the current bin
+  unsigned long long C_above[2];  // ... and their count
+  uint32_t prefix[2];    // selected bit prefix so far
+  int32_t active[2];     // 1 if the l1 projection is not the identity
+  int32_t done;          // stop rule fired
+  int32_t iters;         // completed iterations
+  double rel_change;     // of the last completed iteration
+  double unorm2;         // ||u^(k-1)||^2 of the last iteration
+  int32_t nonfinite;     // a NaN/Inf was seen
+  int32_t max_sweeps;    // largest Jacobi sweep count seen
+  double wnorm2;         // ||w||^2 of the last dual step
+  double rel_tol;
+  int32_t pad[6];
+};
+
+// l1 histograms: per ball, per level: counts (u32) and significand sums (u64).
+struct L1Hist {
+  uint32_t cnt[2][3][kL1MaxBins];
+  unsigned long long sig[2][3][kL1MaxBins];
+};
+
+struct Plan {
+  int n1, n2, n3, k1, k2, K;
+  int Bp;        // bands padded to a multiple of 16
+  int ncol;      // 2 * Bp columns per block (comp-major: c = comp*Bp + band)
+  int ntile;     // ncol / 16
+  long long N;   // n1*n2*n3
+  long long P;   // n1*n2 pixels (= L blocks)
+  // apply tiling (anchors per workgroup tile) and overlap-add partial geometry
+  int TA, TB, ntA, ntB, extA, extB, apply_waves;
+  size_t apply_lds;
+  // step sizes and box (float for the vector arithmetic), radii (double)
+  float g_u, g_s, g_t, g_Y, g_y2, g_y3, mu_min, mu_max;
+  double eps, alpha, beta;
+  // grids of the reduction kernels
+  int red_blocks;
+  // workspace carve
+  float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *zpart, *Z;
+  double *red_primal;  // red_blocks * 4
+  double *red_dual;    // red_blocks
+  DevScalars *sc;
+  L1Hist *hist;
+  size_t bytes;
+};
+
+// ---------------------------------------------------------------- launchers (return hipError_t)
+
+// Vector / stencil kernels.
+hipError_t launch_fill(float *p, long long n, float val, hipStream_t st);
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st);
+hipError_t launch_init_scalars(const Plan &pl, double rel_tol, hipStream_t st);
+hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_check_finite(const float *x, long long n, DevScalars *sc, hipStream_t st);
+// Primal step (Alg. 1 steps 2-4) from (u_cur, s, t_cur, y2, w, Z) into (u_new, xs, xt),
+// plus the level-1 l1 histograms and the stop-rule partial sums.
+hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const float *t_cur,
+                         hipStream_t st);
+// gradient field of u' = ca*a + cb*b into pl.gradf (or gout with the given column stride)
+hipError_t launch_grad(const Plan &pl, const float *a, const float *b, float ca, float cb,
+                       float *gout, hipStream_t st);
+hipError_t launch_zsum(const Plan &pl, hipStream_t st);
+hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, const float *t_cur,
+                       float *t_new, const float *v, hipStream_t st);
+hipError_t launch_finalize(const Plan &pl, hipStream_t st);
+
+// l1 threshold selection for the two balls (ball count 1 or 2): level = 1, 2, 3.
+hipError_t launch_l1_hist(const float *x0, const float *x1, long long n, int nballs, int level,
+                          L1Hist *hist, DevScalars *sc, hipStream_t st);
+hipError_t launch_l1_select(int nballs, int level, double r0, double r1, L1Hist *hist,
+                            DevScalars *sc, hipStream_t st);
+hipError_t launch_l1_apply(const float *x, float *out, long long n, int ball, DevScalars *sc,
+                           hipStream_t st);
+
+// Block kernels (Alg. 1 steps 9-10).
+struct BlockArgs {
+  int n1, n2, k1, k2, K, ncol, ntile;
+  long long nblk;          // number of blocks (anchors)
+  const float *gradf;      // [pixel][ncol] or nullptr (T = 0)
+  float gY;
+  float *Y;                // apply layout, nblk * 16 * ncol floats
+  float *G, *W;            // nblk * 256 floats each
+  // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
+  int TA, TB, ntA, ntB, extA, extB, waves;
+  size_t lds;
+  float *zpart;
+  DevScalars *sc;          // done flag and sweep statistics (nullable)
+};
+hipError_t launch_gram(const BlockArgs &a, hipStream_t st);
+hipError_t launch_eig(const BlockArgs &a, hipStream_t st);
+hipError_t launch_apply(const BlockArgs &a, hipStream_t st);
+
+// Layout converters for the operator entry points.
+// rows x ncols_src row-major blocks <-> apply layout with ncol padded columns. For the
+// structure-tensor layout (paper column order 2b+comp) set paper_cols = 1 with n3 bands.
+hipError_t launch_pack_blocks(const float *src, float *Y, long long nblk, int K, int ncols_src,
+                              int ncol, int paper_cols, int n3, int Bp, hipStream_t st);
+hipError_t launch_unpack_blocks(const float *Y, float *dst, long long nblk, int K,
+                                int ncols_src, int ncol, int paper_cols, int n3, int Bp,
+                                hipStream_t st);
+// [pixel][ncol] field <-> two ABI cubes.
+hipError_t launch_field_to_cubes(const float *f, float *c0, float *c1, long long P, int n3,
+                                 int Bp, hipStream_t st);
+hipError_t launch_cubes_to_field(const float *c0, const float *c1, float *f, long long P, int n3,
+                                 int Bp, hipStream_t st);
+// Plain adjoint D_s^T(D_v^T zv + D_h^T zh) from a [pixel][ncol] field.
+hipError_t launch_grad_adj(const Plan &pl, const float *Z, float *w, hipStream_t st);
+// Residual diagnostics of the result (host reads): ||s||_1, ||t||_1, ||u+s+t-v||, ||D_v t||.
+hipError_t launch_diagnostics(const Plan &pl, const float *u, const float *s, const float *t,
+                              const float *v, double *out4, hipStream_t st);
+
+}  // namespace s3ttv

@@ -1,0 +1,68 @@
+"""Host-only checks of the C ABI: the library loads, exports every function declared in
+include/s3ttv.h, and rejects invalid arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_03313_amd import native as nt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(s3ttv_\w+)\s*\(", txt, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = _declared_functions()
+    assert len(declared) >= 9
+    L = nt.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(nt.EXPORTS) == declared
+
+
+def test_strerror_and_workspace_queries():
+    assert nt.strerror(0) == "ok"
+    assert "workspace" in nt.strerror(nt.EWORKSPACE)
+    b1 = nt.workspace_bytes(32, 32, 16, 3, 3)
+    b2 = nt.workspace_bytes(256, 256, 128, 4, 4)
+    # dominant term: one 16 x 2*Bp dual block per pixel
+    assert b2 > 256 * 256 * 16 * 256 * 4
+    assert b1 < b2
+
+
+@pytest.mark.parametrize("shape,code", [((1, 8, 4, 1, 1), nt.EINVAL), ((8, 8, 1, 1, 1), nt.EINVAL),
+                                        ((8, 8, 4, 9, 1), nt.EINVAL), ((8, 8, 4, 0, 2), nt.EINVAL),
+                                        ((8, 8, 4, 5, 4), nt.EUNSUPPORTED)])
+def test_shape_validation(shape, code):
+    sz = ctypes.c_size_t()
+    sh = nt.Shape(*shape)
+    assert nt.lib().s3ttv_workspace_bytes(ctypes.byref(sh), None, ctypes.byref(sz)) == code
+
+
+@pytest.mark.parametrize("bad", [dict(eps=0.0), dict(alpha=-1.0), dict(beta=float("nan")),
+                                 dict(mu_min=1.0, mu_max=0.0), dict(max_iter=0),
+                                 dict(gammas=dict(gamma_u=0.1))])
+def test_param_validation_before_any_gpu_call(bad):
+    kw = dict(eps=1.0, alpha=1.0, beta=1.0, max_iter=10)
+    kw.update(bad)
+    p = nt.make_params(**kw)
+    dummy = ctypes.c_void_p(16)   # never dereferenced: validation fails first
+    rc = nt.lib().s3ttv_solve(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), dummy, None,
+                              dummy, dummy, dummy, dummy, 1 << 30, None, None)
+    assert rc == nt.EINVAL
+
+
+def test_null_pointers_rejected():
+    p = nt.make_params(1.0, 1.0, 1.0, 10)
+    rc = nt.lib().s3ttv_solve(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), None, None,
+                              None, None, None, None, 0, None, None)
+    assert rc == nt.EINVAL
