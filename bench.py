@@ -64,6 +64,8 @@ def main() -> int:
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol-cap", type=int, default=20000)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the solver has no "
@@ -126,7 +128,23 @@ def main() -> int:
                      "traffic": None, "avg_launch_ms": apply_ms,
                      "algorithmic_bytes_per_launch": apply_bytes},
         "eig_max_sweeps": st["eig_max_sweeps"],
+        "eig_avg_sweeps": st["eig_avg_sweeps"],
     }
+
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        dst.copy_(src)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        out["copy_probe"] = {"bytes_each_way": src.numel() * 4, "ms": ms,
+                             "GBps_read_plus_write": 2 * src.numel() * 4 / (ms * 1e-3) / 1e9}
+        del src, dst
 
     if not args.skip_tol:
         print(f"[bench] time to rel-tol 1e-4 (cap {args.tol_cap})", file=sys.stderr, flush=True)

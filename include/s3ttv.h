@@ -100,7 +100,8 @@ typedef struct {
   double l1_s, l1_t;    /* ||s||_1, ||t||_1 of the result */
   double fid;           /* ||u + s + t - v||_2 of the result */
   double dv_t;          /* ||D_v t||_2 of the result */
-  int32_t eig_max_sweeps; /* largest Jacobi sweep count used by any block */
+  int32_t eig_max_sweeps; /* largest Jacobi sweep count used by any wavefront of blocks */
+  float eig_avg_sweeps;   /* Jacobi sweeps per wavefront of 64 blocks, averaged over the solve */
   float ms;             /* wall time of the iteration loop (HIP events) */
   float kernel_ms[S3TTV_K_COUNT];     /* summed durations of timed classes */
   int32_t kernel_calls[S3TTV_K_COUNT];

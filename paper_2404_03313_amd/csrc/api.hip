@@ -57,7 +57,7 @@ void choose_tiles(Plan &pl) {
   static const int cand[][2] = {{8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
   for (auto &c : cand) {
     int TA = c[0] < pl.n1 ? c[0] : pl.n1, TB = c[1] < pl.n2 ? c[1] : pl.n2;
-    const size_t lds = (size_t)(TA + pl.k1 - 1) * (TB + pl.k2 - 1) * pl.ncol * sizeof(float);
+    const size_t lds = (size_t)(TA + pl.k1 - 1) * (TB + pl.k2 - 1) * (pl.ncol + 16) * sizeof(float);
     pl.TA = TA;
     pl.TB = TB;
     pl.apply_lds = lds;
@@ -103,6 +103,7 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.zpart = cv.take<float>((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB * pl.ncol);
   pl.G = cv.take<float>((size_t)pl.P * 256);
   pl.W = cv.take<float>((size_t)pl.P * 256);
+  pl.V = cv.take<float>((size_t)pl.P * 256);
   pl.Y = cv.take<float>((size_t)pl.P * kRows * pl.ncol);
   pl.red_primal = cv.take<double>((size_t)pl.red_blocks * 4);
   pl.red_dual = cv.take<double>((size_t)(pl.red_blocks > 4 ? pl.red_blocks : 4));
@@ -126,6 +127,7 @@ BlockArgs block_args(const Plan &pl) {
   a.Y = pl.Y;
   a.G = pl.G;
   a.W = pl.W;
+  a.V = pl.V;
   a.TA = pl.TA;
   a.TB = pl.TB;
   a.ntA = pl.ntA;
@@ -298,6 +300,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
   CK(launch_fill(pl.w, pl.N, 0.f, st));
   CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
   CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
+  CK(launch_identity16(pl.V, pl.P, st));
   {
     int32_t bad = 0;
     CK(hipMemcpyAsync(&bad, &pl.sc->nonfinite, sizeof(bad), hipMemcpyDeviceToHost, st));
@@ -363,6 +366,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     stats->fid = sqrt(diag[2]);
     stats->dv_t = sqrt(diag[3]);
     stats->eig_max_sweeps = hs.max_sweeps;
+    stats->eig_avg_sweeps = hs.sweep_waves ? (float)((double)hs.sweep_sum / (double)hs.sweep_waves) : 0.f;
     stats->ms = ms;
     for (auto &r : tm.rec) {
       float k = 0.f;
@@ -478,6 +482,7 @@ int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const flo
   a.Y = Y;
   a.G = G;
   a.W = W;
+  a.V = nullptr;
   a.TA = 1;
   a.TB = nblk < 64 ? nblk : 64;
   a.ntA = 1;
@@ -512,7 +517,8 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   CK(launch_init_scalars(pl, 0.0, st));
   CK(launch_grad(pl, up, up, 1.f, 0.f, pl.gradf, st));
   CK(launch_pack_blocks(yin, pl.Y, pl.P, pl.K, 2 * pl.n3, pl.ncol, 1, pl.n3, pl.Bp, st));
-  const BlockArgs ba = block_args(pl);
+  BlockArgs ba = block_args(pl);
+  ba.V = nullptr;
   CK(launch_gram(ba, st));
   CK(launch_eig(ba, st));
   CK(launch_apply(ba, st));

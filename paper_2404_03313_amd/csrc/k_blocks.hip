@@ -43,28 +43,83 @@ __device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
 // Y'[r][16t + 4kk + s] as both operands, so the 16x16x4 products accumulate
 // G = sum_c Y'[:, c] Y'[:, c]^T. Result lane (j, g) register v = G[4g+v][j].
 __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
+  // per-wavefront transpose buffer for one 16 x 16 tile, row stride 20 floats (conflict-free
+  // for both the 4-byte writes and the 16-byte reads)
+  __shared__ float tbuf[4][16 * 20];
   if (a.sc && a.sc->done) return;
-  const int lane = threadIdx.x & 63;
-  const long long l = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long l = (long long)blockIdx.x * 4 + wave;
   if (l >= a.nblk) return;
   const int r = lane & 15, kk = lane >> 4;
   const int pix = a.gradf ? row_pixel(a, l, r) : -1;
-  const float *Yl = a.Y + (size_t)l * kRows * a.ncol;
+  const f4 *Yl = (const f4 *)(a.Y + (size_t)l * kRows * a.ncol) + lane;
   const float *Tp = pix >= 0 ? a.gradf + (size_t)pix * a.ncol + 4 * kk : nullptr;
-  const int yoff = (16 * (r >> 2) + 4 * kk) * 4 + (r & 3);
+  float *tb = tbuf[wave];
   f4 acc = {0.f, 0.f, 0.f, 0.f};
+  f4 ycur = Yl[0];
   for (int t = 0; t < a.ntile; ++t) {
-    const float *Yt = Yl + t * 256 + yoff;
+    // apply layout: this lane holds rows 4kk+s of column r of tile t (lane = 16*kk + r)
+    const f4 ynext = t + 1 < a.ntile ? Yl[64 * (t + 1)] : ycur;
     f4 T = {0.f, 0.f, 0.f, 0.f};
     if (Tp) T = *(const f4 *)(Tp + 16 * t);
-    const float y0 = fmaf(a.gY, T[0], Yt[0]);
-    const float y1 = fmaf(a.gY, T[1], Yt[4]);
-    const float y2 = fmaf(a.gY, T[2], Yt[8]);
-    const float y3 = fmaf(a.gY, T[3], Yt[12]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) tb[(4 * kk + s) * 20 + r] = ycur[s];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Gram layout: row r, columns 4kk..4kk+3 of the tile
+    const f4 yg = *(const f4 *)(tb + r * 20 + 4 * kk);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float y0 = fmaf(a.gY, T[0], yg[0]);
+    const float y1 = fmaf(a.gY, T[1], yg[1]);
+    const float y2 = fmaf(a.gY, T[2], yg[2]);
+    const float y3 = fmaf(a.gY, T[3], yg[3]);
     acc = mfma4(y0, y0, acc);
     acc = mfma4(y1, y1, acc);
     acc = mfma4(y2, y2, acc);
     acc = mfma4(y3, y3, acc);
+    ycur = ynext;
+  }
+  if (a.V) {
+    // Warm start. With M and N held in the result layout (lane j + 16g, register
+    // v = X[4g+v][j]) the four MFMA steps MFMA(M_v, N_v) accumulate M^T N.
+    // 1) Re-orthogonalise the stored eigenvector basis V by one Newton-Schulz step,
+    //    Vc = V (3I - V^T V) / 2, so rounding in the rotations never accumulates.
+    // 2) Rotate the Gram matrix into it: Gt = Vc^T G Vc.
+    const int j = lane & 15, g = lane >> 4;
+    float *Vl = a.V + (size_t)l * 256;
+    const float vd0 = Vl[(4 * g) * 16 + j], vd1 = Vl[(4 * g + 1) * 16 + j];
+    const float vd2 = Vl[(4 * g + 2) * 16 + j], vd3 = Vl[(4 * g + 3) * 16 + j];
+    const f4 vt = *(const f4 *)(Vl + j * 16 + 4 * g);  // result layout of V^T
+    f4 X = {0.f, 0.f, 0.f, 0.f};
+    X = mfma4(vd0, vd0, X);  // V^T V
+    X = mfma4(vd1, vd1, X);
+    X = mfma4(vd2, vd2, X);
+    X = mfma4(vd3, vd3, X);
+    f4 VX = {0.f, 0.f, 0.f, 0.f};
+    VX = mfma4(vt[0], X[0], VX);  // (V^T)^T X = V X
+    VX = mfma4(vt[1], X[1], VX);
+    VX = mfma4(vt[2], X[2], VX);
+    VX = mfma4(vt[3], X[3], VX);
+    const float c0 = fmaf(1.5f, vd0, -0.5f * VX[0]), c1 = fmaf(1.5f, vd1, -0.5f * VX[1]);
+    const float c2 = fmaf(1.5f, vd2, -0.5f * VX[2]), c3 = fmaf(1.5f, vd3, -0.5f * VX[3]);
+    f4 P = {0.f, 0.f, 0.f, 0.f};
+    P = mfma4(acc[0], c0, P);  // G^T Vc = G Vc
+    P = mfma4(acc[1], c1, P);
+    P = mfma4(acc[2], c2, P);
+    P = mfma4(acc[3], c3, P);
+    f4 Gt = {0.f, 0.f, 0.f, 0.f};
+    Gt = mfma4(c0, P[0], Gt);  // Vc^T (G Vc)
+    Gt = mfma4(c1, P[1], Gt);
+    Gt = mfma4(c2, P[2], Gt);
+    Gt = mfma4(c3, P[3], Gt);
+    acc = Gt;
+    Vl[(4 * g) * 16 + j] = c0;
+    Vl[(4 * g + 1) * 16 + j] = c1;
+    Vl[(4 * g + 2) * 16 + j] = c2;
+    Vl[(4 * g + 3) * 16 + j] = c3;
   }
   float *Gl = a.G + (size_t)l * 256 + (4 * (lane >> 4)) * 16 + (lane & 15);
   Gl[0] = acc[0];
@@ -76,10 +131,11 @@ __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
 // ---------------------------------------------------------------- Jacobi eigen-solve
 
 // One lane per block: the lane holds the upper triangle of its symmetric Gram matrix (136
-// floats) and the eigenvector matrix V (256 floats) in registers, and runs cyclic Jacobi
+// floats) and the eigenvector matrix V (256 floats) in registers and runs cyclic Jacobi
 // sweeps (row order p < q). All register indices are compile-time constants (the sweep is
 // fully unrolled). A rotation whose pivot |G_pq| is at most thr = kJacobiTol * ||G||_F in
 // every lane of the wavefront is skipped; the solve stops when no pivot exceeds thr.
+// With a stored basis (warm start) the input is V^T G V and the rotations continue V.
 // Output: W = I - sum_k (1 - min(1, lambda_k^{-1/2})) v_k v_k^T, row-major.
 
 constexpr int kMaxSweeps = 16;
@@ -134,28 +190,32 @@ __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
   long long blk = (long long)blockIdx.x * 64 + threadIdx.x;
   const bool valid = blk < a.nblk;
   if (!valid) blk = a.nblk - 1;  // duplicate a real block so every lane runs the same sweeps
-  const f4 *g4 = (const f4 *)(a.G + (size_t)blk * 256);
-  float Gf[256];
-#pragma unroll
-  for (int k = 0; k < 64; ++k) {
-    const f4 v = g4[k];
-    Gf[4 * k] = v[0];
-    Gf[4 * k + 1] = v[1];
-    Gf[4 * k + 2] = v[2];
-    Gf[4 * k + 3] = v[3];
-  }
+  // The Gram matrix from k_gram is symmetric; read its upper triangle.
+  const float *Gl = a.G + (size_t)blk * 256;
   float A[136], V[256];
   float fro = 0.f;
 #pragma unroll
   for (int p = 0; p < 16; ++p)
 #pragma unroll
     for (int q = p; q < 16; ++q) {
-      const float x = 0.5f * (Gf[p * 16 + q] + Gf[q * 16 + p]);
+      const float x = Gl[p * 16 + q];
       A[tri(p, q)] = x;
       fro = fmaf(p == q ? x : 2.f * x, x, fro);
     }
+  if (a.V) {
+    const f4 *v4 = (const f4 *)(a.V + (size_t)blk * 256);
 #pragma unroll
-  for (int k = 0; k < 256; ++k) V[k] = (k / 16 == k % 16) ? 1.f : 0.f;
+    for (int k = 0; k < 64; ++k) {
+      const f4 x = v4[k];
+      V[4 * k] = x[0];
+      V[4 * k + 1] = x[1];
+      V[4 * k + 2] = x[2];
+      V[4 * k + 3] = x[3];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 256; ++k) V[k] = (k / 16 == k % 16) ? 1.f : 0.f;
+  }
   const float thr = kJacobiTol * sqrtf(fro);
   int sweeps = 0;
   for (; sweeps < kMaxSweeps; ++sweeps) {
@@ -173,33 +233,38 @@ __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
     const float lam = A[tri(k, k)];
     h[k] = lam > 1.f ? 1.f - rsqrtf(lam) : 0.f;
   }
-  float Wt[136];
-#pragma unroll
-  for (int p = 0; p < 16; ++p) {
-    float hv[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) hv[k] = h[k] * V[p * 16 + k];
-#pragma unroll
-    for (int q = p; q < 16; ++q) {
-      float acc = 0.f;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) acc = fmaf(hv[k], V[q * 16 + k], acc);
-      Wt[tri(p, q)] = (p == q ? 1.f : 0.f) - acc;
-    }
-  }
   if (valid) {
+    // W row by row (W = I - V diag(h) V^T), written as it is formed
     f4 *w4 = (f4 *)(a.W + (size_t)blk * 256);
 #pragma unroll
-    for (int k = 0; k < 64; ++k) {
-      f4 v;
+    for (int p = 0; p < 16; ++p) {
+      float hv[16];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = (4 * k + e) / 16, c = (4 * k + e) % 16;
-        v[e] = r <= c ? Wt[tri(r, c)] : Wt[tri(c, r)];
+      for (int k = 0; k < 16; ++k) hv[k] = h[k] * V[p * 16 + k];
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        f4 o;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int q = 4 * q4 + e;
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) acc = fmaf(hv[k], V[q * 16 + k], acc);
+          o[e] = (p == q ? 1.f : 0.f) - acc;
+        }
+        w4[p * 4 + q4] = o;
       }
-      w4[k] = v;
     }
-    if (a.sc) atomicMax(&a.sc->max_sweeps, sweeps);
+    if (a.V) {
+      f4 *v4 = (f4 *)(a.V + (size_t)blk * 256);
+#pragma unroll
+      for (int k = 0; k < 64; ++k) v4[k] = (f4){V[4 * k], V[4 * k + 1], V[4 * k + 2], V[4 * k + 3]};
+    }
+  }
+  if (a.sc && threadIdx.x == 0) {
+    atomicMax(&a.sc->max_sweeps, sweeps);
+    atomicAdd(&a.sc->sweep_sum, (unsigned long long)sweeps);
+    atomicAdd(&a.sc->sweep_waves, 1ull);
   }
 }
 
@@ -220,56 +285,83 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
   const int np = min(a.TA, a.n1 - p0), nq = min(a.TB, a.n2 - q0);
   const bool doz = a.zpart != nullptr;
   const int next = a.extA * a.extB;
+  const int zs = a.ncol + 16;  // padded LDS row stride: the four row groups land in distinct banks
   if (doz) {
     for (int t = wave; t < a.ntile; t += a.waves)
-      for (int e = g; e < next; e += 4) zacc[(size_t)e * a.ncol + 16 * t + tc] = 0.f;
+      for (int e = g; e < next; e += 4) zacc[(size_t)e * zs + 16 * t + tc] = 0.f;
   }
-  for (int da = 0; da < np; ++da)
-    for (int db = 0; db < nq; ++db) {
-      const long long l = (long long)(p0 + da) * a.n2 + (q0 + db);
-      const f4 wv = *(const f4 *)(a.W + (size_t)l * 256 + tc * 16 + 4 * g);
-      int pix[4], zo[4];
+  // Window geometry of this lane's four rows 4g+s (fixed for the whole kernel).
+  int ar[4], cr[4];
+  bool rv[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int row = 4 * g + s;
+    rv[s] = row < a.K && a.gradf != nullptr;
+    ar[s] = row / a.k2;
+    cr[s] = row - ar[s] * a.k2;
+  }
+  const bool hasT = a.gradf != nullptr;
+  // Anchors are visited in a fixed order (row-major inside the tile); for each group of kU
+  // anchors all loads are issued before any result is consumed, so each wavefront keeps
+  // several 1 KB tiles in flight. Per column the overlap-add order is the anchor order.
+  constexpr int kU = 4;
+  const int nanch = np * nq;
+  for (int anc0 = 0; anc0 < nanch; anc0 += kU) {
+    long long lb[kU];
+    int pixo[kU][4], zo[kU][4];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int anc = anc0 + u < nanch ? anc0 + u : nanch - 1;  // tail: repeat, not stored
+      const int da = anc / nq, db = anc - (anc / nq) * nq;
+      const int p = p0 + da, q = q0 + db;
+      lb[u] = (long long)p * a.n2 + q;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int row = 4 * g + s;
-        pix[s] = a.gradf ? row_pixel(a, l, row) : -1;
-        if (row < a.K) {
-          const int ar = row / a.k2, cr = row - (row / a.k2) * a.k2;
-          zo[s] = ((da + ar) * a.extB + (db + cr)) * a.ncol;
-        } else {
-          zo[s] = -1;
-        }
+        int i = p + ar[s];
+        if (i >= a.n1) i -= a.n1;
+        int j = q + cr[s];
+        if (j >= a.n2) j -= a.n2;
+        pixo[u][s] = rv[s] ? (i * a.n2 + j) * a.ncol : -1;
+        zo[u][s] = (4 * g + s < a.K) ? ((da + ar[s]) * a.extB + (db + cr[s])) * zs : -1;
       }
-      float *Yl = a.Y + (size_t)l * kRows * a.ncol + lane * 4;
-      for (int t = wave; t < a.ntile; t += a.waves) {
-        f4 *Yt = (f4 *)(Yl + t * 256);
-        const f4 y = *Yt;
-        float yp[4];
+    }
+    for (int t = wave; t < a.ntile; t += a.waves) {
+      const int col = 16 * t + tc;
+      f4 wv[kU], y[kU];
+      float T[kU][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const float T = pix[s] >= 0 ? a.gradf[(size_t)pix[s] * a.ncol + 16 * t + tc] : 0.f;
-          yp[s] = fmaf(a.gY, T, y[s]);
-        }
+      for (int u = 0; u < kU; ++u) {
+        wv[u] = *(const f4 *)(a.W + (size_t)lb[u] * 256 + tc * 16 + 4 * g);
+        y[u] = *(const f4 *)(a.Y + (size_t)lb[u] * kRows * a.ncol + t * 256 + lane * 4);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) T[u][s] = (hasT && pixo[u][s] >= 0) ? a.gradf[pixo[u][s] + col] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (anc0 + u >= nanch) break;
+        const float yp0 = fmaf(a.gY, T[u][0], y[u][0]);
+        const float yp1 = fmaf(a.gY, T[u][1], y[u][1]);
+        const float yp2 = fmaf(a.gY, T[u][2], y[u][2]);
+        const float yp3 = fmaf(a.gY, T[u][3], y[u][3]);
         f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mfma4(wv[0], yp[0], acc);
-        acc = mfma4(wv[1], yp[1], acc);
-        acc = mfma4(wv[2], yp[2], acc);
-        acc = mfma4(wv[3], yp[3], acc);
-        *Yt = acc;
+        acc = mfma4(wv[u][0], yp0, acc);
+        acc = mfma4(wv[u][1], yp1, acc);
+        acc = mfma4(wv[u][2], yp2, acc);
+        acc = mfma4(wv[u][3], yp3, acc);
+        *(f4 *)(a.Y + (size_t)lb[u] * kRows * a.ncol + t * 256 + lane * 4) = acc;
         if (doz) {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (zo[v] >= 0) zacc[zo[v] + 16 * t + tc] += acc[v];
+            if (zo[u][v] >= 0) zacc[zo[u][v] + col] += acc[v];
         }
       }
     }
+  }
   if (doz) {
     float *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
     for (int t = wave; t < a.ntile; t += a.waves)
-      for (int e = g; e < next; e += 4) {
-        const size_t o = (size_t)e * a.ncol + 16 * t + tc;
-        zp[o] = zacc[o];
-      }
+      for (int e = g; e < next; e += 4)
+        zp[(size_t)e * a.ncol + 16 * t + tc] = zacc[(size_t)e * zs + 16 * t + tc];
   }
 }
 

@@ -46,18 +46,32 @@ __global__ __launch_bounds__(kNT) void k_l1_hist(const float *x0, const float *x
   for (int k = threadIdx.x; k < 2 * kL1MaxBins; k += kNT) (&h[0][0])[k] = 0ull;
   __syncthreads();
   const uint32_t mask = (uint32_t)nb - 1u;
-  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n;
+  auto add = [&](int k, float x) {
+    const uint32_t bits = __float_as_uint(x) & 0x7fffffffu;
+    if (level > 1 && (bits >> ps) != pref[k]) return;
+    const uint32_t ex = bits >> 23;
+    const uint32_t sig = ex ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
+    atomicAdd(&h[k][(bits >> shift) & mask], (1ull << 40) | (unsigned long long)sig);
+  };
+  // four elements per thread per trip (16-byte loads), scalar tail
+  const long long n4 = n >> 2;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n4;
        e += (long long)gridDim.x * kNT) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (!use[k]) continue;
-      const float x = (k == 0 ? x0 : x1)[e];
-      const uint32_t bits = __float_as_uint(x) & 0x7fffffffu;
-      if (level > 1 && (bits >> ps) != pref[k]) continue;
-      const uint32_t ex = bits >> 23;
-      const uint32_t sig = ex ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
-      atomicAdd(&h[k][(bits >> shift) & mask], (1ull << 40) | (unsigned long long)sig);
+      const float4 x = reinterpret_cast<const float4 *>(k == 0 ? x0 : x1)[e];
+      add(k, x.x);
+      add(k, x.y);
+      add(k, x.z);
+      add(k, x.w);
     }
+  }
+  for (long long e = 4 * n4 + (long long)blockIdx.x * kNT + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kNT) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      if (use[k]) add(k, (k == 0 ? x0 : x1)[e]);
   }
   __syncthreads();
   for (int k = 0; k < 2; ++k) {

@@ -197,51 +197,54 @@ struct ZsumArgs {
   DevScalars *sc;
 };
 
-// Slots (tile, ext index) of the partial buffers that hold contributions to pixel row x:
-// tiles of the anchors x - a (a < k), every ext index congruent to x inside those tiles.
-// Writes at most 32 slots to LDS arrays; returns the count.
-__device__ inline int zslots(int x, int n, int k, int TT, int ext, int *tile, int *ext_idx) {
-  int ns = 0;
-  int last_tile = -1, first_tile = -1;
-  for (int off = 0; off < k; ++off) {
-    const int anchor = wrap_dn(x - off, n);
-    const int tt = anchor / TT;
-    // tiles of consecutive anchors form at most two runs (wrap), so comparing with the
-    // previous and first tile visited removes every duplicate
-    if (tt == last_tile || tt == first_tile) continue;
-    if (first_tile < 0) first_tile = tt;
-    last_tile = tt;
-    int e0 = x - tt * TT;
-    if (e0 < 0) e0 += n;
-    for (int e = e0; e < ext && ns < 32; e += n) {
-      tile[ns] = tt;
-      ext_idx[ns] = e;
-      ++ns;
-    }
-  }
-  return ns;
+// Overlap-add partials: anchor tile (ta, tb) holds the contributions of its anchors to the
+// pixels of its extended region (TA + k1 - 1) x (TB + k2 - 1). Pixel row x receives partials
+// from the tiles of the anchors x - a (a < k1, on the torus), at every extended row index
+// congruent to x. The anchors x, x-1, ... form one circular run, so a tile repeats only as a
+// run of equal neighbours or as the first tile again after the wrap.
+__device__ inline int anchor_tile(int x, int off, int n, int TT) { return wrap_dn(x - off, n) / TT; }
+
+__device__ inline bool first_visit(int x, int off, int n, int TT) {
+  if (off == 0) return true;
+  const int tt = anchor_tile(x, off, n, TT);
+  return tt != anchor_tile(x, off - 1, n, TT) && tt != anchor_tile(x, 0, n, TT);
 }
 
+// Z[pix][c] = sum over slots of zpart[slot][c], four columns per thread.
 __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
-  __shared__ int rt[32], re[32], ct[32], ce[32];
-  __shared__ int nsl[2];
   if (a.sc && a.sc->done) return;
-  const int pix = blockIdx.x;
-  if (threadIdx.x == 0) {
+  const int c4n = a.ncol >> 2;
+  const long long total = (long long)a.n1 * a.n2 * c4n;
+  const size_t tile_stride = (size_t)a.extA * a.extB;
+  for (long long idx = (long long)blockIdx.x * kNT + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * kNT) {
+    const int pix = (int)(idx / c4n);
+    const int c4 = (int)(idx - (long long)pix * c4n);
     const int i = pix / a.n2, j = pix - (pix / a.n2) * a.n2;
-    nsl[0] = zslots(i, a.n1, a.k1, a.TA, a.extA, rt, re);
-    nsl[1] = zslots(j, a.n2, a.k2, a.TB, a.extB, ct, ce);
-  }
-  __syncthreads();
-  const int nr = nsl[0], nc = nsl[1];
-  for (int c = threadIdx.x; c < a.ncol; c += blockDim.x) {
-    float acc = 0.f;
-    for (int r = 0; r < nr; ++r)
-      for (int q = 0; q < nc; ++q) {
-        const size_t slot = (((size_t)rt[r] * a.ntB + ct[q]) * a.extA + re[r]) * a.extB + ce[q];
-        acc += a.zpart[slot * a.ncol + c];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int offr = 0; offr < a.k1; ++offr) {
+      if (!first_visit(i, offr, a.n1, a.TA)) continue;
+      const int ta = anchor_tile(i, offr, a.n1, a.TA);
+      int e0 = i - ta * a.TA;
+      if (e0 < 0) e0 += a.n1;
+      for (int ei = e0; ei < a.extA; ei += a.n1) {
+        for (int offc = 0; offc < a.k2; ++offc) {
+          if (!first_visit(j, offc, a.n2, a.TB)) continue;
+          const int tb = anchor_tile(j, offc, a.n2, a.TB);
+          int f0 = j - tb * a.TB;
+          if (f0 < 0) f0 += a.n2;
+          for (int ej = f0; ej < a.extB; ej += a.n2) {
+            const size_t slot = ((size_t)ta * a.ntB + tb) * tile_stride + (size_t)ei * a.extB + ej;
+            const float4 v = reinterpret_cast<const float4 *>(a.zpart)[slot * c4n + c4];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+          }
+        }
       }
-    a.Z[(size_t)pix * a.ncol + c] = acc;
+    }
+    reinterpret_cast<float4 *>(a.Z)[(size_t)pix * c4n + c4] = acc;
   }
 }
 
@@ -337,6 +340,15 @@ __global__ void k_fill(float *p, long long n, float val) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
     p[e] = val;
+}
+
+__global__ void k_identity16(float *V, long long nblk) {
+  const long long n = nblk * 256;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int w = (int)(e & 255);
+    V[e] = (w >> 4) == (w & 15) ? 1.f : 0.f;
+  }
 }
 
 __global__ void k_copy(float *dst, const float *src, long long n) {
@@ -447,6 +459,11 @@ hipError_t launch_fill(float *p, long long n, float val, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_identity16(float *V, long long nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_identity16, dim3(grid_for(nblk * 256, 8)), dim3(kNT), 0, st, V, nblk);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 8)), dim3(kNT), 0, st, dst, src, n);
   return hipGetLastError();
@@ -499,8 +516,7 @@ hipError_t launch_zsum(const Plan &pl, hipStream_t st) {
   a.n1 = pl.n1; a.n2 = pl.n2; a.ncol = pl.ncol; a.k1 = pl.k1; a.k2 = pl.k2;
   a.TA = pl.TA; a.TB = pl.TB; a.ntA = pl.ntA; a.ntB = pl.ntB; a.extA = pl.extA; a.extB = pl.extB;
   a.zpart = pl.zpart; a.Z = pl.Z; a.sc = pl.sc;
-  const int nt = pl.ncol >= 256 ? 256 : pl.ncol;
-  hipLaunchKernelGGL(k_zsum, dim3((unsigned)pl.P), dim3(nt), 0, st, a);
+  hipLaunchKernelGGL(k_zsum, dim3(grid_for(pl.P * (pl.ncol / 4), 2)), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -35,7 +35,9 @@ struct DevScalars {
   int32_t max_sweeps;    // largest Jacobi sweep count seen
   double wnorm2;         // ||w||^2 of the last dual step
   double rel_tol;
-  int32_t pad[6];
+  unsigned long long sweep_sum;   // Jacobi sweeps summed over wavefronts
+  unsigned long long sweep_waves; // wavefronts counted in sweep_sum
+  int32_t pad[2];
 };
 
 // l1 histograms: per ball, per level: counts (u32) and significand sums (u64).
@@ -60,7 +62,7 @@ struct Plan {
   // grids of the reduction kernels
   int red_blocks;
   // workspace carve
-  float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *zpart, *Z;
+  float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *zpart, *Z;
   double *red_primal;  // red_blocks * 4
   double *red_dual;    // red_blocks
   DevScalars *sc;
@@ -72,6 +74,7 @@ struct Plan {
 
 // Vector / stencil kernels.
 hipError_t launch_fill(float *p, long long n, float val, hipStream_t st);
+hipError_t launch_identity16(float *V, long long nblk, hipStream_t st);
 hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st);
 hipError_t launch_init_scalars(const Plan &pl, double rel_tol, hipStream_t st);
 hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
@@ -104,6 +107,7 @@ struct BlockArgs {
   float gY;
   float *Y;                // apply layout, nblk * 16 * ncol floats
   float *G, *W;            // nblk * 256 floats each
+  float *V;                // nblk * 256: eigenvectors of the previous step (warm start) or null
   // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
   int TA, TB, ntA, ntB, extA, extB, waves;
   size_t lds;
