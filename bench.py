@@ -37,6 +37,28 @@ def apply_algorithmic_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> int:
     return 4 * L * (2 * K * 2 * n3 + K * K + 2 * n3 + 2 * n3)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the kernel source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_bytes_*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) < 5 or parts[0] != "traffic" or parts[1] != kernel:
+                    continue
+                kv = dict(p.split("=", 1) for p in parts[2:] if "=" in p)
+                src = os.path.join(ROOT, kv.get("source", ""))
+                if not os.path.isfile(src):
+                    continue
+                with open(src, "rb") as fs:
+                    digest = hashlib.sha256(fs.read()).hexdigest()[:16]
+                if digest == kv.get("sha256_16"):
+                    return int(kv["bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None
+
+
 def iteration_algorithmic_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> int:
     """(44 + 16K) bytes per voxel: u, s, t, y2, y3 read+written, v read, Y read+written."""
     N = n1 * n2 * n3
@@ -105,6 +127,7 @@ def main() -> int:
     apply_bytes = apply_algorithmic_bytes(n1, n2, n3, k1, k2)
     achieved = apply_bytes / (apply_ms * 1e-3) / 1e9
 
+    traffic = measured_traffic("k_apply")
     out = {
         "metric": METRIC,
         "value": value,
@@ -125,8 +148,9 @@ def main() -> int:
         "iteration_algorithmic_bytes": iteration_algorithmic_bytes(n1, n2, n3, k1, k2),
         "roofline": {"kernel": "k_apply", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_ms": apply_ms,
-                     "algorithmic_bytes_per_launch": apply_bytes},
+                     "traffic": traffic[0] if traffic else None, "avg_launch_ms": apply_ms,
+                     "algorithmic_bytes_per_launch": apply_bytes,
+                     "traffic_source": traffic[1] if traffic else None},
         "eig_max_sweeps": st["eig_max_sweeps"],
         "eig_avg_sweeps": st["eig_avg_sweeps"],
     }
