@@ -153,6 +153,9 @@ def main() -> int:
                      "traffic_source": traffic[1] if traffic else None},
         "eig_max_sweeps": st["eig_max_sweeps"],
         "eig_avg_sweeps": st["eig_avg_sweeps"],
+        "eig_avg_steps": st["eig_avg_steps"],
+        "eig_max_steps": st["eig_max_steps"],
+        "eig_fallback_blocks": st["eig_fallback_blocks"],
     }
 
     if args.copy_probe:

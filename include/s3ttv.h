@@ -100,8 +100,13 @@ typedef struct {
   double l1_s, l1_t;    /* ||s||_1, ||t||_1 of the result */
   double fid;           /* ||u + s + t - v||_2 of the result */
   double dv_t;          /* ||D_v t||_2 of the result */
-  int32_t eig_max_sweeps; /* largest Jacobi sweep count used by any wavefront of blocks */
-  float eig_avg_sweeps;   /* Jacobi sweeps per wavefront of 64 blocks, averaged over the solve */
+  int32_t eig_max_sweeps; /* largest per-lane Jacobi sweep count of any wavefront of blocks */
+  float eig_avg_sweeps;   /* per-lane Jacobi sweeps per wavefront that ran them, averaged */
+  float eig_avg_steps;    /* MFMA rotation steps per block, averaged over iterations 2..iters */
+  int32_t eig_max_steps;  /* largest MFMA rotation step count of one block */
+  int64_t eig_fallback_blocks; /* blocks of iterations 2..iters the MFMA rotations could not
+                                  certify, finished by the per-lane Jacobi (iteration 1 always
+                                  solves every block with the per-lane Jacobi) */
   float ms;             /* wall time of the iteration loop (HIP events) */
   float kernel_ms[S3TTV_K_COUNT];     /* summed durations of timed classes */
   int32_t kernel_calls[S3TTV_K_COUNT];

@@ -104,6 +104,7 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.G = cv.take<float>((size_t)pl.P * 256);
   pl.W = cv.take<float>((size_t)pl.P * 256);
   pl.V = cv.take<float>((size_t)pl.P * 256);
+  pl.eflag = cv.take<int>((size_t)pl.P);
   pl.Y = cv.take<float>((size_t)pl.P * kRows * pl.ncol);
   pl.red_primal = cv.take<double>((size_t)pl.red_blocks * 4);
   pl.red_dual = cv.take<double>((size_t)(pl.red_blocks > 4 ? pl.red_blocks : 4));
@@ -114,6 +115,7 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
 
 BlockArgs block_args(const Plan &pl) {
   BlockArgs a;
+  memset(&a, 0, sizeof(a));
   a.n1 = pl.n1;
   a.n2 = pl.n2;
   a.k1 = pl.k1;
@@ -307,7 +309,11 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     CK(hipStreamSynchronize(st));
     if (bad) return S3TTV_ENONFINITE;
   }
+  // First iteration: the stored basis is the identity, so every block is solved by the
+  // per-lane Jacobi (cold). Later iterations diagonalise on MFMA from the previous basis.
   const BlockArgs ba = block_args(pl);
+  BlockArgs bw = ba;
+  bw.eflag = pl.eflag;
   const int check = params->check_every > 0 ? params->check_every : 16;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
@@ -323,9 +329,10 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_GRAD, launch_grad(pl, pl.u[n], pl.u[c], 2.f, -1.f, nullptr, st));
-    TIMED(S3TTV_K_GRAM, launch_gram(ba, st));
-    TIMED(S3TTV_K_EIG, launch_eig(ba, st));
-    TIMED(S3TTV_K_APPLY, launch_apply(ba, st));
+    const BlockArgs &bk = it == 0 ? ba : bw;
+    TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
+    TIMED(S3TTV_K_EIG, launch_eig(bk, st));
+    TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
     TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
     TIMED(S3TTV_K_DUAL, launch_dual(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, st));
@@ -367,6 +374,9 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     stats->dv_t = sqrt(diag[3]);
     stats->eig_max_sweeps = hs.max_sweeps;
     stats->eig_avg_sweeps = hs.sweep_waves ? (float)((double)hs.sweep_sum / (double)hs.sweep_waves) : 0.f;
+    stats->eig_avg_steps = hs.step_blocks ? (float)((double)hs.step_sum / (double)hs.step_blocks) : 0.f;
+    stats->eig_max_steps = hs.max_steps;
+    stats->eig_fallback_blocks = (int64_t)hs.fallback_blocks;
     stats->ms = ms;
     for (auto &r : tm.rec) {
       float k = 0.f;

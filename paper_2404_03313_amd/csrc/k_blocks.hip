@@ -7,7 +7,10 @@
 // the projection of Y'_l onto the unit spectral-norm ball. With K <= 2B rows this is
 //   Y+_l = W_l Y'_l,   W_l = I - sum_{lambda_k > 1} (1 - lambda_k^{-1/2}) v_k v_k^T,
 // where (lambda_k, v_k) are the eigenpairs of the K x K Gram matrix G_l = Y'_l Y'_l^T.
-// Three kernels: Gram on MFMA (k_gram), a per-lane Jacobi eigen-solve (k_eig), and W_l Y'_l on MFMA with a deterministic overlap-add of the result (k_apply).
+// Three kernels: Gram on MFMA (k_gram), which in the warm-started solver also diagonalises the
+// Gram matrix on MFMA (simultaneous Jacobi rotations from the previous eigenbasis) and forms
+// W_l; a per-lane cyclic Jacobi eigen-solve (k_eig) for cold starts and for the blocks the MFMA
+// rotations cannot certify; and W_l Y'_l on MFMA with a deterministic overlap-add (k_apply).
 //
 // Block storage ("apply layout", 16 rows x ncol columns per block, ncol = 2*Bp, column
 // c = comp*Bp + band): column tile t holds columns 16t..16t+15 as 64 lanes x 4 floats,
@@ -25,6 +28,48 @@ __device__ inline f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// 16 x 16 matrices in the MFMA result layout ("D-form"): lane j + 16g, register v holds
+// X[4g+v][j]. Feeding the four registers of two D-form matrices M, N as the A and B operands
+// of four consecutive 16x16x4 steps accumulates M^T N.
+__device__ inline f4 mtn(f4 M, f4 N) {
+  f4 acc = {0.f, 0.f, 0.f, 0.f};
+  acc = mfma4(M[0], N[0], acc);
+  acc = mfma4(M[1], N[1], acc);
+  acc = mfma4(M[2], N[2], acc);
+  acc = mfma4(M[3], N[3], acc);
+  return acc;
+}
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sum over the 64 lanes; every lane receives the same (bitwise) value.
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+// Sum over the 16 lanes j of a row group (same value in all 16 lanes).
+__device__ inline float row_sum16(float x) {
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) x += __shfl_xor(x, m);
+  return x;
+}
+
+// Transpose of a D-form matrix through the wavefront's LDS tile (row stride 20 floats).
+__device__ inline f4 dform_transpose(f4 x, float *tb, int j, int g) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) tb[(4 * g + v) * 20 + j] = x[v];
+  wave_lds_sync();
+  const f4 y = *(const f4 *)(tb + j * 20 + 4 * g);
+  wave_lds_sync();
+  return y;
+}
+
 // Pixel offset (into the [pixel][ncol] field) of block row `row` of anchor l, or -1.
 __device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
   if (row >= a.K) return -1;
@@ -37,6 +82,166 @@ __device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
   return i * a.n2 + j;
 }
 
+// ---------------------------------------------------------------- eigen-solve on MFMA
+
+// Simultaneous Jacobi rotations on the wavefront's 16 x 16 Gram matrix G (D-form), warm
+// started from the stored eigenbasis V of the previous iteration:
+//   A = V^T G V; repeat: symmetrise A; if certified stop; else K_ij = tan(theta_ij), the
+//   tangent of the angle that zeroes A_ij in its own 2 x 2 rotation (|theta| <= pi/4), for all
+//   pairs at once (K is exactly skew: it is computed from the symmetrised A), damped to
+//   ||K||_F <= kStepCap; J = I + K + K^2/2 with J^T J = I + K^4/4, corrected to first order
+//   by J (I - K^4/8); A <- J^T A J, V <- V J.
+// Certificate (what W = f(G), f(l) = min(1, l^-1/2), needs): every off-diagonal A_ij with
+// A_ii > 1 or A_jj > 1 is at most kJacobiTol ||G||_F, and every row i with A_ii <= 1 has its
+// Gershgorin radius over the other such rows within 1 + kGershSlack, so no eigenvalue of that
+// sub-block exceeds 1. After a damped (large) step, V is re-orthogonalised by a Newton-Schulz
+// step and A recomputed as V^T G V before the certificate may be accepted. Certified blocks get
+// W = I - V diag((1 - A_ii^-1/2)_+) V^T; others (rare; cold starts) are left to k_eig with
+// A and V stored. V always leaves with one Newton-Schulz step applied.
+constexpr float kJacobiTol = 1e-7f;
+constexpr int kSteps = 24;
+constexpr float kStepCap = 0.5f;
+constexpr float kRoughNorm2 = 0.0225f;    // a step with ||K||_F > 0.15 forces the recompute
+constexpr float kQuarticNorm2 = 2e-4f;    // below this ||K^4||/8 is under FP32 rounding
+constexpr float kGershSlack = 1e-6f;
+
+__device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 15, g = lane >> 4;
+  float *Vl = a.V + (size_t)l * 256;
+  f4 vd;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) vd[v] = Vl[(4 * g + v) * 16 + j];
+  f4 Vt = *(const f4 *)(Vl + j * 16 + 4 * g);  // D-form of V^T
+  f4 A = mtn(vd, mtn(G, vd));                   // V^T G V  (G symmetric)
+  const float fro = sqrtf(wave_sum(G[0] * G[0] + G[1] * G[1] + G[2] * G[2] + G[3] * G[3]));
+  const float thr = kJacobiTol * fro;
+
+  // Newton-Schulz re-orthogonalisation of V (held as Vt); optionally returns D-form V too.
+  auto orthonormalise = [&](f4 &Vc) {
+    const f4 Vd = dform_transpose(Vt, tb, j, g);
+    const f4 X = mtn(Vd, Vd);          // V^T V
+    const f4 VX = mtn(Vt, X);          // V X
+    const f4 XVt = mtn(X, Vt);         // X V^T
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Vc[v] = fmaf(1.5f, Vd[v], -0.5f * VX[v]);
+      Vt[v] = fmaf(1.5f, Vt[v], -0.5f * XVt[v]);
+    }
+  };
+
+  f4 dI;
+  float dJ = 0.f;
+  bool ok = false, rough = false;
+  int steps = 0;
+  for (;;) {
+    // symmetrise (exactly) and fetch the diagonal for rows 4g+v and column j
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tb[(4 * g + v) * 20 + j] = A[v];
+    wave_lds_sync();
+    const f4 At = *(const f4 *)(tb + j * 20 + 4 * g);
+    dJ = tb[j * 20 + j];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dI[v] = tb[(4 * g + v) * 20 + 4 * g + v];
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A[v] = 0.5f * (A[v] + At[v]);
+    // certificate
+    bool bad = false;
+    float gr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const bool off = (4 * g + v) != j;
+      bad |= off && (dI[v] > 1.f || dJ > 1.f) && fabsf(A[v]) > thr;
+      gr[v] = (off && !(dJ > 1.f)) ? fabsf(A[v]) : 0.f;
+    }
+    if (!__any(bad)) {
+      bool gbad = false;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float rs = row_sum16(gr[v]);
+        gbad |= !(dI[v] > 1.f) && dI[v] + rs > 1.f + kGershSlack;
+      }
+      if (!__any(gbad)) {
+        if (!rough) {
+          ok = true;
+          break;
+        }
+        // large steps were taken: restore orthonormality exactly and re-derive A from G
+        f4 Vc;
+        orthonormalise(Vc);
+        A = mtn(Vc, mtn(G, Vc));
+        rough = false;
+        continue;
+      }
+    }
+    if (steps == kSteps) break;
+    // one damped simultaneous rotation step
+    f4 K;
+    float kf2 = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * g + v;
+      const float den = dJ - dI[v];
+      const float sg = (den > 0.f || (den == 0.f && i < j)) ? 1.f : -1.f;
+      const float q = fabsf(den) + sqrtf(fmaf(den, den, 4.f * A[v] * A[v]));
+      const float t = (i != j && q > 0.f) ? __fdividef(2.f * A[v] * sg, q) : 0.f;
+      K[v] = t;
+      kf2 = fmaf(t, t, kf2);
+    }
+    kf2 = wave_sum(kf2);
+    if (kf2 > kStepCap * kStepCap) {
+      const float sc = kStepCap * rsqrtf(kf2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) K[v] *= sc;
+      kf2 = kStepCap * kStepCap;
+    }
+    rough |= kf2 > kRoughNorm2;
+    const f4 KK = mtn(K, K);  // K^T K = -K^2
+    f4 J, Jt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float id = (4 * g + v) == j ? 1.f : 0.f;
+      const float h = -0.5f * KK[v];
+      J[v] = id + K[v] + h;
+      Jt[v] = id - K[v] + h;
+    }
+    if (kf2 > kQuarticNorm2) {
+      f4 K2;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) K2[v] = -KK[v];
+      const f4 K4 = mtn(K2, K2);   // (K^2)^T K^2 = K^4
+      const f4 JK4 = mtn(Jt, K4);  // J K^4
+#pragma unroll
+      for (int v = 0; v < 4; ++v) J[v] = fmaf(-0.125f, JK4[v], J[v]);
+    }
+    A = mtn(J, mtn(A, J));  // J^T (A J), A symmetric
+    Vt = mtn(J, Vt);        // (V J)^T
+    ++steps;
+  }
+
+  float *Gl = a.G + (size_t)l * 256 + (4 * g) * 16 + j;
+  if (ok) {
+    f4 Vc;
+    orthonormalise(Vc);
+    f4 H;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) H[v] = (dI[v] > 1.f ? 1.f - rsqrtf(dI[v]) : 0.f) * Vt[v];
+    const f4 S = mtn(Vt, H);  // V diag(h) V^T
+    float *Wl = a.W + (size_t)l * 256 + (4 * g) * 16 + j;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Wl[16 * v] = ((4 * g + v) == j ? 1.f : 0.f) - S[v];
+  } else {
+    f4 Vc;
+    orthonormalise(Vc);
+    A = mtn(Vc, mtn(G, Vc));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Gl[16 * v] = A[v];
+  }
+  *(f4 *)(Vl + j * 16 + 4 * g) = Vt;
+  if (lane == 0) a.eflag[l] = steps | (ok ? 0 : 256);
+}
+
 // ---------------------------------------------------------------- Gram on MFMA
 
 // One wavefront per block. In MFMA step (t, s) lane (r = lane&15, kk = lane>>4) supplies
@@ -45,7 +250,7 @@ __device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
 __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
   // per-wavefront transpose buffer for one 16 x 16 tile, row stride 20 floats (conflict-free
   // for both the 4-byte writes and the 16-byte reads)
-  __shared__ float tbuf[4][16 * 20];
+  __shared__ __align__(16) float tbuf[4][16 * 20];
   if (a.sc && a.sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long l = (long long)blockIdx.x * 4 + wave;
@@ -81,6 +286,10 @@ __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
     acc = mfma4(y2, y2, acc);
     acc = mfma4(y3, y3, acc);
     ycur = ynext;
+  }
+  if (a.V && a.eflag) {
+    block_eigen_mfma(a, l, acc, tb);
+    return;
   }
   if (a.V) {
     // Warm start. With M and N held in the result layout (lane j + 16g, register
@@ -139,7 +348,6 @@ __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
 // Output: W = I - sum_k (1 - min(1, lambda_k^{-1/2})) v_k v_k^T, row-major.
 
 constexpr int kMaxSweeps = 16;
-constexpr float kJacobiTol = 1e-7f;
 
 __host__ __device__ constexpr int tri(int p, int q) { return p * 16 - p * (p - 1) / 2 + (q - p); }
 
@@ -188,8 +396,33 @@ __device__ __forceinline__ void jsweep(float (&A)[136], float (&V)[256], float t
 __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
   if (a.sc && a.sc->done) return;
   long long blk = (long long)blockIdx.x * 64 + threadIdx.x;
-  const bool valid = blk < a.nblk;
-  if (!valid) blk = a.nblk - 1;  // duplicate a real block so every lane runs the same sweeps
+  bool valid = blk < a.nblk;
+  if (a.eflag) {
+    // Only the blocks k_gram could not certify. Wavefront statistics first (one atomic each).
+    const int f = valid ? a.eflag[blk] : 0;
+    const bool mine = valid && (f & 256);
+    int st = f & 255, mx = st, nv = valid ? 1 : 0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      st += __shfl_xor(st, m);
+      mx = max(mx, __shfl_xor(mx, m));
+      nv += __shfl_xor(nv, m);
+    }
+    const unsigned long long fb = __ballot(mine);
+    if (a.sc && threadIdx.x == 0) {
+      atomicAdd(&a.sc->step_sum, (unsigned long long)st);
+      atomicAdd(&a.sc->step_blocks, (unsigned long long)nv);
+      atomicMax(&a.sc->max_steps, mx);
+      if (fb) atomicAdd(&a.sc->fallback_blocks, (unsigned long long)__popcll(fb));
+    }
+    if (!fb) return;
+    // lanes without a flagged block mirror the first flagged one (run the same sweeps, store nothing)
+    const long long first = __shfl(blk, __ffsll((long long)fb) - 1);
+    if (!mine) blk = first;
+    valid = mine;
+  } else if (!valid) {
+    blk = a.nblk - 1;  // duplicate a real block so every lane runs the same sweeps
+  }
   // The Gram matrix from k_gram is symmetric; read its upper triangle.
   const float *Gl = a.G + (size_t)blk * 256;
   float A[136], V[256];

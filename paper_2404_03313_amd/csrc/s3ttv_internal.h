@@ -37,7 +37,11 @@ struct DevScalars {
   double rel_tol;
   unsigned long long sweep_sum;   // Jacobi sweeps summed over wavefronts
   unsigned long long sweep_waves; // wavefronts counted in sweep_sum
-  int32_t pad[2];
+  unsigned long long step_sum;    // MFMA rotation steps summed over blocks (warm iterations)
+  unsigned long long step_blocks; // blocks counted in step_sum
+  unsigned long long fallback_blocks;  // warm-iteration blocks handed to the per-lane Jacobi
+  int32_t max_steps;              // largest rotation step count of one block
+  int32_t pad;
 };
 
 // l1 histograms: per ball, per level: counts (u32) and significand sums (u64).
@@ -63,6 +67,7 @@ struct Plan {
   int red_blocks;
   // workspace carve
   float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *zpart, *Z;
+  int *eflag;          // per block: rotation steps | 256 if the per-lane Jacobi must finish it
   double *red_primal;  // red_blocks * 4
   double *red_dual;    // red_blocks
   DevScalars *sc;
@@ -108,6 +113,11 @@ struct BlockArgs {
   float *Y;                // apply layout, nblk * 16 * ncol floats
   float *G, *W;            // nblk * 256 floats each
   float *V;                // nblk * 256: eigenvectors of the previous step (warm start) or null
+  // Eigen mode. eflag == nullptr: k_gram writes the (rotated) Gram matrix and k_eig solves
+  // every block. eflag != nullptr (requires V): k_gram diagonalises each block itself on MFMA
+  // starting from V, writes W and V, and flags the blocks it cannot certify; k_eig solves
+  // only the flagged ones.
+  int *eflag;
   // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
   int TA, TB, ntA, ntB, extA, extB, waves;
   size_t lds;

@@ -43,6 +43,8 @@ class Stats(ctypes.Structure):
                 ("rel_change", ctypes.c_double), ("l1_s", ctypes.c_double),
                 ("l1_t", ctypes.c_double), ("fid", ctypes.c_double), ("dv_t", ctypes.c_double),
                 ("eig_max_sweeps", ctypes.c_int32), ("eig_avg_sweeps", ctypes.c_float),
+                ("eig_avg_steps", ctypes.c_float), ("eig_max_steps", ctypes.c_int32),
+                ("eig_fallback_blocks", ctypes.c_int64),
                 ("ms", ctypes.c_float),
                 ("kernel_ms", ctypes.c_float * 9), ("kernel_calls", ctypes.c_int32 * 9)]
 
@@ -174,7 +176,9 @@ class Solver:
         _check(rc, "s3ttv_solve", allow=(OK, NOT_CONVERGED))
         stats = dict(iters=st.iters, converged=bool(st.converged), rel_change=st.rel_change,
                      l1_s=st.l1_s, l1_t=st.l1_t, fid=st.fid, dv_t=st.dv_t,
-                     eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps, ms=st.ms,
+                     eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps,
+                     eig_avg_steps=st.eig_avg_steps, eig_max_steps=st.eig_max_steps,
+                     eig_fallback_blocks=st.eig_fallback_blocks, ms=st.ms,
                      kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(9)},
                      kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i] for i in range(9)},
                      code=rc)

@@ -41,7 +41,8 @@ def _parity(device, d, k, iters, tol=1e-4, **kw):
     r = oracle.solve(d["v64"], k1, k2, max_iter=iters, **d["radii"], **kw_o)
     errs = {name: rel_l2(_np(g), r[name]) for name, g in (("u", u), ("s", s), ("t", t))}
     _say("rel L2 vs oracle:", errs, "gpu iters", st["iters"], "oracle iters", r["stats"]["iters"],
-         "max sweeps", st["eig_max_sweeps"])
+         "max sweeps", st["eig_max_sweeps"], "avg steps", st["eig_avg_steps"],
+         "fallback blocks", st["eig_fallback_blocks"])
     for name, e in errs.items():
         assert e <= tol, (name, e)
     return u, s, t, st, r
@@ -132,4 +133,5 @@ def test_large_shape_first_iterations_and_invariants(device):
     assert st["l1_s"] <= d["radii"]["alpha"] * (1 + 1e-5)
     assert st["l1_t"] <= d["radii"]["beta"] * (1 + 1e-5)
     assert np.isfinite(st["fid"]) and np.isfinite(st["dv_t"])
-    _say("stats", {k: st[k] for k in ("iters", "fid", "dv_t", "eig_max_sweeps", "ms")})
+    _say("stats", {k: st[k] for k in ("iters", "fid", "dv_t", "eig_max_sweeps", "eig_avg_steps",
+                                      "eig_max_steps", "eig_fallback_blocks", "ms")})
