@@ -105,12 +105,20 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.W = cv.take<float>((size_t)pl.P * 256);
   pl.V = cv.take<float>((size_t)pl.P * 256);
   pl.eflag = cv.take<int>((size_t)pl.P);
+  pl.estat = cv.take<int>((size_t)(pl.P + 63) / 64 * 4);
+  pl.l1part = cv.take<unsigned long long>((size_t)2 * l1_part_blocks(pl.N) * kL1Bins2);
   pl.Y = cv.take<float>((size_t)pl.P * kRows * pl.ncol);
   pl.red_primal = cv.take<double>((size_t)pl.red_blocks * 4);
   pl.red_dual = cv.take<double>((size_t)(pl.red_blocks > 4 ? pl.red_blocks : 4));
   pl.sc = cv.take<DevScalars>(1);
   pl.hist = cv.take<L1Hist>(1);
   pl.bytes = align_up(cv.off);
+}
+
+// Operator l1 projection: scalars, histograms and the level-2 partial histograms.
+size_t l1_workspace_bytes(long long n) {
+  return align_up(sizeof(DevScalars)) + align_up(sizeof(L1Hist)) +
+         align_up((size_t)l1_part_blocks(n) * kL1Bins2 * sizeof(unsigned long long));
 }
 
 BlockArgs block_args(const Plan &pl) {
@@ -314,6 +322,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
   const BlockArgs ba = block_args(pl);
   BlockArgs bw = ba;
   bw.eflag = pl.eflag;
+  bw.estat = pl.estat;
   const int check = params->check_every > 0 ? params->check_every : 16;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
@@ -324,7 +333,8 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     const int c = it & 1, n = c ^ 1;
     TIMED(S3TTV_K_PRIMAL, launch_primal(pl, pl.u[c], pl.u[n], pl.t[c], st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 1, pl.alpha, pl.beta, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 2, pl.hist, pl.sc, st));
+    TIMED(S3TTV_K_L1, launch_l1_hist_part(pl.xs, pl.xt, pl.N, 2, pl.l1part, pl.sc, st));
+    TIMED(S3TTV_K_L1, launch_l1_part_reduce(2, pl.N, pl.l1part, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 2, pl.alpha, pl.beta, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
@@ -335,7 +345,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
     TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
     TIMED(S3TTV_K_DUAL, launch_dual(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
-    TIMED(S3TTV_K_FINAL, launch_finalize(pl, st));
+    TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
     ++launched;
     if (params->rel_tol > 0 && (it + 1) % check == 0 && it + 1 < params->max_iter) {
       int32_t done = 0;
@@ -418,7 +428,8 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
     }
     case S3TTV_OP_L1:
       if (n < 1) return S3TTV_EINVAL;
-      *bytes = align_up(sizeof(DevScalars)) + align_up(sizeof(L1Hist));
+      if (n >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
+      *bytes = l1_workspace_bytes(n);
       return S3TTV_OK;
     default:
       return S3TTV_EINVAL;
@@ -543,11 +554,12 @@ int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out
                             void *workspace, size_t workspace_bytes, void *stream) {
   if (n < 1 || !x || !out || !workspace || !(radius > 0 && isfinite(radius))) return S3TTV_EINVAL;
   if (n >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
-  const size_t need = align_up(sizeof(DevScalars)) + align_up(sizeof(L1Hist));
+  const size_t need = l1_workspace_bytes(n);
   if (workspace_bytes < need) return S3TTV_EWORKSPACE;
   Carver cv{(char *)workspace, 0, false};
   DevScalars *sc = cv.take<DevScalars>(1);
   L1Hist *h = cv.take<L1Hist>(1);
+  unsigned long long *part = cv.take<unsigned long long>((size_t)l1_part_blocks(n) * kL1Bins2);
   hipStream_t st = (hipStream_t)stream;
   Plan tmp;
   memset(&tmp, 0, sizeof(tmp));
@@ -555,7 +567,12 @@ int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out
   CK(launch_init_scalars(tmp, 0.0, st));
   CK(launch_zero_bytes(h, sizeof(L1Hist), st));
   for (int level = 1; level <= 3; ++level) {
-    CK(launch_l1_hist(x, nullptr, n, 1, level, h, sc, st));
+    if (level == 2) {
+      CK(launch_l1_hist_part(x, nullptr, n, 1, part, sc, st));
+      CK(launch_l1_part_reduce(1, n, part, h, sc, st));
+    } else {
+      CK(launch_l1_hist(x, nullptr, n, 1, level, h, sc, st));
+    }
     CK(launch_l1_select(1, level, radius, radius, h, sc, st));
   }
   CK(launch_l1_apply(x, out, n, 0, sc, st));

@@ -398,7 +398,8 @@ __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
   long long blk = (long long)blockIdx.x * 64 + threadIdx.x;
   bool valid = blk < a.nblk;
   if (a.eflag) {
-    // Only the blocks k_gram could not certify. Wavefront statistics first (one atomic each).
+    // Only the blocks k_gram could not certify. First the workgroup's statistics (summed
+    // later by the finalize kernel, no atomics).
     const int f = valid ? a.eflag[blk] : 0;
     const bool mine = valid && (f & 256);
     int st = f & 255, mx = st, nv = valid ? 1 : 0;
@@ -409,11 +410,13 @@ __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
       nv += __shfl_xor(nv, m);
     }
     const unsigned long long fb = __ballot(mine);
-    if (a.sc && threadIdx.x == 0) {
-      atomicAdd(&a.sc->step_sum, (unsigned long long)st);
-      atomicAdd(&a.sc->step_blocks, (unsigned long long)nv);
-      atomicMax(&a.sc->max_steps, mx);
-      if (fb) atomicAdd(&a.sc->fallback_blocks, (unsigned long long)__popcll(fb));
+    if (threadIdx.x == 0) {
+      int4 r;
+      r.x = st;
+      r.y = mx;
+      r.z = __popcll(fb);
+      r.w = nv;
+      *(int4 *)(a.estat + 4 * (size_t)blockIdx.x) = r;
     }
     if (!fb) return;
     // lanes without a flagged block mirror the first flagged one (run the same sweeps, store nothing)

@@ -30,7 +30,7 @@ __device__ inline int level_bins(int level) {
 __device__ inline int parent_shift(int level) { return level == 2 ? kL1Shift1 : kL1Shift2; }
 
 __global__ __launch_bounds__(kNT) void k_l1_hist(const float *x0, const float *x1, long long n,
-                                                 int nballs, int level, L1Hist *hist,
+                                                 int nballs, int level, int vec, L1Hist *hist,
                                                  DevScalars *sc) {
   __shared__ unsigned long long h[2][kL1MaxBins];
   if (sc->done) return;
@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kNT) void k_l1_hist(const float *x0, const float *x
     const uint32_t sig = ex ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
     atomicAdd(&h[k][(bits >> shift) & mask], (1ull << 40) | (unsigned long long)sig);
   };
-  // four elements per thread per trip (16-byte loads), scalar tail
-  const long long n4 = n >> 2;
+  // four elements per thread per trip (16-byte loads when aligned), scalar tail
+  const long long n4 = vec ? n >> 2 : 0;
   for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < n4;
        e += (long long)gridDim.x * kNT) {
 #pragma unroll
@@ -85,6 +85,91 @@ __global__ __launch_bounds__(kNT) void k_l1_hist(const float *x0, const float *x
         atomicAdd(&gs[bi], v & ((1ull << 40) - 1));
       }
     }
+  }
+}
+
+// Level 2 without global atomics. Each workgroup histograms kL1PartElems elements per ball in
+// LDS (count << 40 | significand sum: the significand sum of kL1PartElems 24-bit values fits
+// in 40 bits) and writes its whole 2048-bin histogram to part[ball][workgroup][bin];
+// k_l1_part_reduce then sums the partials per bin into the level-2 histogram. Every thread
+// issues its kPartLoads 16-byte loads per ball before it touches the histogram.
+constexpr int kPT = 1024;
+constexpr int kPartLoads = kL1PartElems / (4 * kPT);  // float4 per thread per ball
+
+__global__ __launch_bounds__(kPT) void k_l1_hist_part(const float *x0, const float *x1,
+                                                      long long n, int nballs, int vec,
+                                                      unsigned long long *part, DevScalars *sc) {
+  __shared__ unsigned long long h[2][kL1Bins2];
+  if (sc->done) return;
+  const int ps = parent_shift(2);
+  const bool use[2] = {sc->active[0] != 0, nballs > 1 && sc->active[1] != 0};
+  if (!use[0] && !use[1]) return;
+  const uint32_t pref[2] = {sc->prefix[0] >> ps, sc->prefix[1] >> ps};
+  for (int k = threadIdx.x; k < 2 * kL1Bins2; k += kPT) (&h[0][0])[k] = 0ull;
+  __syncthreads();
+  const long long beg = (long long)blockIdx.x * kL1PartElems;
+  const long long end = beg + kL1PartElems < n ? beg + kL1PartElems : n;
+  auto add = [&](int k, float xv) {
+    const uint32_t bits = __float_as_uint(xv) & 0x7fffffffu;
+    if ((bits >> ps) != pref[k]) return;
+    const uint32_t ex = bits >> 23;
+    const uint32_t sig = ex ? ((bits & 0x7fffffu) | 0x800000u) : (bits & 0x7fffffu);
+    atomicAdd(&h[k][(bits >> kL1Shift2) & (kL1Bins2 - 1)], (1ull << 40) | (unsigned long long)sig);
+  };
+  for (int k = 0; k < 2; ++k) {
+    if (!use[k]) continue;
+    const float *x = k == 0 ? x0 : x1;
+    if (vec && end - beg == kL1PartElems) {
+      const float4 *x4 = reinterpret_cast<const float4 *>(x + beg);
+      float4 r[kPartLoads];
+#pragma unroll
+      for (int j = 0; j < kPartLoads; ++j) r[j] = x4[j * kPT + threadIdx.x];
+#pragma unroll
+      for (int j = 0; j < kPartLoads; ++j) {
+        add(k, r[j].x);
+        add(k, r[j].y);
+        add(k, r[j].z);
+        add(k, r[j].w);
+      }
+    } else {
+      for (long long e = beg + threadIdx.x; e < end; e += kPT) add(k, x[e]);
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < 2; ++k) {
+    if (!use[k]) continue;
+    unsigned long long *dst = part + ((size_t)k * gridDim.x + blockIdx.x) * kL1Bins2;
+    for (int bi = threadIdx.x; bi < kL1Bins2; bi += kPT) dst[bi] = h[k][bi];
+  }
+}
+
+// Sums the level-2 partials: workgroup = 32 bins x 32 row groups; writes hist level 2.
+__global__ __launch_bounds__(kPT) void k_l1_part_reduce(const unsigned long long *part, int nparts,
+                                                        L1Hist *hist, DevScalars *sc) {
+  __shared__ unsigned long long sc_[32][33], ss_[32][33];
+  if (sc->done) return;
+  const int per_ball = kL1Bins2 / 32;
+  const int ball = blockIdx.x / per_ball;
+  if (!sc->active[ball]) return;
+  const int lb = threadIdx.x & 31, rg = threadIdx.x >> 5;
+  const int b = (blockIdx.x - ball * per_ball) * 32 + lb;
+  const unsigned long long *src = part + (size_t)ball * nparts * kL1Bins2 + b;
+  unsigned long long c = 0, g = 0;
+  for (int w = rg; w < nparts; w += 32) {
+    const unsigned long long v = src[(size_t)w * kL1Bins2];
+    c += v >> 40;
+    g += v & ((1ull << 40) - 1);
+  }
+  sc_[rg][lb] = c;
+  ss_[rg][lb] = g;
+  __syncthreads();
+  if (rg == 0) {
+    for (int r = 1; r < 32; ++r) {
+      c += sc_[r][lb];
+      g += ss_[r][lb];
+    }
+    hist->cnt[ball][1][b] = (uint32_t)c;
+    hist->sig[ball][1][b] = g;
   }
 }
 
@@ -225,8 +310,32 @@ int l1_grid(long long n) {
 
 hipError_t launch_l1_hist(const float *x0, const float *x1, long long n, int nballs, int level,
                           L1Hist *hist, DevScalars *sc, hipStream_t st) {
-  hipLaunchKernelGGL(k_l1_hist, dim3(l1_grid(n)), dim3(kNT), 0, st, x0, x1 ? x1 : x0, n, nballs,
-                     level, hist, sc);
+  if (!x1) x1 = x0;
+  const int vec = ((reinterpret_cast<uintptr_t>(x0) | reinterpret_cast<uintptr_t>(x1)) & 15) == 0;
+  hipLaunchKernelGGL(k_l1_hist, dim3(l1_grid(n)), dim3(kNT), 0, st, x0, x1, n, nballs, level, vec,
+                     hist, sc);
+  return hipGetLastError();
+}
+
+int l1_part_blocks(long long n) {
+  long long g = (n + kL1PartElems - 1) / kL1PartElems;
+  return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_l1_hist_part(const float *x0, const float *x1, long long n, int nballs,
+                               unsigned long long *part, DevScalars *sc, hipStream_t st) {
+  if (!x1) x1 = x0;
+  // 16-byte loads for the full chunks when both vectors are 16-byte aligned
+  const int vec = ((reinterpret_cast<uintptr_t>(x0) | reinterpret_cast<uintptr_t>(x1)) & 15) == 0;
+  hipLaunchKernelGGL(k_l1_hist_part, dim3(l1_part_blocks(n)), dim3(kPT), 0, st, x0, x1, n,
+                     nballs, vec, part, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_l1_part_reduce(int nballs, long long n, const unsigned long long *part,
+                                 L1Hist *hist, DevScalars *sc, hipStream_t st) {
+  hipLaunchKernelGGL(k_l1_part_reduce, dim3(nballs * (kL1Bins2 / 32)), dim3(kPT), 0, st, part,
+                     l1_part_blocks(n), hist, sc);
   return hipGetLastError();
 }
 

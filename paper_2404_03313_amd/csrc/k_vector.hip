@@ -33,6 +33,18 @@ __device__ inline double block_sum(double v, double *sh) {
   return r;
 }
 
+__device__ inline double block_max(double v, double *sh) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) r = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  return r;
+}
+
 __device__ inline float box(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
 // Soft threshold with an FP64 threshold; the difference is formed in double and rounded once.
@@ -301,6 +313,8 @@ struct FinalArgs {
   int nblk;
   const double *red_primal, *red_dual;
   double eps_g3;  // eps * gamma_y3
+  const int *estat;  // per-workgroup eigen statistics of this iteration (4 ints), or null
+  long long nstat;
   DevScalars *sc;
 };
 
@@ -318,8 +332,29 @@ __global__ __launch_bounds__(kNT) void k_finalize(FinalArgs a) {
   u2 = block_sum(u2, sh);
   bad = block_sum(bad, sh);
   w2 = block_sum(w2, sh);
+  // eigen-solve statistics: rotation steps per block and blocks left to the per-lane Jacobi
+  double ssum = 0, nfb = 0, smax = 0, nblk = 0;
+  if (a.estat) {
+    for (long long k = threadIdx.x; k < a.nstat; k += kNT) {
+      const int4 r = *(const int4 *)(a.estat + 4 * k);
+      ssum += (double)r.x;
+      smax = fmax(smax, (double)r.y);
+      nfb += (double)r.z;
+      nblk += (double)r.w;
+    }
+    ssum = block_sum(ssum, sh);
+    nfb = block_sum(nfb, sh);
+    nblk = block_sum(nblk, sh);
+    smax = block_max(smax, sh);
+  }
   if (threadIdx.x == 0) {
     DevScalars *sc = a.sc;
+    if (a.estat) {
+      sc->step_sum += (unsigned long long)ssum;
+      sc->step_blocks += (unsigned long long)nblk;
+      sc->fallback_blocks += (unsigned long long)nfb;
+      if ((int)smax > sc->max_steps) sc->max_steps = (int)smax;
+    }
     const double wn = sqrt(w2);
     sc->kappa = wn > a.eps_g3 ? 1.0 - a.eps_g3 / wn : 0.0;
     sc->wnorm2 = w2;
@@ -530,10 +565,12 @@ hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, c
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Plan &pl, hipStream_t st) {
+hipError_t launch_finalize(const Plan &pl, bool eig_stats, hipStream_t st) {
   FinalArgs a;
   a.nblk = pl.red_blocks; a.red_primal = pl.red_primal; a.red_dual = pl.red_dual;
   a.eps_g3 = pl.eps * (double)pl.g_y3; a.sc = pl.sc;
+  a.estat = eig_stats ? pl.estat : nullptr;
+  a.nstat = (pl.P + 63) / 64;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }

@@ -18,6 +18,9 @@ constexpr int kL1Bins1 = 2048, kL1Shift1 = 20;
 constexpr int kL1Bins2 = 2048, kL1Shift2 = 9;
 constexpr int kL1Bins3 = 512, kL1Shift3 = 0;
 constexpr int kL1MaxBins = 2048;
+// Level 2 is histogrammed per workgroup over at most this many elements per ball, so the
+// packed LDS bins (count << 40 | significand sum) cannot overflow.
+constexpr int kL1PartElems = 32768;
 
 // Device-resident scalars of one solve.
 struct DevScalars {
@@ -68,6 +71,8 @@ struct Plan {
   // workspace carve
   float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *zpart, *Z;
   int *eflag;          // per block: rotation steps | 256 if the per-lane Jacobi must finish it
+  int *estat;          // per k_eig workgroup (64 blocks): step sum, max steps, fallbacks, blocks
+  unsigned long long *l1part;  // level-2 l1 partial histograms: 2 x l1_part_blocks(N) x 2048
   double *red_primal;  // red_blocks * 4
   double *red_dual;    // red_blocks
   DevScalars *sc;
@@ -94,13 +99,21 @@ hipError_t launch_grad(const Plan &pl, const float *a, const float *b, float ca,
 hipError_t launch_zsum(const Plan &pl, hipStream_t st);
 hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, const float *t_cur,
                        float *t_new, const float *v, hipStream_t st);
-hipError_t launch_finalize(const Plan &pl, hipStream_t st);
+// eig_stats: also fold this iteration's eigen-solve statistics (written by k_eig) in.
+hipError_t launch_finalize(const Plan &pl, bool eig_stats, hipStream_t st);
 
 // l1 threshold selection for the two balls (ball count 1 or 2): level = 1, 2, 3.
 hipError_t launch_l1_hist(const float *x0, const float *x1, long long n, int nballs, int level,
                           L1Hist *hist, DevScalars *sc, hipStream_t st);
 hipError_t launch_l1_select(int nballs, int level, double r0, double r1, L1Hist *hist,
                             DevScalars *sc, hipStream_t st);
+// Level 2 in two passes: per-workgroup partial histograms (l1_part_blocks(n) per ball, 2048
+// u64 each), then their per-bin sum into hist level 2.
+int l1_part_blocks(long long n);
+hipError_t launch_l1_hist_part(const float *x0, const float *x1, long long n, int nballs,
+                               unsigned long long *part, DevScalars *sc, hipStream_t st);
+hipError_t launch_l1_part_reduce(int nballs, long long n, const unsigned long long *part,
+                                 L1Hist *hist, DevScalars *sc, hipStream_t st);
 hipError_t launch_l1_apply(const float *x, float *out, long long n, int ball, DevScalars *sc,
                            hipStream_t st);
 
@@ -118,6 +131,7 @@ struct BlockArgs {
   // starting from V, writes W and V, and flags the blocks it cannot certify; k_eig solves
   // only the flagged ones.
   int *eflag;
+  int *estat;              // with eflag: per-workgroup eigen statistics written by k_eig
   // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
   int TA, TB, ntA, ntB, extA, extB, waves;
   size_t lds;

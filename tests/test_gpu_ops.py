@@ -121,7 +121,8 @@ def test_dual_blocks_match_oracle(device, shape, k):
     assert np.abs(_np(zh) - wzh).max() < 1e-4 * zs
 
 
-L1_CASES = ["normal_large", "ties", "inside", "single", "zeros_denormals", "spiky", "c2_size"]
+L1_CASES = ["normal_large", "ties", "inside", "single", "zeros_denormals", "spiky", "c2_size",
+            "one_bin", "misaligned"]
 
 
 @pytest.mark.parametrize("case", L1_CASES)
@@ -147,12 +148,26 @@ def test_l1_projection_matches_oracle(device, case):
         x = rng.normal(size=200000) * 1e-3
         x[rng.choice(x.size, 300, replace=False)] = rng.choice([-1, 1], 300) * rng.uniform(0.5, 5, 300)
         r = 0.7 * np.abs(x).sum()
+    elif case == "misaligned":
+        # passed as a view 4 bytes into its allocation (no 16-byte alignment)
+        x = rng.normal(size=300_001) * 0.3
+        r = 0.2 * np.abs(x).sum()
+    elif case == "one_bin":
+        # every |x| in [0.5, 0.55): one level-1 bin, so levels 2-3 see all elements
+        x = 0.5 * (1 + 0.1 * rng.uniform(size=1 << 20)) * rng.choice([-1, 1], 1 << 20)
+        r = 0.3 * np.abs(x).sum()
     else:
         x = rng.normal(size=256 * 256 * 128) * 0.05
         x[rng.choice(x.size, 400000, replace=False)] += rng.choice([-0.7, 0.7], 400000)
         r = 0.95 * 0.05 * x.size / 2
     x32 = x.astype(np.float32)
-    got, tau = nt.op_l1_project(_t(x32, device), r)
+    if case == "misaligned":
+        buf = _t(np.concatenate([[0.0], x32]), device)
+        xin = buf[1:]
+        assert xin.data_ptr() % 16 != 0
+    else:
+        xin = _t(x32, device)
+    got, tau = nt.op_l1_project(xin, r)
     want, wtau = oracle.proj_l1(x32.astype(np.float64), r)
     if wtau == 0:
         assert tau == 0
