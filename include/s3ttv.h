@@ -68,7 +68,13 @@ typedef struct {
  *  check_every: iterations between host checks of the stop flag (<= 0 means 16). The
  *    iterate returned is always the one at which the rule fired.
  *  timing_mask: bit c set => time every launch of kernel class c with HIP events and
- *    report the totals in s3ttv_stats (classes: see S3TTV_K_*). 0 for no timing. */
+ *    report the totals in s3ttv_stats (classes: see S3TTV_K_*). 0 for no timing.
+ *  eig_max_steps: from the second iteration on, each block's 16 x 16 eigenproblem is solved
+ *    by at most this many simultaneous rotation steps on MFMA, warm started from the previous
+ *    iteration's eigenbasis; blocks not certified by then are finished by a per-lane cyclic
+ *    Jacobi. 0 selects the default (24); a negative value sends every block not already
+ *    certified by the warm start to the Jacobi. The result does not depend on it beyond
+ *    rounding; it only moves work between the two solvers. At most 255. */
 typedef struct {
   double eps, alpha, beta;
   double mu_min, mu_max;
@@ -77,6 +83,7 @@ typedef struct {
   double rel_tol;
   int32_t check_every;
   int32_t timing_mask;
+  int32_t eig_max_steps;
 } s3ttv_params;
 
 /* Kernel classes for timing_mask / s3ttv_stats.kernel_ms. */
@@ -90,7 +97,9 @@ enum {
   S3TTV_K_ZSUM = 6,   /* sum of overlap-add partials (P_l^T of step 2) */
   S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) */
   S3TTV_K_FINAL = 8,  /* scalar reductions, stop rule */
-  S3TTV_K_COUNT = 9
+  S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks for iterations 2.. (N3 <= 128): steps 9-10
+                         (Gram, eigen-solve, clip) and the overlap-add on MFMA */
+  S3TTV_K_COUNT = 10
 };
 
 typedef struct {

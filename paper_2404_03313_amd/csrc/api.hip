@@ -22,6 +22,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 152 * 1024;
+constexpr int kDefaultEigSteps = 24;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -100,7 +101,7 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.xt = cv.take<float>(N);
   pl.gradf = cv.take<float>((size_t)pl.P * pl.ncol);
   pl.Z = cv.take<float>((size_t)pl.P * pl.ncol);
-  pl.zpart = cv.take<float>((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB * pl.ncol);
+  pl.zpart = cv.take<int>((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB * pl.ncol);
   pl.G = cv.take<float>((size_t)pl.P * 256);
   pl.W = cv.take<float>((size_t)pl.P * 256);
   pl.V = cv.take<float>((size_t)pl.P * 256);
@@ -184,6 +185,7 @@ bool valid_params(const s3ttv_params *pr) {
   if (!(isfinite(pr->mu_min) && isfinite(pr->mu_max) && pr->mu_min < pr->mu_max)) return false;
   if (pr->max_iter < 1) return false;
   if (!(pr->rel_tol >= 0 && isfinite(pr->rel_tol))) return false;
+  if (pr->eig_max_steps > 255) return false;
   return true;
 }
 
@@ -323,6 +325,9 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
   BlockArgs bw = ba;
   bw.eflag = pl.eflag;
   bw.estat = pl.estat;
+  bw.eig_steps = params->eig_max_steps == 0 ? kDefaultEigSteps
+                                            : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
+  const bool fused = fused_supported(bw) && fused_lds_bytes(bw) <= kMaxLds;
   const int check = params->check_every > 0 ? params->check_every : 16;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
@@ -339,10 +344,16 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_GRAD, launch_grad(pl, pl.u[n], pl.u[c], 2.f, -1.f, nullptr, st));
-    const BlockArgs &bk = it == 0 ? ba : bw;
-    TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
-    TIMED(S3TTV_K_EIG, launch_eig(bk, st));
-    TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
+    if (it > 0 && fused) {
+      TIMED(S3TTV_K_BLOCK, launch_block_fused(bw, st));
+      TIMED(S3TTV_K_EIG, launch_eig(bw, st));
+      TIMED(S3TTV_K_EIG, launch_fixup(bw, st));
+    } else {
+      const BlockArgs &bk = it == 0 ? ba : bw;
+      TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
+      TIMED(S3TTV_K_EIG, launch_eig(bk, st));
+      TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
+    }
     TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
     TIMED(S3TTV_K_DUAL, launch_dual(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
@@ -546,8 +557,10 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   CK(launch_zsum(pl, st));
   CK(launch_unpack_blocks(pl.Y, yout, pl.P, pl.K, 2 * pl.n3, pl.ncol, 1, pl.n3, pl.Bp, st));
   CK(launch_field_to_cubes(pl.Z, zv, zh, pl.P, pl.n3, pl.Bp, st));
+  int32_t bad = 0;
+  CK(hipMemcpyAsync(&bad, &pl.sc->nonfinite, sizeof(bad), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  return S3TTV_OK;
+  return bad ? S3TTV_ENONFINITE : S3TTV_OK;
 }
 
 int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out, double *tau,

@@ -46,6 +46,14 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A non-finite (or out-of-range) overlap-add value: flag the solve and stop it.
+__device__ inline void flag_nonfinite(DevScalars *sc, bool bad) {
+  if (__any(bad) && sc && (threadIdx.x & 63) == 0) {
+    atomicOr(&sc->nonfinite, 1);
+    atomicOr(&sc->done, 1);
+  }
+}
+
 // Sum over the 64 lanes; every lane receives the same (bitwise) value.
 __device__ inline float wave_sum(float x) {
 #pragma unroll
@@ -99,13 +107,15 @@ __device__ inline int row_pixel(const BlockArgs &a, long long l, int row) {
 // W = I - V diag((1 - A_ii^-1/2)_+) V^T; others (rare; cold starts) are left to k_eig with
 // A and V stored. V always leaves with one Newton-Schulz step applied.
 constexpr float kJacobiTol = 1e-7f;
-constexpr int kSteps = 24;
 constexpr float kStepCap = 0.5f;
 constexpr float kRoughNorm2 = 0.0225f;    // a step with ||K||_F > 0.15 forces the recompute
 constexpr float kQuarticNorm2 = 2e-4f;    // below this ||K^4||/8 is under FP32 rounding
 constexpr float kGershSlack = 1e-6f;
 
-__device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb) {
+// Returns true with W (D-form) for a certified block; otherwise stores A (into a.G) for k_eig.
+// Always stores the re-orthogonalised V and the block's flag.
+__device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb,
+                                           f4 &Wout) {
   const int lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   float *Vl = a.V + (size_t)l * 256;
@@ -175,7 +185,7 @@ __device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l
         continue;
       }
     }
-    if (steps == kSteps) break;
+    if (steps >= a.eig_steps) break;
     // one damped simultaneous rotation step
     f4 K;
     float kf2 = 0.f;
@@ -228,9 +238,8 @@ __device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l
 #pragma unroll
     for (int v = 0; v < 4; ++v) H[v] = (dI[v] > 1.f ? 1.f - rsqrtf(dI[v]) : 0.f) * Vt[v];
     const f4 S = mtn(Vt, H);  // V diag(h) V^T
-    float *Wl = a.W + (size_t)l * 256 + (4 * g) * 16 + j;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Wl[16 * v] = ((4 * g + v) == j ? 1.f : 0.f) - S[v];
+    for (int v = 0; v < 4; ++v) Wout[v] = ((4 * g + v) == j ? 1.f : 0.f) - S[v];
   } else {
     f4 Vc;
     orthonormalise(Vc);
@@ -240,6 +249,18 @@ __device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l
   }
   *(f4 *)(Vl + j * 16 + 4 * g) = Vt;
   if (lane == 0) a.eflag[l] = steps | (ok ? 0 : 256);
+  return ok;
+}
+
+// k_gram's warm mode: W of a certified block goes to a.W (row-major) for k_apply.
+__device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb) {
+  f4 W;
+  if (eigen_mfma(a, l, G, tb, W)) {
+    const int lane = threadIdx.x & 63;
+    float *Wl = a.W + (size_t)l * 256 + (4 * (lane >> 4)) * 16 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Wl[16 * v] = W[v];
+  }
 }
 
 // ---------------------------------------------------------------- Gram on MFMA
@@ -594,11 +615,187 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
     }
   }
   if (doz) {
-    float *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
+    int *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
+    bool bad = false;
     for (int t = wave; t < a.ntile; t += a.waves)
       for (int e = g; e < next; e += 4)
-        zp[(size_t)e * a.ncol + 16 * t + tc] = zacc[(size_t)e * zs + 16 * t + tc];
+        zp[(size_t)e * a.ncol + 16 * t + tc] = to_fixed(zacc[(size_t)e * zs + 16 * t + tc], bad);
+    flag_nonfinite(a.sc, bad);
   }
+}
+
+// ---------------------------------------------------------------- fused warm-iteration pass
+
+// Steps 9-10 and the overlap-add of the next step 2 in one pass over Y (warm iterations, at
+// most kFusedTiles column tiles, i.e. N3 <= 128). Workgroup = one TA x TB anchor tile with kFW
+// wavefronts; each wavefront takes the tile's anchors w, w + kFW, ... and keeps Y'_l (16 x ncol)
+// in registers in the apply layout: loads Y_l and T_l, forms the Gram matrix (column tiles
+// transposed in pairs through LDS into the Gram operand layout), diagonalises it on MFMA
+// (eigen_mfma), applies W_l on MFMA and stores Y+_l. The overlap-add goes to fixed-point LDS
+// accumulators with integer atomics, so the wavefronts never wait for each other and the sum
+// does not depend on their order. Blocks eigen_mfma cannot certify keep Y'_l in Y and are
+// finished by k_eig and k_fixup.
+constexpr int kFW = 8;
+constexpr int kFusedTiles = 16;
+
+template <int NT>
+__global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
+  extern __shared__ __align__(16) float zacc_f[];
+  int *zacc = reinterpret_cast<int *>(zacc_f);
+  if (a.sc && a.sc->done) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tc = lane & 15, g = lane >> 4;
+  const int ta = blockIdx.x / a.ntB, tb_ = blockIdx.x - (blockIdx.x / a.ntB) * a.ntB;
+  const int p0 = ta * a.TA, q0 = tb_ * a.TB;
+  const int np = min(a.TA, a.n1 - p0), nq = min(a.TB, a.n2 - q0);
+  const int next = a.extA * a.extB;
+  const int zs = a.ncol + 16;
+  // this wavefront's two transpose tiles (row stride 20 floats)
+  float *tbw = zacc_f + (size_t)next * zs + wave * 640;
+  for (int e = threadIdx.x; e < next * zs; e += kFW * 64) zacc[e] = 0;
+  // rows 4g+s of this lane: window offsets (fixed for the kernel); rows >= K are padding
+  int ar[4], cr[4];
+  float tw[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int row = 4 * g + s;
+    const bool rv = row < a.K;
+    ar[s] = rv ? row / a.k2 : 0;
+    cr[s] = rv ? row - (row / a.k2) * a.k2 : 0;
+    tw[s] = rv ? a.gY : 0.f;
+  }
+  __syncthreads();
+  bool bad = false;
+  const int nanch = np * nq;
+  for (int idx = wave; idx < nanch; idx += kFW) {
+    const int da = idx / nq, db = idx - (idx / nq) * nq;
+    const int p = p0 + da, q = q0 + db;
+    const long long lb = (long long)p * a.n2 + q;
+    const float *gp[4];
+    int zo[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int i = p + ar[s];
+      if (i >= a.n1) i -= a.n1;
+      int j = q + cr[s];
+      if (j >= a.n2) j -= a.n2;
+      gp[s] = a.gradf + (size_t)(i * a.n2 + j) * a.ncol + tc;  // padding rows: a real pixel, weight 0
+      zo[s] = ((da + ar[s]) * a.extB + (db + cr[s])) * zs + tc;
+    }
+    float *Yl = a.Y + (size_t)lb * kRows * a.ncol + lane * 4;
+    // all loads of the block first, then Y' = Y + g_Y T in the apply layout
+    f4 y[NT];
+    float T[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      y[t] = *(const f4 *)(Yl + t * 256);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) T[t][s] = gp[s][16 * t];
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) y[t][s] = fmaf(tw[s], T[t][s], y[t][s]);
+    // Gram: two column tiles per LDS round trip, transposed into the operand layout
+    // (lane r + 16kk: row r, columns 4kk..4kk+3 of the tile), accumulating Y' Y'^T
+    f4 G = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NT; t += 2) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        tbw[(4 * g + s) * 20 + tc] = y[t][s];
+        tbw[320 + (4 * g + s) * 20 + tc] = y[t + 1][s];
+      }
+      wave_lds_sync();
+      const f4 y0 = *(const f4 *)(tbw + tc * 20 + 4 * g);
+      const f4 y1 = *(const f4 *)(tbw + 320 + tc * 20 + 4 * g);
+      wave_lds_sync();
+      G = mfma4(y0[0], y0[0], G);
+      G = mfma4(y0[1], y0[1], G);
+      G = mfma4(y0[2], y0[2], G);
+      G = mfma4(y0[3], y0[3], G);
+      G = mfma4(y1[0], y1[0], G);
+      G = mfma4(y1[1], y1[1], G);
+      G = mfma4(y1[2], y1[2], G);
+      G = mfma4(y1[3], y1[3], G);
+    }
+    f4 W;
+    if (eigen_mfma(a, lb, G, tbw, W)) {
+      // Y+ = W Y' (W symmetric: its D-form register s of lane (r, g) is W[r][4g+s]),
+      // stored in place and added to the tile's overlap-add accumulators
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma4(W[0], y[t][0], acc);
+        acc = mfma4(W[1], y[t][1], acc);
+        acc = mfma4(W[2], y[t][2], acc);
+        acc = mfma4(W[3], y[t][3], acc);
+        *(f4 *)(Yl + t * 256) = acc;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed(acc[s], bad));
+      }
+    } else {
+      // left to k_eig / k_fixup: keep Y'
+#pragma unroll
+      for (int t = 0; t < NT; ++t) *(f4 *)(Yl + t * 256) = y[t];
+    }
+  }
+  flag_nonfinite(a.sc, bad);
+  __syncthreads();
+  int *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
+  for (int e = threadIdx.x; e < next * a.ncol; e += kFW * 64) {
+    const int px = e / a.ncol, c = e - px * a.ncol;
+    zp[e] = zacc[px * zs + c];
+  }
+}
+
+// Finishes the blocks k_block_fused left uncertified once k_eig has written their W: one
+// wavefront per anchor tile applies W to Y' and adds the result to the tile's fixed-point
+// overlap-add partial.
+__global__ __launch_bounds__(64) void k_fixup(BlockArgs a) {
+  if (a.sc && a.sc->done) return;
+  const int lane = threadIdx.x, tc = lane & 15, g = lane >> 4;
+  const int ta = blockIdx.x / a.ntB, tb_ = blockIdx.x - (blockIdx.x / a.ntB) * a.ntB;
+  const int p0 = ta * a.TA, q0 = tb_ * a.TB;
+  const int np = min(a.TA, a.n1 - p0), nq = min(a.TB, a.n2 - q0);
+  const int nanch = np * nq;  // <= 64
+  bool mine = false;
+  if (lane < nanch) {
+    const int da = lane / nq, db = lane - (lane / nq) * nq;
+    mine = (a.eflag[(long long)(p0 + da) * a.n2 + (q0 + db)] & 256) != 0;
+  }
+  unsigned long long todo = __ballot(mine);
+  if (!todo) return;
+  int *zp = a.zpart + (size_t)blockIdx.x * a.extA * a.extB * a.ncol;
+  bool bad = false;
+  while (todo) {
+    const int anc = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int da = anc / nq, db = anc - (anc / nq) * nq;
+    const long long lb = (long long)(p0 + da) * a.n2 + (q0 + db);
+    const f4 wv = *(const f4 *)(a.W + (size_t)lb * 256 + tc * 16 + 4 * g);
+    float *Yl = a.Y + (size_t)lb * kRows * a.ncol + lane * 4;
+    for (int t = 0; t < a.ntile; ++t) {
+      const f4 yp = *(const f4 *)(Yl + t * 256);
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma4(wv[0], yp[0], acc);
+      acc = mfma4(wv[1], yp[1], acc);
+      acc = mfma4(wv[2], yp[2], acc);
+      acc = mfma4(wv[3], yp[3], acc);
+      *(f4 *)(Yl + t * 256) = acc;
+      const int col = 16 * t + tc;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int row = 4 * g + s;
+        if (row < a.K) {
+          const int ar = row / a.k2, cr = row - (row / a.k2) * a.k2;
+          zp[(size_t)((da + ar) * a.extB + (db + cr)) * a.ncol + col] += to_fixed(acc[s], bad);
+        }
+      }
+    }
+  }
+  flag_nonfinite(a.sc, bad);
 }
 
 // ---------------------------------------------------------------- layout converters
@@ -666,6 +863,46 @@ hipError_t launch_gram(const BlockArgs &a, hipStream_t st) {
 hipError_t launch_eig(const BlockArgs &a, hipStream_t st) {
   const long long g = (a.nblk + 63) / 64;
   hipLaunchKernelGGL(k_eig, dim3((unsigned)g), dim3(64), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t fused_lds_bytes(const BlockArgs &a) {
+  return (size_t)a.extA * a.extB * (a.ncol + 16) * sizeof(float) + (size_t)kFW * 640 * sizeof(float);
+}
+
+bool fused_supported(const BlockArgs &a) {
+  // ntile = 2 ceil(N3/16) is even
+  return a.ntile <= kFusedTiles && a.ntile % 2 == 0 && a.TA * a.TB <= 64 && a.zpart && a.gradf &&
+         a.V && a.eflag;
+}
+
+template <int NT>
+hipError_t launch_fused_nt(const BlockArgs &a, size_t lds, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_block_fused<NT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_fused<NT>, dim3((unsigned)(a.ntA * a.ntB)), dim3(kFW * 64), lds, st,
+                     a);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st) {
+  const size_t lds = fused_lds_bytes(a);
+  switch (a.ntile) {
+    case 2: return launch_fused_nt<2>(a, lds, st);
+    case 4: return launch_fused_nt<4>(a, lds, st);
+    case 6: return launch_fused_nt<6>(a, lds, st);
+    case 8: return launch_fused_nt<8>(a, lds, st);
+    case 10: return launch_fused_nt<10>(a, lds, st);
+    case 12: return launch_fused_nt<12>(a, lds, st);
+    case 14: return launch_fused_nt<14>(a, lds, st);
+    case 16: return launch_fused_nt<16>(a, lds, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fixup(const BlockArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(k_fixup, dim3((unsigned)(a.ntA * a.ntB)), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 

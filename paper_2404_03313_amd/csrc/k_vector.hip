@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kNT) void k_grad_adj(int n1, int n2, int n3, int Bp
 
 struct ZsumArgs {
   int n1, n2, ncol, k1, k2, TA, TB, ntA, ntB, extA, extB;
-  const float *zpart;
+  const int *zpart;
   float *Z;
   DevScalars *sc;
 };
@@ -222,7 +222,8 @@ __device__ inline bool first_visit(int x, int off, int n, int TT) {
   return tt != anchor_tile(x, off - 1, n, TT) && tt != anchor_tile(x, 0, n, TT);
 }
 
-// Z[pix][c] = sum over slots of zpart[slot][c], four columns per thread.
+// Z[pix][c] = sum over slots of zpart[slot][c] (fixed point, summed exactly), four columns per
+// thread.
 __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
   if (a.sc && a.sc->done) return;
   const int c4n = a.ncol >> 2;
@@ -233,7 +234,7 @@ __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
     const int pix = (int)(idx / c4n);
     const int c4 = (int)(idx - (long long)pix * c4n);
     const int i = pix / a.n2, j = pix - (pix / a.n2) * a.n2;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int4 acc = make_int4(0, 0, 0, 0);
     for (int offr = 0; offr < a.k1; ++offr) {
       if (!first_visit(i, offr, a.n1, a.TA)) continue;
       const int ta = anchor_tile(i, offr, a.n1, a.TA);
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
           if (f0 < 0) f0 += a.n2;
           for (int ej = f0; ej < a.extB; ej += a.n2) {
             const size_t slot = ((size_t)ta * a.ntB + tb) * tile_stride + (size_t)ei * a.extB + ej;
-            const float4 v = reinterpret_cast<const float4 *>(a.zpart)[slot * c4n + c4];
+            const int4 v = reinterpret_cast<const int4 *>(a.zpart)[slot * c4n + c4];
             acc.x += v.x;
             acc.y += v.y;
             acc.z += v.z;
@@ -256,7 +257,9 @@ __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
         }
       }
     }
-    reinterpret_cast<float4 *>(a.Z)[(size_t)pix * c4n + c4] = acc;
+    reinterpret_cast<float4 *>(a.Z)[(size_t)pix * c4n + c4] =
+        make_float4((float)acc.x * kZInv, (float)acc.y * kZInv, (float)acc.z * kZInv,
+                    (float)acc.w * kZInv);
   }
 }
 

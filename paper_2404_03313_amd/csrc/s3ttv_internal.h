@@ -6,6 +6,20 @@
 
 namespace s3ttv {
 
+// Overlap-add partials (P_l^T of step 2) are accumulated in 32-bit fixed point with this
+// scale: every entry of Y+_l lies in [-1, 1] (its spectral norm is at most 1), so a pixel's
+// sum over at most 16 windows stays below 2^30. Integer addition is associative, so the
+// accumulation order (and thus the run) does not change the result.
+constexpr float kZScale = 67108864.f;        // 2^26
+constexpr float kZInv = 1.f / 67108864.f;
+constexpr float kZMax = 16.f;                // larger magnitudes (or NaN) are flagged
+
+// Fixed-point value of y; sets bad if |y| > kZMax or y is not a number.
+__device__ inline int to_fixed(float y, bool &bad) {
+  bad |= !(fabsf(y) <= kZMax);
+  return __float2int_rn(fminf(fmaxf(y, -kZMax), kZMax) * kZScale);
+}
+
 // Number of float32 columns per block tile handled by one 16x16 MFMA step group.
 constexpr int kTile = 16;
 // Rows of the padded block (K <= 16 rows of the structure tensor, zero padded).
@@ -69,7 +83,8 @@ struct Plan {
   // grids of the reduction kernels
   int red_blocks;
   // workspace carve
-  float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *zpart, *Z;
+  float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *Z;
+  int *zpart;          // overlap-add partials per anchor tile, fixed point (kZScale)
   int *eflag;          // per block: rotation steps | 256 if the per-lane Jacobi must finish it
   int *estat;          // per k_eig workgroup (64 blocks): step sum, max steps, fallbacks, blocks
   unsigned long long *l1part;  // level-2 l1 partial histograms: 2 x l1_part_blocks(N) x 2048
@@ -132,15 +147,22 @@ struct BlockArgs {
   // only the flagged ones.
   int *eflag;
   int *estat;              // with eflag: per-workgroup eigen statistics written by k_eig
+  int eig_steps;           // with eflag: MFMA rotation steps per block before the fallback
   // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
   int TA, TB, ntA, ntB, extA, extB, waves;
   size_t lds;
-  float *zpart;
+  int *zpart;              // fixed point (kZScale)
   DevScalars *sc;          // done flag and sweep statistics (nullable)
 };
 hipError_t launch_gram(const BlockArgs &a, hipStream_t st);
 hipError_t launch_eig(const BlockArgs &a, hipStream_t st);
 hipError_t launch_apply(const BlockArgs &a, hipStream_t st);
+// Warm iterations in one pass over Y (Gram, MFMA eigen-solve, clip, overlap-add), followed by
+// launch_eig and launch_fixup for the blocks it could not certify. Requires fused_supported.
+bool fused_supported(const BlockArgs &a);
+size_t fused_lds_bytes(const BlockArgs &a);
+hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st);
+hipError_t launch_fixup(const BlockArgs &a, hipStream_t st);
 
 // Layout converters for the operator entry points.
 // rows x ncols_src row-major blocks <-> apply layout with ncol padded columns. For the

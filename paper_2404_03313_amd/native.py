@@ -14,8 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libs3ttv.so")
 
 OK, NOT_CONVERGED, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
-K_PRIMAL, K_L1, K_GRAD, K_GRAM, K_EIG, K_APPLY, K_ZSUM, K_DUAL, K_FINAL = range(9)
-KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", "final"]
+K_PRIMAL, K_L1, K_GRAD, K_GRAM, K_EIG, K_APPLY, K_ZSUM, K_DUAL, K_FINAL, K_BLOCK = range(10)
+KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", "final", "block"]
+N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 
 EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
@@ -35,7 +36,8 @@ class Params(ctypes.Structure):
                 ("gamma_t", ctypes.c_double), ("gamma_Y", ctypes.c_double),
                 ("gamma_y2", ctypes.c_double), ("gamma_y3", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("timing_mask", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
+                ("eig_max_steps", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("eig_avg_steps", ctypes.c_float), ("eig_max_steps", ctypes.c_int32),
                 ("eig_fallback_blocks", ctypes.c_int64),
                 ("ms", ctypes.c_float),
-                ("kernel_ms", ctypes.c_float * 9), ("kernel_calls", ctypes.c_int32 * 9)]
+                ("kernel_ms", ctypes.c_float * 10), ("kernel_calls", ctypes.c_int32 * 10)]
 
 
 class S3TTVError(RuntimeError):
@@ -136,12 +138,12 @@ def default_gammas(k1: int, k2: int) -> dict:
 
 
 def make_params(eps, alpha, beta, max_iter, mu_min=0.0, mu_max=1.0, gammas: Optional[dict] = None,
-                rel_tol=0.0, check_every=16, timing_mask=0) -> Params:
+                rel_tol=0.0, check_every=16, timing_mask=0, eig_max_steps=0) -> Params:
     g = gammas or {}
     return Params(eps, alpha, beta, mu_min, mu_max, g.get("gamma_u", 0.0), g.get("gamma_s", 0.0),
                   g.get("gamma_t", 0.0), g.get("gamma_Y", 0.0), g.get("gamma_y2", 0.0),
                   g.get("gamma_y3", 0.0), int(max_iter), float(rel_tol), int(check_every),
-                  int(timing_mask))
+                  int(timing_mask), int(eig_max_steps))
 
 
 def workspace_bytes(n1, n2, n3, k1, k2) -> int:
@@ -179,8 +181,9 @@ class Solver:
                      eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps,
                      eig_avg_steps=st.eig_avg_steps, eig_max_steps=st.eig_max_steps,
                      eig_fallback_blocks=st.eig_fallback_blocks, ms=st.ms,
-                     kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(9)},
-                     kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i] for i in range(9)},
+                     kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(N_KERNEL_CLASSES)},
+                     kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i]
+                                   for i in range(N_KERNEL_CLASSES)},
                      code=rc)
         return u, s, t, stats
 

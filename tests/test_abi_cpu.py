@@ -50,7 +50,7 @@ def test_shape_validation(shape, code):
 
 @pytest.mark.parametrize("bad", [dict(eps=0.0), dict(alpha=-1.0), dict(beta=float("nan")),
                                  dict(mu_min=1.0, mu_max=0.0), dict(max_iter=0),
-                                 dict(gammas=dict(gamma_u=0.1))])
+                                 dict(gammas=dict(gamma_u=0.1)), dict(eig_max_steps=256)])
 def test_param_validation_before_any_gpu_call(bad):
     kw = dict(eps=1.0, alpha=1.0, beta=1.0, max_iter=10)
     kw.update(bad)
@@ -66,3 +66,29 @@ def test_null_pointers_rejected():
     rc = nt.lib().s3ttv_solve(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), None, None,
                               None, None, None, None, 0, None, None)
     assert rc == nt.EINVAL
+
+
+@pytest.mark.parametrize("cname,pyty", [("s3ttv_shape", "Shape"), ("s3ttv_params", "Params"),
+                                        ("s3ttv_stats", "Stats")])
+def test_struct_layouts_match_header(tmp_path, cname, pyty):
+    """ctypes mirrors of the public structs agree with the C header field by field (offsets
+    and total size, as gcc lays them out)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    cls = getattr(nt, pyty)
+    lines = [f'printf("size %zu\\n", sizeof({cname}));']
+    for name, *_ in cls._fields_:
+        lines.append(f'printf("{name} %zu\\n", offsetof({cname}, {name}));')
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"s3ttv.h\"\n"
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    assert int(out["size"]) == ctypes.sizeof(cls)
+    for name, *_ in cls._fields_:
+        assert int(out[name]) == getattr(cls, name).offset, name

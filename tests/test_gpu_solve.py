@@ -80,6 +80,26 @@ def test_solve_parity_custom_steps_and_warm_start(device):
     _parity(device, d, (2, 2), 40, gammas=g, u0=u0)
 
 
+@pytest.mark.parametrize("steps", [-1, 1])
+def test_solve_parity_eigen_fallback(device, steps):
+    """Few (or no) MFMA rotation steps: most blocks go through the per-lane Jacobi and the
+    fix-up of the fused block pass; the result must not change beyond rounding."""
+    _say("solve c1 eig_max_steps", steps)
+    w = synth.WORKLOADS["c1"]
+    d = synth.make_hsi(w["cfg"])
+    u, s, t, st, r = _parity(device, d, w["k"], 60, eig_max_steps=steps)
+    assert st["eig_fallback_blocks"] > 0
+
+
+def test_solve_parity_many_bands(device):
+    """N3 > 128: the warm iterations take the separate Gram / eigen / apply kernels."""
+    _say("solve 12x10x150")
+    cfg = synth.HSIConfig(12, 10, 150, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=14)
+    d = synth.make_hsi(cfg)
+    u, s, t, st, r = _parity(device, d, (2, 2), 40)
+    assert st["eig_avg_steps"] > 0
+
+
 def test_solve_stop_rule_matches_oracle(device):
     _say("solve rel_tol")
     cfg = synth.HSIConfig(12, 12, 8, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=13)
