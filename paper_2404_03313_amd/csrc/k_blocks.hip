@@ -114,16 +114,22 @@ constexpr float kGershSlack = 1e-6f;
 
 // Returns true with W (D-form) for a certified block; otherwise stores A (into a.G) for k_eig.
 // Always stores the re-orthogonalised V and the block's flag.
-__device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb,
-                                           f4 &Wout) {
+// The stored basis of block l in both D-forms (V and V^T), loaded ahead of use.
+__device__ inline void load_basis(const BlockArgs &a, long long l, f4 &vd, f4 &vt) {
+  const int lane = threadIdx.x & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const float *Vl = a.V + (size_t)l * 256;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) vd[v] = Vl[(4 * g + v) * 16 + j];
+  vt = *(const f4 *)(Vl + j * 16 + 4 * g);
+}
+
+__device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G, f4 vd, f4 Vt,
+                                           float *tb, f4 &Wout) {
   const int lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   float *Vl = a.V + (size_t)l * 256;
-  f4 vd;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) vd[v] = Vl[(4 * g + v) * 16 + j];
-  f4 Vt = *(const f4 *)(Vl + j * 16 + 4 * g);  // D-form of V^T
-  f4 A = mtn(vd, mtn(G, vd));                   // V^T G V  (G symmetric)
+  f4 A = mtn(vd, mtn(G, vd));                   // V^T G V  (G symmetric; Vt = D-form of V^T)
   const float fro = sqrtf(wave_sum(G[0] * G[0] + G[1] * G[1] + G[2] * G[2] + G[3] * G[3]));
   const float thr = kJacobiTol * fro;
 
@@ -253,9 +259,10 @@ __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G
 }
 
 // k_gram's warm mode: W of a certified block goes to a.W (row-major) for k_apply.
-__device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l, f4 G, float *tb) {
+__device__ __forceinline__ void block_eigen_mfma(const BlockArgs &a, long long l, f4 G, f4 vd,
+                                                 f4 vt, float *tb) {
   f4 W;
-  if (eigen_mfma(a, l, G, tb, W)) {
+  if (eigen_mfma(a, l, G, vd, vt, tb, W)) {
     const int lane = threadIdx.x & 63;
     float *Wl = a.W + (size_t)l * 256 + (4 * (lane >> 4)) * 16 + (lane & 15);
 #pragma unroll
@@ -281,6 +288,8 @@ __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
   const f4 *Yl = (const f4 *)(a.Y + (size_t)l * kRows * a.ncol) + lane;
   const float *Tp = pix >= 0 ? a.gradf + (size_t)pix * a.ncol + 4 * kk : nullptr;
   float *tb = tbuf[wave];
+  f4 vd = {0.f, 0.f, 0.f, 0.f}, vt = {0.f, 0.f, 0.f, 0.f};
+  if (a.V && a.eflag) load_basis(a, l, vd, vt);
   f4 acc = {0.f, 0.f, 0.f, 0.f};
   f4 ycur = Yl[0];
   for (int t = 0; t < a.ntile; ++t) {
@@ -309,7 +318,7 @@ __global__ __launch_bounds__(256) void k_gram(BlockArgs a) {
     ycur = ynext;
   }
   if (a.V && a.eflag) {
-    block_eigen_mfma(a, l, acc, tb);
+    block_eigen_mfma(a, l, acc, vd, vt, tb);
     return;
   }
   if (a.V) {
@@ -628,7 +637,7 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
 
 // Steps 9-10 and the overlap-add of the next step 2 in one pass over Y (warm iterations, at
 // most kFusedTiles column tiles, i.e. N3 <= 128). Workgroup = one TA x TB anchor tile with kFW
-// wavefronts; each wavefront takes the tile's anchors w, w + kFW, ... and keeps Y'_l (16 x ncol)
+// wavefronts; each wavefront takes anchors from a shared counter and keeps Y'_l (16 x ncol)
 // in registers in the apply layout: loads Y_l and T_l, forms the Gram matrix (column tiles
 // transposed in pairs through LDS into the Gram operand layout), diagonalises it on MFMA
 // (eigen_mfma), applies W_l on MFMA and stores Y+_l. The overlap-add goes to fixed-point LDS
@@ -641,6 +650,7 @@ constexpr int kFusedTiles = 16;
 template <int NT>
 __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   extern __shared__ __align__(16) float zacc_f[];
+  __shared__ int next_anchor;
   int *zacc = reinterpret_cast<int *>(zacc_f);
   if (a.sc && a.sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -653,6 +663,7 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   // this wavefront's two transpose tiles (row stride 20 floats)
   float *tbw = zacc_f + (size_t)next * zs + wave * 640;
   for (int e = threadIdx.x; e < next * zs; e += kFW * 64) zacc[e] = 0;
+  if (threadIdx.x == 0) next_anchor = kFW;
   // rows 4g+s of this lane: window offsets (fixed for the kernel); rows >= K are padding
   int ar[4], cr[4];
   float tw[4];
@@ -667,7 +678,8 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   __syncthreads();
   bool bad = false;
   const int nanch = np * nq;
-  for (int idx = wave; idx < nanch; idx += kFW) {
+  // anchors are handed out dynamically (the eigen-solve cost varies a lot between blocks)
+  for (int idx = wave; idx < nanch;) {
     const int da = idx / nq, db = idx - (idx / nq) * nq;
     const int p = p0 + da, q = q0 + db;
     const long long lb = (long long)p * a.n2 + q;
@@ -686,6 +698,8 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
     // all loads of the block first, then Y' = Y + g_Y T in the apply layout
     f4 y[NT];
     float T[NT][4];
+    f4 vd, vt;
+    load_basis(a, lb, vd, vt);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       y[t] = *(const f4 *)(Yl + t * 256);
@@ -719,8 +733,12 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
       G = mfma4(y1[2], y1[2], G);
       G = mfma4(y1[3], y1[3], G);
     }
+    // Y+ below is a spectral-norm projection (entries in [-1, 1]) of Y'; a non-finite Y'
+    // shows in its Gram matrix, so that is the one check needed before the fixed-point sum.
+    const bool fin = isfinite(G[0] + G[1] + G[2] + G[3]);
+    bad |= !fin;
     f4 W;
-    if (eigen_mfma(a, lb, G, tbw, W)) {
+    if (eigen_mfma(a, lb, G, vd, vt, tbw, W) && fin) {
       // Y+ = W Y' (W symmetric: its D-form register s of lane (r, g) is W[r][4g+s]),
       // stored in place and added to the tile's overlap-add accumulators
 #pragma unroll
@@ -733,13 +751,16 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
         *(f4 *)(Yl + t * 256) = acc;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed(acc[s], bad));
+          if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed_bounded(acc[s]));
       }
     } else {
       // left to k_eig / k_fixup: keep Y'
 #pragma unroll
       for (int t = 0; t < NT; ++t) *(f4 *)(Yl + t * 256) = y[t];
     }
+    int nxt = 0;
+    if (lane == 0) nxt = atomicAdd(&next_anchor, 1);
+    idx = __shfl(nxt, 0);
   }
   flag_nonfinite(a.sc, bad);
   __syncthreads();

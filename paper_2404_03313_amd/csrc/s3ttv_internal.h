@@ -19,6 +19,8 @@ __device__ inline int to_fixed(float y, bool &bad) {
   bad |= !(fabsf(y) <= kZMax);
   return __float2int_rn(fminf(fmaxf(y, -kZMax), kZMax) * kZScale);
 }
+// Same for a value already known to be finite and within [-kZMax, kZMax].
+__device__ inline int to_fixed_bounded(float y) { return __float2int_rn(y * kZScale); }
 
 // Number of float32 columns per block tile handled by one 16x16 MFMA step group.
 constexpr int kTile = 16;
