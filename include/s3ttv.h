@@ -90,12 +90,13 @@ typedef struct {
 enum {
   S3TTV_K_PRIMAL = 0, /* u, s, t primal step + first l1 histogram (Alg. 1 steps 2-4) */
   S3TTV_K_L1 = 1,     /* l1 threshold refinement passes and selections */
-  S3TTV_K_GRAD = 2,   /* D_v D_s u', D_h D_s u' (steps 5, 9) */
+  S3TTV_K_GRAD = 2,   /* D_v D_s u', D_h D_s u' (steps 5, 9); in s3ttv_solve part of DUAL */
   S3TTV_K_GRAM = 3,   /* Y' = Y + gamma_Y P_l D D_s u', Gram Y' Y'^T on MFMA (step 9) */
   S3TTV_K_EIG = 4,    /* Jacobi eigen-solve, spectral clip matrix (step 10) */
   S3TTV_K_APPLY = 5,  /* Y+ = W Y' on MFMA, overlap-add partials (steps 10, 2) */
-  S3TTV_K_ZSUM = 6,   /* sum of overlap-add partials (P_l^T of step 2) */
-  S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) */
+  S3TTV_K_ZSUM = 6,   /* sum of overlap-add partials (P_l^T of step 2), when the primal step
+                         cannot read them itself */
+  S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) and the gradient field */
   S3TTV_K_FINAL = 8,  /* scalar reductions, stop rule */
   S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks for iterations 2.. (N3 <= 128): steps 9-10
                          (Gram, eigen-solve, clip) and the overlap-add on MFMA */

@@ -2,10 +2,12 @@
 //
 // Validates arguments, carves the caller's workspace, and enqueues the per-iteration
 // kernel chain:
-//   primal (steps 2-4, level-1 l1 histograms) -> l1 select/refine x3 (tau_s, tau_t)
-//   -> grad (D_v D_s u', D_h D_s u') -> gram -> eig -> apply (steps 9-10 + overlap-add)
-//   -> zsum (P^T for the next step 2) -> dual (steps 3-7 thresholds, 12, 13) -> finalize
-//   (y3 projection scalar of step 14, stop rule).
+//   primal (steps 2-4, level-1 l1 histograms) -> l1 select / level-2 partial histograms /
+//   reduce / select / level-3 histogram / select (tau_s, tau_t) -> dual steps (3-7
+//   thresholds, 12, 13) with the gradient field D_v D_s u', D_h D_s u' -> block pass (steps
+//   9-10 + overlap-add: fused Gram / MFMA eigen-solve / clip from the second iteration on,
+//   else gram -> eig -> apply) -> zsum (P^T for the next step 2) -> finalize (y3 projection
+//   scalar of step 14, stop rule).
 // The only device->host traffic inside the loop is a 4-byte stop flag every check_every
 // iterations when rel_tol > 0.
 #include <math.h>
@@ -101,7 +103,9 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.xt = cv.take<float>(N);
   pl.gradf = cv.take<float>((size_t)pl.P * pl.ncol);
   pl.Z = cv.take<float>((size_t)pl.P * pl.ncol);
-  pl.zpart = cv.take<int>((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB * pl.ncol);
+  // one extra all-zero slot at the end (named by the primal step's slot table for absent terms)
+  pl.zpart = cv.take<int>(((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol);
+  pl.zslot = cv.take<int>((size_t)pl.P * 4);
   pl.G = cv.take<float>((size_t)pl.P * 256);
   pl.W = cv.take<float>((size_t)pl.P * 256);
   pl.V = cv.take<float>((size_t)pl.P * 256);
@@ -313,11 +317,16 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
   CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
   CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
   CK(launch_identity16(pl.V, pl.P, st));
+  // overlap-add partials start at zero (the first primal step may read them directly)
+  CK(launch_fill(reinterpret_cast<float *>(pl.zpart),
+                 ((long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol, 0.f, st));
+  CK(launch_zslots(pl, st));
   {
-    int32_t bad = 0;
-    CK(hipMemcpyAsync(&bad, &pl.sc->nonfinite, sizeof(bad), hipMemcpyDeviceToHost, st));
+    DevScalars hs0;
+    CK(hipMemcpyAsync(&hs0, pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    if (bad) return S3TTV_ENONFINITE;
+    if (hs0.nonfinite) return S3TTV_ENONFINITE;
+    pl.zfold = hs0.zslot_overflow == 0 && zslots_fit(pl);
   }
   // First iteration: the stored basis is the identity, so every block is solved by the
   // per-lane Jacobi (cold). Later iterations diagonalise on MFMA from the previous basis.
@@ -343,7 +352,9 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
     TIMED(S3TTV_K_L1, launch_l1_select(2, 2, pl.alpha, pl.beta, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
     TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_GRAD, launch_grad(pl, pl.u[n], pl.u[c], 2.f, -1.f, nullptr, st));
+    // dual steps (3-7 thresholds, 12, 13) together with the gradient field of u' (steps 5, 9):
+    // neither depends on the block pass
+    TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
     if (it > 0 && fused) {
       TIMED(S3TTV_K_BLOCK, launch_block_fused(bw, st));
       TIMED(S3TTV_K_EIG, launch_eig(bw, st));
@@ -354,8 +365,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
       TIMED(S3TTV_K_EIG, launch_eig(bk, st));
       TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
     }
-    TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
-    TIMED(S3TTV_K_DUAL, launch_dual(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
+    if (!pl.zfold) TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
     ++launched;
     if (params->rel_tol > 0 && (it + 1) % check == 0 && it + 1 < params->max_iter) {

@@ -655,7 +655,8 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   if (a.sc && a.sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tc = lane & 15, g = lane >> 4;
-  const int ta = blockIdx.x / a.ntB, tb_ = blockIdx.x - (blockIdx.x / a.ntB) * a.ntB;
+  const int tile = xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles share an L2
+  const int ta = tile / a.ntB, tb_ = tile - (tile / a.ntB) * a.ntB;
   const int p0 = ta * a.TA, q0 = tb_ * a.TB;
   const int np = min(a.TA, a.n1 - p0), nq = min(a.TB, a.n2 - q0);
   const int next = a.extA * a.extB;
@@ -764,7 +765,7 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   }
   flag_nonfinite(a.sc, bad);
   __syncthreads();
-  int *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
+  int *zp = a.zpart + (size_t)tile * next * a.ncol;
   for (int e = threadIdx.x; e < next * a.ncol; e += kFW * 64) {
     const int px = e / a.ncol, c = e - px * a.ncol;
     zp[e] = zacc[px * zs + c];

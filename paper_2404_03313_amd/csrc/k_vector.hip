@@ -80,11 +80,20 @@ struct PrimalArgs {
   long long N;
   float g_u, g_s, g_t, lo, hi;
   const float *u, *s, *t, *y2, *w, *Z;
+  const int *zpart, *zslot;  // with zslot: read the overlap-add partials instead of Z
   float *un, *xs, *xt;
   double *red;
   DevScalars *sc;
   L1Hist *hist;
 };
+
+// Overlap-add field value at column col of a pixel from its four partial slots, given as
+// element offsets into zpart (fixed point; unused entries name an all-zero slot, so the loads
+// carry no branches).
+__device__ inline float zfold_val(const int *zpart, int4 off, int col) {
+  const int acc = (zpart[off.x + col] + zpart[off.y + col]) + (zpart[off.z + col] + zpart[off.w + col]);
+  return (float)acc * kZInv;
+}
 
 // Alg. 1 steps 2-4 before the l1 projections:
 //   u+ = P_box(u - g_u (D_s^T (D_v^T Zv + D_h^T Zh) + y3))        (eq. prox_box_constraint)
@@ -106,12 +115,23 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
     const int bm = wrap_dn(b - 1, n3);
     const uint32_t pim = (uint32_t)(wrap_dn(i - 1, a.n1) * n2 + j);
     const uint32_t pjm = (uint32_t)(i * n2 + wrap_dn(j - 1, n2));
-    const float *Zp = a.Z + (size_t)pix * ncol;
-    const float *Zi = a.Z + (size_t)pim * ncol;
-    const float *Zj = a.Z + (size_t)pjm * ncol;
     // q(b) = (D_v^T Zv + D_h^T Zh)(b); adjoint of D_s: q(b-1) - q(b)
-    const float q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
-    const float q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+    float q0, q1;
+    if (a.zslot) {
+      const int4 sp = reinterpret_cast<const int4 *>(a.zslot)[pix];
+      const int4 si = reinterpret_cast<const int4 *>(a.zslot)[pim];
+      const int4 sj = reinterpret_cast<const int4 *>(a.zslot)[pjm];
+      q0 = (zfold_val(a.zpart, si, b) - zfold_val(a.zpart, sp, b)) +
+           (zfold_val(a.zpart, sj, Bp + b) - zfold_val(a.zpart, sp, Bp + b));
+      q1 = (zfold_val(a.zpart, si, bm) - zfold_val(a.zpart, sp, bm)) +
+           (zfold_val(a.zpart, sj, Bp + bm) - zfold_val(a.zpart, sp, Bp + bm));
+    } else {
+      const float *Zp = a.Z + (size_t)pix * ncol;
+      const float *Zi = a.Z + (size_t)pim * ncol;
+      const float *Zj = a.Z + (size_t)pjm * ncol;
+      q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
+      q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+    }
     const float adj = q1 - q0;
     const float y3 = kappa * a.w[e];
     const float uo = a.u[e];
@@ -263,6 +283,41 @@ __global__ __launch_bounds__(kNT) void k_zsum(ZsumArgs a) {
   }
 }
 
+// Slot table of the same enumeration as k_zsum, as element offsets (slot * ncol) into zpart:
+// one thread per pixel.
+__global__ __launch_bounds__(kNT) void k_zslots(ZsumArgs a, int *zslot, int zero_slot) {
+  const long long P = (long long)a.n1 * a.n2;
+  const size_t tile_stride = (size_t)a.extA * a.extB;
+  for (long long pix = (long long)blockIdx.x * kNT + threadIdx.x; pix < P;
+       pix += (long long)gridDim.x * kNT) {
+    const int i = (int)(pix / a.n2), j = (int)(pix - (pix / a.n2) * a.n2);
+    const int zero = (int)((long long)zero_slot * a.ncol);  // table unused unless it fits
+    int sl[4] = {zero, zero, zero, zero};
+    int cnt = 0;
+    for (int offr = 0; offr < a.k1; ++offr) {
+      if (!first_visit(i, offr, a.n1, a.TA)) continue;
+      const int ta = anchor_tile(i, offr, a.n1, a.TA);
+      int e0 = i - ta * a.TA;
+      if (e0 < 0) e0 += a.n1;
+      for (int ei = e0; ei < a.extA; ei += a.n1) {
+        for (int offc = 0; offc < a.k2; ++offc) {
+          if (!first_visit(j, offc, a.n2, a.TB)) continue;
+          const int tb = anchor_tile(j, offc, a.n2, a.TB);
+          int f0 = j - tb * a.TB;
+          if (f0 < 0) f0 += a.n2;
+          for (int ej = f0; ej < a.extB; ej += a.n2) {
+            const size_t slot = ((size_t)ta * a.ntB + tb) * tile_stride + (size_t)ei * a.extB + ej;
+            if (cnt < 4) sl[cnt] = (int)((long long)slot * a.ncol);
+            ++cnt;
+          }
+        }
+      }
+    }
+    if (cnt > 4) atomicOr(&a.sc->zslot_overflow, 1);
+    reinterpret_cast<int4 *>(zslot)[pix] = make_int4(sl[0], sl[1], sl[2], sl[3]);
+  }
+}
+
 // ---------------------------------------------------------------- dual step
 
 struct DualArgs {
@@ -305,6 +360,70 @@ __global__ __launch_bounds__(kNT) void k_dual(DualArgs a) {
     a.s[e] = sn;
     a.tn[e] = tn0;
     w2 += (double)wn * (double)wn;
+  }
+  w2 = block_sum(w2, sh);
+  if (threadIdx.x == 0) a.red[blockIdx.x] = w2;
+}
+
+// k_dual and k_grad in one sweep (the dual step does not depend on the block pass, which only
+// needs the gradient field): one thread per (pixel, padded band); bands >= N3 only write the
+// zero padding of the gradient field. The extrapolated u' = 2u+ - u is formed once.
+struct DualGradArgs {
+  DualArgs d;
+  int Bp, ncol;
+  float *g;
+};
+
+__global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
+  __shared__ double sh[4];
+  const DualArgs &a = ag.d;
+  if (a.sc->done) return;
+  const int act_s = a.sc->active[0], act_t = a.sc->active[1];
+  const double tau_s = a.sc->tau[0], tau_t = a.sc->tau[1];
+  const float kappa = (float)a.sc->kappa;
+  const int n2 = a.n2, n3 = a.n3, Bp = ag.Bp;
+  const long long total = (long long)a.n1 * n2 * Bp;
+  double w2 = 0;
+  for (long long idx = (long long)blockIdx.x * kNT + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * kNT) {
+    const uint32_t pix = (uint32_t)(idx / Bp);
+    const int b = (int)(idx - (long long)pix * Bp);
+    float gv = 0.f, gh = 0.f;
+    if (b < n3) {
+      const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
+      const size_t e = (size_t)pix * n3 + b;
+      const size_t o10 = ((size_t)wrap_up(i + 1, a.n1) * n2 + j) * n3;
+      const size_t o01 = ((size_t)i * n2 + wrap_up(j + 1, n2)) * n3;
+      const size_t ep = o10 + b;
+      // dual step (as k_dual)
+      const float xs = a.xs[e];
+      const float sn = act_s ? soft(xs, tau_s) : xs;
+      const float xt0 = a.xt[e], xt1 = a.xt[ep];
+      const float tn0 = act_t ? soft(xt0, tau_t) : xt0;
+      const float tn1 = act_t ? soft(xt1, tau_t) : xt1;
+      const float tp0 = 2.f * tn0 - a.to[e];
+      const float tp1 = 2.f * tn1 - a.to[ep];
+      const float sp = 2.f * sn - a.s[e];
+      const float up = 2.f * a.un[e] - a.uo[e];
+      a.y2[e] = a.y2[e] + a.g_y2 * (tp1 - tp0);
+      const float wn = kappa * a.w[e] + a.g_y3 * (((up + sp) + tp0) - a.v[e]);
+      a.w[e] = wn;
+      a.s[e] = sn;
+      a.tn[e] = tn0;
+      w2 += (double)wn * (double)wn;
+      // gradient field of u' (as k_grad with ca = 2, cb = -1)
+      const int b1 = wrap_up(b + 1, n3);
+      const size_t o00 = (size_t)pix * n3;
+#define UP(o, bb) (2.f * a.un[(o) + (bb)] + -1.f * a.uo[(o) + (bb)])
+      const float d00 = UP(o00, b1) - up;
+      const float d10 = UP(o10, b1) - UP(o10, b);
+      const float d01 = UP(o01, b1) - UP(o01, b);
+#undef UP
+      gv = d10 - d00;
+      gh = d01 - d00;
+    }
+    ag.g[(size_t)pix * ag.ncol + b] = gv;
+    ag.g[(size_t)pix * ag.ncol + Bp + b] = gh;
   }
   w2 = block_sum(w2, sh);
   if (threadIdx.x == 0) a.red[blockIdx.x] = w2;
@@ -529,6 +648,7 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
   a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.Bp = pl.Bp; a.ncol = pl.ncol; a.N = pl.N;
   a.g_u = pl.g_u; a.g_s = pl.g_s; a.g_t = pl.g_t; a.lo = pl.mu_min; a.hi = pl.mu_max;
   a.u = u_cur; a.s = pl.s; a.t = t_cur; a.y2 = pl.y2; a.w = pl.w; a.Z = pl.Z;
+  a.zpart = pl.zpart; a.zslot = pl.zfold ? pl.zslot : nullptr;
   a.un = u_new; a.xs = pl.xs; a.xt = pl.xt; a.red = pl.red_primal; a.sc = pl.sc; a.hist = pl.hist;
   hipLaunchKernelGGL(k_primal, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   return hipGetLastError();
@@ -558,6 +678,21 @@ hipError_t launch_zsum(const Plan &pl, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_zslots(const Plan &pl, hipStream_t st) {
+  ZsumArgs a;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.ncol = pl.ncol; a.k1 = pl.k1; a.k2 = pl.k2;
+  a.TA = pl.TA; a.TB = pl.TB; a.ntA = pl.ntA; a.ntB = pl.ntB; a.extA = pl.extA; a.extB = pl.extB;
+  a.zpart = pl.zpart; a.Z = pl.Z; a.sc = pl.sc;
+  const int zero_slot = pl.ntA * pl.ntB * pl.extA * pl.extB;  // the extra all-zero slot
+  hipLaunchKernelGGL(k_zslots, dim3(grid_for(pl.P, 1)), dim3(kNT), 0, st, a, pl.zslot, zero_slot);
+  return hipGetLastError();
+}
+
+// The slot table holds 32-bit element offsets: usable while zpart has fewer than 2^31 entries.
+bool zslots_fit(const Plan &pl) {
+  return ((long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol < (1ll << 31);
+}
+
 hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, const float *t_cur,
                        float *t_new, const float *v, hipStream_t st) {
   DualArgs a;
@@ -565,6 +700,18 @@ hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, c
   a.un = u_new; a.uo = u_cur; a.xs = pl.xs; a.xt = pl.xt; a.to = t_cur; a.v = v;
   a.s = pl.s; a.tn = t_new; a.y2 = pl.y2; a.w = pl.w; a.red = pl.red_dual; a.sc = pl.sc;
   hipLaunchKernelGGL(k_dual, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_dual_grad(const Plan &pl, const float *u_cur, const float *u_new,
+                            const float *t_cur, float *t_new, const float *v, hipStream_t st) {
+  DualGradArgs g;
+  DualArgs &a = g.d;
+  a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.N = pl.N; a.g_y2 = pl.g_y2; a.g_y3 = pl.g_y3;
+  a.un = u_new; a.uo = u_cur; a.xs = pl.xs; a.xt = pl.xt; a.to = t_cur; a.v = v;
+  a.s = pl.s; a.tn = t_new; a.y2 = pl.y2; a.w = pl.w; a.red = pl.red_dual; a.sc = pl.sc;
+  g.Bp = pl.Bp; g.ncol = pl.ncol; g.g = pl.gradf;
+  hipLaunchKernelGGL(k_dual_grad, dim3(pl.red_blocks), dim3(kNT), 0, st, g);
   return hipGetLastError();
 }
 

@@ -22,6 +22,14 @@ __device__ inline int to_fixed(float y, bool &bad) {
 // Same for a value already known to be finite and within [-kZMax, kZMax].
 __device__ inline int to_fixed_bounded(float y) { return __float2int_rn(y * kZScale); }
 
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin. Remapping
+// workgroup b to logical index (b % 8) * (G / 8) + b / 8 gives each XCD a contiguous eighth of
+// the work, so stencil neighbours are found in the same L2. Identity when G % 8 != 0.
+constexpr int kXcds = 8;
+__device__ inline int xcd_block(int b, int G) {
+  return (G % kXcds) ? b : (b % kXcds) * (G / kXcds) + b / kXcds;
+}
+
 // Number of float32 columns per block tile handled by one 16x16 MFMA step group.
 constexpr int kTile = 16;
 // Rows of the padded block (K <= 16 rows of the structure tensor, zero padded).
@@ -60,7 +68,7 @@ struct DevScalars {
   unsigned long long step_blocks; // blocks counted in step_sum
   unsigned long long fallback_blocks;  // warm-iteration blocks handed to the per-lane Jacobi
   int32_t max_steps;              // largest rotation step count of one block
-  int32_t pad;
+  int32_t zslot_overflow;         // some pixel has more than 4 overlap-add partial slots
 };
 
 // l1 histograms: per ball, per level: counts (u32) and significand sums (u64).
@@ -87,6 +95,9 @@ struct Plan {
   // workspace carve
   float *u[2], *s, *t[2], *y2, *w, *xs, *xt, *gradf, *Y, *G, *W, *V, *Z;
   int *zpart;          // overlap-add partials per anchor tile, fixed point (kZScale)
+  int *zslot;          // per pixel: the (up to 4) partial slots holding its overlap-add terms;
+                       // absent ones name the extra all-zero slot at the end of zpart
+  bool zfold;          // the primal step sums the partials itself (no separate zsum pass)
   int *eflag;          // per block: rotation steps | 256 if the per-lane Jacobi must finish it
   int *estat;          // per k_eig workgroup (64 blocks): step sum, max steps, fallbacks, blocks
   unsigned long long *l1part;  // level-2 l1 partial histograms: 2 x l1_part_blocks(N) x 2048
@@ -114,8 +125,15 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
 hipError_t launch_grad(const Plan &pl, const float *a, const float *b, float ca, float cb,
                        float *gout, hipStream_t st);
 hipError_t launch_zsum(const Plan &pl, hipStream_t st);
+// Per-pixel slot table for the primal step's own overlap-add sum; flags pixels with more
+// than 4 slots in DevScalars::zslot_overflow.
+hipError_t launch_zslots(const Plan &pl, hipStream_t st);
+bool zslots_fit(const Plan &pl);
 hipError_t launch_dual(const Plan &pl, const float *u_cur, const float *u_new, const float *t_cur,
                        float *t_new, const float *v, hipStream_t st);
+// launch_dual and the gradient field of u' = 2 u_new - u_cur (into pl.gradf) in one sweep.
+hipError_t launch_dual_grad(const Plan &pl, const float *u_cur, const float *u_new,
+                            const float *t_cur, float *t_new, const float *v, hipStream_t st);
 // eig_stats: also fold this iteration's eigen-solve statistics (written by k_eig) in.
 hipError_t launch_finalize(const Plan &pl, bool eig_stats, hipStream_t st);
 

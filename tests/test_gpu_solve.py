@@ -62,7 +62,10 @@ def test_solve_parity_small_workload(device):
 
 
 @pytest.mark.parametrize("shape,k,iters", [((13, 11, 7), (2, 3), 60), ((20, 24, 33), (4, 4), 40),
-                                           ((6, 5, 3), (1, 2), 80), ((16, 16, 16), (4, 1), 50)])
+                                           ((6, 5, 3), (1, 2), 80), ((16, 16, 16), (4, 1), 50),
+                                           # ragged wrapping tiles: more than 4 overlap-add
+                                           # partials per pixel, summed by the separate pass
+                                           ((10, 10, 8), (4, 4), 40)])
 def test_solve_parity_ragged(device, shape, k, iters):
     _say("solve ragged", shape, k, iters)
     cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2, seed=11)
