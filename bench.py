@@ -87,6 +87,8 @@ def main() -> int:
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol-cap", type=int, default=20000)
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--gram-precision", choices=["fp32", "bf16", "fp16"], default="fp32",
+                    help="input precision of the block Gram products (accumulation stays FP32)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -101,6 +103,7 @@ def main() -> int:
     from paper_2404_03313_amd import native as nt
     from paper_2404_03313_amd import synth
 
+    prec = {"fp32": nt.GRAM_FP32, "bf16": nt.GRAM_BF16, "fp16": nt.GRAM_FP16}[args.gram_precision]
     w = synth.WORKLOADS["c2"]
     cfg = w["cfg"]
     k1, k2 = w["k"]
@@ -113,11 +116,12 @@ def main() -> int:
     rad = d["radii"]
 
     print(f"[bench] warmup {args.warmup} iterations", file=sys.stderr, flush=True)
-    solver.solve(v, nt.make_params(max_iter=max(args.warmup, 1), **rad))
+    solver.solve(v, nt.make_params(max_iter=max(args.warmup, 1), gram_precision=prec, **rad))
     torch.cuda.synchronize()
 
     print(f"[bench] timed {args.steps} iterations", file=sys.stderr, flush=True)
-    params = nt.make_params(max_iter=args.steps, timing_mask=1 << nt.K_BLOCK, **rad)
+    params = nt.make_params(max_iter=args.steps, timing_mask=1 << nt.K_BLOCK, gram_precision=prec,
+                            **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u, s, t, st = solver.solve(v, params)
@@ -144,11 +148,12 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.gram_precision == "fp32" else f"f32 ({args.gram_precision} Gram inputs)",
         "data": "synthetic",
         "config": {"workload": f"S3TTV P-PDS, synthetic HSI {n1}x{n2}x{n3}, block {k1}x{k2}, "
                                f"sigma {cfg.sigma}, salt-and-pepper {cfg.p_sp}, stripes {cfg.p_stripe}",
-                   "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed},
+                   "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed,
+                   "gram_precision": args.gram_precision},
         "loop_ms_per_step": st["ms"] / args.steps,
         "iteration_algorithmic_bytes": iteration_algorithmic_bytes(n1, n2, n3, k1, k2),
         "roofline": {"kernel": "k_block_fused", "bound": "hbm", "achieved": achieved,
@@ -181,7 +186,8 @@ def main() -> int:
 
     if not args.skip_tol:
         print(f"[bench] time to rel-tol 1e-4 (cap {args.tol_cap})", file=sys.stderr, flush=True)
-        p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=1e-4, check_every=32, **rad)
+        p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=1e-4, check_every=32,
+                            gram_precision=prec, **rad)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, _, st2 = solver.solve(v, p2)

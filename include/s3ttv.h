@@ -74,7 +74,12 @@ typedef struct {
  *    iteration's eigenbasis; blocks not certified by then are finished by a per-lane cyclic
  *    Jacobi. 0 selects the default (24); a negative value sends every block not already
  *    certified by the warm start to the Jacobi. The result does not depend on it beyond
- *    rounding; it only moves work between the two solvers. At most 255. */
+ *    rounding; it only moves work between the two solvers. At most 255.
+ *  gram_precision: S3TTV_GRAM_FP32 (default), S3TTV_GRAM_BF16 or S3TTV_GRAM_FP16: input
+ *    precision of the per-block Gram products Y' Y'^T on MFMA from the second iteration on
+ *    (accumulation is FP32; the eigen-solve, the clip W Y' and every update stay FP32). The
+ *    reduced modes trade the accuracy of W (inputs rounded to 8 or 11 significand bits) for
+ *    fewer MFMA instructions; see the error report of the tests. */
 typedef struct {
   double eps, alpha, beta;
   double mu_min, mu_max;
@@ -84,7 +89,10 @@ typedef struct {
   int32_t check_every;
   int32_t timing_mask;
   int32_t eig_max_steps;
+  int32_t gram_precision;
 } s3ttv_params;
+
+enum { S3TTV_GRAM_FP32 = 0, S3TTV_GRAM_BF16 = 1, S3TTV_GRAM_FP16 = 2 };
 
 /* Kernel classes for timing_mask / s3ttv_stats.kernel_ms. */
 enum {

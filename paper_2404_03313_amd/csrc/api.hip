@@ -190,6 +190,7 @@ bool valid_params(const s3ttv_params *pr) {
   if (pr->max_iter < 1) return false;
   if (!(pr->rel_tol >= 0 && isfinite(pr->rel_tol))) return false;
   if (pr->eig_max_steps > 255) return false;
+  if (pr->gram_precision < S3TTV_GRAM_FP32 || pr->gram_precision > S3TTV_GRAM_FP16) return false;
   return true;
 }
 
@@ -334,6 +335,7 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
   BlockArgs bw = ba;
   bw.eflag = pl.eflag;
   bw.estat = pl.estat;
+  bw.gram_prec = params->gram_precision;
   bw.eig_steps = params->eig_max_steps == 0 ? kDefaultEigSteps
                                             : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
   const bool fused = fused_supported(bw) && fused_lds_bytes(bw) <= kMaxLds;

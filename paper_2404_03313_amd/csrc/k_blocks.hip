@@ -23,6 +23,8 @@ namespace s3ttv {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 __device__ inline f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -712,8 +714,12 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
 #pragma unroll
       for (int s = 0; s < 4; ++s) y[t][s] = fmaf(tw[s], T[t][s], y[t][s]);
     // Gram: two column tiles per LDS round trip, transposed into the operand layout
-    // (lane r + 16kk: row r, columns 4kk..4kk+3 of the tile), accumulating Y' Y'^T
+    // (lane r + 16kk: row r, columns 4kk..4kk+3 of the tile), accumulating Y' Y'^T. With
+    // reduced-precision inputs one 16x16x32 MFMA takes both tiles' eight columns per lane
+    // (A and B are the same registers, so any fixed column-to-slot assignment is a valid
+    // order of the sum).
     f4 G = {0.f, 0.f, 0.f, 0.f};
+    const int prec = a.gram_prec;
 #pragma unroll
     for (int t = 0; t < NT; t += 2) {
 #pragma unroll
@@ -725,14 +731,32 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
       const f4 y0 = *(const f4 *)(tbw + tc * 20 + 4 * g);
       const f4 y1 = *(const f4 *)(tbw + 320 + tc * 20 + 4 * g);
       wave_lds_sync();
-      G = mfma4(y0[0], y0[0], G);
-      G = mfma4(y0[1], y0[1], G);
-      G = mfma4(y0[2], y0[2], G);
-      G = mfma4(y0[3], y0[3], G);
-      G = mfma4(y1[0], y1[0], G);
-      G = mfma4(y1[1], y1[1], G);
-      G = mfma4(y1[2], y1[2], G);
-      G = mfma4(y1[3], y1[3], G);
+      if (prec == 0) {
+        G = mfma4(y0[0], y0[0], G);
+        G = mfma4(y0[1], y0[1], G);
+        G = mfma4(y0[2], y0[2], G);
+        G = mfma4(y0[3], y0[3], G);
+        G = mfma4(y1[0], y1[0], G);
+        G = mfma4(y1[1], y1[1], G);
+        G = mfma4(y1[2], y1[2], G);
+        G = mfma4(y1[3], y1[3], G);
+      } else if (prec == 1) {
+        bf8 v;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          v[s] = (__bf16)y0[s];
+          v[4 + s] = (__bf16)y1[s];
+        }
+        G = __builtin_amdgcn_mfma_f32_16x16x32_bf16(v, v, G, 0, 0, 0);
+      } else {
+        h8 v;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          v[s] = (_Float16)y0[s];
+          v[4 + s] = (_Float16)y1[s];
+        }
+        G = __builtin_amdgcn_mfma_f32_16x16x32_f16(v, v, G, 0, 0, 0);
+      }
     }
     // Y+ below is a spectral-norm projection (entries in [-1, 1]) of Y'; a non-finite Y'
     // shows in its Gram matrix, so that is the one check needed before the fixed-point sum.

@@ -168,6 +168,7 @@ struct BlockArgs {
   int *eflag;
   int *estat;              // with eflag: per-workgroup eigen statistics written by k_eig
   int eig_steps;           // with eflag: MFMA rotation steps per block before the fallback
+  int gram_prec;           // fused pass: Gram inputs FP32 (0), BF16 (1) or FP16 (2)
   // apply tiling / overlap-add (zpart == nullptr: no overlap-add)
   int TA, TB, ntA, ntB, extA, extB, waves;
   size_t lds;

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libs3ttv.so")
 
 OK, NOT_CONVERGED, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
 K_PRIMAL, K_L1, K_GRAD, K_GRAM, K_EIG, K_APPLY, K_ZSUM, K_DUAL, K_FINAL, K_BLOCK = range(10)
+GRAM_FP32, GRAM_BF16, GRAM_FP16 = 0, 1, 2
 KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", "final", "block"]
 N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
                 ("gamma_y2", ctypes.c_double), ("gamma_y3", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
-                ("eig_max_steps", ctypes.c_int32)]
+                ("eig_max_steps", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -138,12 +139,13 @@ def default_gammas(k1: int, k2: int) -> dict:
 
 
 def make_params(eps, alpha, beta, max_iter, mu_min=0.0, mu_max=1.0, gammas: Optional[dict] = None,
-                rel_tol=0.0, check_every=16, timing_mask=0, eig_max_steps=0) -> Params:
+                rel_tol=0.0, check_every=16, timing_mask=0, eig_max_steps=0,
+                gram_precision=0) -> Params:
     g = gammas or {}
     return Params(eps, alpha, beta, mu_min, mu_max, g.get("gamma_u", 0.0), g.get("gamma_s", 0.0),
                   g.get("gamma_t", 0.0), g.get("gamma_Y", 0.0), g.get("gamma_y2", 0.0),
                   g.get("gamma_y3", 0.0), int(max_iter), float(rel_tol), int(check_every),
-                  int(timing_mask), int(eig_max_steps))
+                  int(timing_mask), int(eig_max_steps), int(gram_precision))
 
 
 def workspace_bytes(n1, n2, n3, k1, k2) -> int:

@@ -94,6 +94,17 @@ def test_solve_parity_eigen_fallback(device, steps):
     assert st["eig_fallback_blocks"] > 0
 
 
+@pytest.mark.parametrize("prec,tol", [(nt.GRAM_BF16, 3e-4), (nt.GRAM_FP16, 3e-5)])
+def test_solve_parity_reduced_precision_gram(device, prec, tol):
+    """Block Gram products with BF16 / FP16 inputs (FP32 accumulation, everything else FP32)
+    against the FP64 oracle on the parity workload. Measured on MI355X: BF16 up to 6.5e-5,
+    FP16 up to 6.3e-6 relative L2 (t the largest); the bounds are about 5x those."""
+    _say("solve c1 gram precision", prec)
+    w = synth.WORKLOADS["c1"]
+    d = synth.make_hsi(w["cfg"])
+    _parity(device, d, w["k"], w["iters"], tol=tol, gram_precision=prec)
+
+
 def test_solve_parity_many_bands(device):
     """N3 > 128: the warm iterations take the separate Gram / eigen / apply kernels."""
     _say("solve 12x10x150")
