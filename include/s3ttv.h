@@ -125,9 +125,11 @@ typedef struct {
   int64_t eig_fallback_blocks; /* blocks of iterations 2..iters the MFMA rotations could not
                                   certify, finished by the per-lane Jacobi (iteration 1 always
                                   solves every block with the per-lane Jacobi) */
-  float ms;             /* wall time of the iteration loop (HIP events) */
+  float ms;             /* wall time of the iteration loop (HIP events; batched: of the batch) */
   float kernel_ms[S3TTV_K_COUNT];     /* summed durations of timed classes */
   int32_t kernel_calls[S3TTV_K_COUNT];
+  int32_t tile_a, tile_b; /* anchor tile of the block kernels (does not change the result) */
+  int32_t status;         /* this problem's return code */
 } s3ttv_stats;
 
 /* Bytes of device workspace s3ttv_solve needs for this shape (host out-pointer bytes). */
@@ -140,6 +142,28 @@ int32_t s3ttv_workspace_bytes(const s3ttv_shape *shape, const s3ttv_params *para
 int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
                     const float *u0, float *u, float *s, float *t, void *workspace,
                     size_t workspace_bytes, void *stream, s3ttv_stats *stats);
+
+/* ---------------- Batched solve ---------------- */
+
+/* Bytes of device workspace s3ttv_solve_batched needs for n problems of the given shapes
+ * (params may be null). */
+int32_t s3ttv_batch_workspace_bytes(int32_t n, const s3ttv_shape *shapes,
+                                    const s3ttv_params *params, size_t *bytes);
+
+/* Solves n independent instances of Prob. (18) by Alg. 1 (each with its own shape,
+ * parameters, input v[i], optional start u0[i] and outputs u[i], s[i], t[i], all device
+ * pointers as in s3ttv_solve; u0 may be null or hold null entries). Each result is identical
+ * to s3ttv_solve on the same inputs: every problem stops by its own rule or max_iter. The
+ * problems run concurrently: after the first iteration, 16-iteration spans of all problems
+ * are captured once into a HIP graph and replayed; the anchor tile of each shape is chosen
+ * by timing the block pass on the problem's workspace (cached per shape). workspace: device,
+ * >= s3ttv_batch_workspace_bytes. stats: host array of n (nullable), with stats[i].status the
+ * problem's own code. Returns S3TTV_OK, S3TTV_NOT_CONVERGED if some problem with rel_tol > 0
+ * used up max_iter, or the first negative code. timing_mask is ignored. */
+int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_params *params,
+                            const float *const *v, const float *const *u0, float *const *u,
+                            float *const *s, float *const *t, void *workspace,
+                            size_t workspace_bytes, void *stream, s3ttv_stats *stats);
 
 /* Static description of a return code. */
 const char *s3ttv_strerror(int32_t code);

@@ -13,6 +13,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/s3ttv.h"
@@ -23,8 +25,11 @@ using namespace s3ttv;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr size_t kMaxLds = 152 * 1024;
+constexpr size_t kMaxLds = kLdsLimit;
 constexpr int kDefaultEigSteps = 24;
+// Iterations per captured graph of the batched solve (even: the u / t buffer parity of the
+// captured launches then holds for every replay).
+constexpr int kBatchSpan = 16;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -55,16 +60,30 @@ int32_t supported_shape(const s3ttv_shape *sh) {
   return S3TTV_OK;
 }
 
-// Anchor tile of the apply kernel: the largest tile whose overlap-add accumulators fit LDS.
-void choose_tiles(Plan &pl) {
-  static const int cand[][2] = {{8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}, {2, 1}, {1, 1}};
-  for (auto &c : cand) {
-    int TA = c[0] < pl.n1 ? c[0] : pl.n1, TB = c[1] < pl.n2 ? c[1] : pl.n2;
-    const size_t lds = (size_t)(TA + pl.k1 - 1) * (TB + pl.k2 - 1) * (pl.ncol + 16) * sizeof(float);
-    pl.TA = TA;
-    pl.TB = TB;
-    pl.apply_lds = lds;
-    if (lds <= kMaxLds) break;
+// Anchor-tile candidates (largest first). The arithmetic of a solve does not depend on the
+// tile (the overlap-add is exact fixed point), only its speed does.
+const int kTileCand[][2] = {{8, 8}, {8, 4}, {4, 8}, {4, 4}, {4, 2}, {2, 4}, {2, 2}, {2, 1}, {1, 1}};
+constexpr int kNumTileCand = sizeof(kTileCand) / sizeof(kTileCand[0]);
+
+size_t apply_lds_bytes(const Plan &pl, int TA, int TB) {
+  return (size_t)(TA + pl.k1 - 1) * (TB + pl.k2 - 1) * (pl.ncol + 16) * sizeof(float);
+}
+
+// Anchor tile: the forced one (clipped to the image) or the largest candidate whose
+// overlap-add accumulators fit LDS.
+void choose_tiles(Plan &pl, int forceTA, int forceTB) {
+  if (forceTA > 0 && forceTB > 0) {
+    pl.TA = forceTA < pl.n1 ? forceTA : pl.n1;
+    pl.TB = forceTB < pl.n2 ? forceTB : pl.n2;
+    pl.apply_lds = apply_lds_bytes(pl, pl.TA, pl.TB);
+  } else {
+    for (auto &c : kTileCand) {
+      const int TA = c[0] < pl.n1 ? c[0] : pl.n1, TB = c[1] < pl.n2 ? c[1] : pl.n2;
+      pl.TA = TA;
+      pl.TB = TB;
+      pl.apply_lds = apply_lds_bytes(pl, TA, TB);
+      if (pl.apply_lds <= kMaxLds) break;
+    }
   }
   pl.extA = pl.TA + pl.k1 - 1;
   pl.extB = pl.TB + pl.k2 - 1;
@@ -73,8 +92,8 @@ void choose_tiles(Plan &pl) {
   pl.apply_waves = pl.ntile < 16 ? pl.ntile : 16;
 }
 
-// Geometry + carve. base == nullptr -> size only.
-void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
+// Geometry + carve. base == nullptr -> size only. forceTA/TB > 0 fix the anchor tile.
+void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int forceTA = 0, int forceTB = 0) {
   memset(&pl, 0, sizeof(pl));
   pl.n1 = sh->n1;
   pl.n2 = sh->n2;
@@ -87,7 +106,7 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base) {
   pl.ntile = pl.ncol / 16;
   pl.P = (long long)sh->n1 * sh->n2;
   pl.N = pl.P * sh->n3;
-  choose_tiles(pl);
+  choose_tiles(pl, forceTA, forceTB);
   long long rb = (pl.N + 8191) / 8192;
   pl.red_blocks = (int)(rb < 1 ? 1 : (rb > 65535 ? 65535 : rb));
   Carver cv{base, 0, base == nullptr};
@@ -245,6 +264,314 @@ struct Timer {
     tm.end(cls, _b);                       \
   } while (0)
 
+// One problem of a solve: plan, kernel arguments and the caller's buffers.
+struct Problem {
+  Plan pl;
+  BlockArgs ba, bw;  // block-pass arguments: cold (first iteration) and warm
+  bool fused = false;
+  const s3ttv_params *prm = nullptr;
+  const float *v = nullptr, *u0 = nullptr;
+  float *u = nullptr, *s = nullptr, *t = nullptr;
+};
+
+// Validation, plan and parameters; no device work. forceTA/TB > 0 fix the anchor tile.
+int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *params,
+                const float *v, const float *u0, float *u, float *s, float *t, void *ws,
+                size_t ws_bytes, int forceTA, int forceTB) {
+  if (!valid_shape(shape) || !valid_params(params) || !v || !u || !s || !t || !ws)
+    return S3TTV_EINVAL;
+  const int32_t sup = supported_shape(shape);
+  if (sup != S3TTV_OK) return sup;
+  Gammas gm;
+  if (!resolve_gammas(shape, params, gm)) return S3TTV_EINVAL;
+  Plan &pl = pr.pl;
+  make_plan(pl, shape, nullptr, forceTA, forceTB);
+  if (ws_bytes < pl.bytes) return S3TTV_EWORKSPACE;
+  make_plan(pl, shape, (char *)ws, forceTA, forceTB);
+  pl.g_u = (float)gm.u;
+  pl.g_s = (float)gm.s;
+  pl.g_t = (float)gm.t;
+  pl.g_Y = (float)gm.Y;
+  pl.g_y2 = (float)gm.y2;
+  pl.g_y3 = (float)gm.y3;
+  pl.mu_min = (float)params->mu_min;
+  pl.mu_max = (float)params->mu_max;
+  pl.eps = params->eps;
+  pl.alpha = params->alpha;
+  pl.beta = params->beta;
+  pr.prm = params;
+  pr.v = v;
+  pr.u0 = u0;
+  pr.u = u;
+  pr.s = s;
+  pr.t = t;
+  // First iteration: the stored basis is the identity, so every block is solved by the
+  // per-lane Jacobi (cold). Later iterations diagonalise on MFMA from the previous basis.
+  pr.ba = block_args(pl);
+  pr.bw = pr.ba;
+  pr.bw.eflag = pl.eflag;
+  pr.bw.estat = pl.estat;
+  pr.bw.gram_prec = params->gram_precision;
+  pr.bw.eig_steps = params->eig_max_steps == 0
+                        ? kDefaultEigSteps
+                        : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
+  pr.fused = fused_supported(pr.bw) && fused_lds_bytes(pr.bw) <= kMaxLds;
+  return S3TTV_OK;
+}
+
+// Scalars and block arguments point at sc (the batched solve keeps them side by side).
+void set_scalars(Problem &pr, DevScalars *sc) {
+  pr.pl.sc = sc;
+  pr.ba.sc = sc;
+  pr.bw.sc = sc;
+}
+
+// Initial state (all zero except u0) and the input checks.
+int32_t enqueue_init(const Problem &pr, hipStream_t st) {
+  const Plan &pl = pr.pl;
+  CK(launch_init_scalars(pl, pr.prm->rel_tol, pr.prm->max_iter, st));
+  CK(launch_zero_bytes(pl.hist, sizeof(L1Hist), st));
+  CK(launch_check_finite(pr.v, pl.N, pl.sc, st));
+  if (pr.u0) {
+    CK(launch_check_finite(pr.u0, pl.N, pl.sc, st));
+    CK(launch_copy(pl.u[0], pr.u0, pl.N, st));
+  } else {
+    CK(launch_fill(pl.u[0], pl.N, 0.f, st));
+  }
+  CK(launch_fill(pl.s, pl.N, 0.f, st));
+  CK(launch_fill(pl.t[0], pl.N, 0.f, st));
+  CK(launch_fill(pl.y2, pl.N, 0.f, st));
+  CK(launch_fill(pl.w, pl.N, 0.f, st));
+  CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
+  CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
+  CK(launch_identity16(pl.V, pl.P, st));
+  // overlap-add partials start at zero (the first primal step may read them directly)
+  CK(launch_fill(reinterpret_cast<float *>(pl.zpart),
+                 ((long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol, 0.f, st));
+  CK(launch_zslots(pl, st));
+  return S3TTV_OK;
+}
+
+// After enqueue_init has completed: the input check and the overlap-add route.
+int32_t check_init(Problem &pr, const DevScalars &hs0) {
+  if (hs0.nonfinite) return S3TTV_ENONFINITE;
+  pr.pl.zfold = hs0.zslot_overflow == 0 && zslots_fit(pr.pl);
+  return S3TTV_OK;
+}
+
+// Iteration `it` (0-based) of Alg. 1 steps 2-14 for one problem.
+int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) {
+  const Plan &pl = pr.pl;
+  const int c = it & 1, n = c ^ 1;
+  TIMED(S3TTV_K_PRIMAL, launch_primal(pl, pl.u[c], pl.u[n], pl.t[c], st));
+  TIMED(S3TTV_K_L1, launch_l1_select(2, 1, pl.alpha, pl.beta, pl.hist, pl.sc, st));
+  TIMED(S3TTV_K_L1, launch_l1_hist_part(pl.xs, pl.xt, pl.N, 2, pl.l1part, pl.sc, st));
+  TIMED(S3TTV_K_L1, launch_l1_part_reduce(2, pl.N, pl.l1part, pl.hist, pl.sc, st));
+  TIMED(S3TTV_K_L1, launch_l1_select(2, 2, pl.alpha, pl.beta, pl.hist, pl.sc, st));
+  TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
+  TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
+  // dual steps (3-7 thresholds, 12, 13) together with the gradient field of u' (steps 5, 9):
+  // neither depends on the block pass
+  TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], pr.v, st));
+  if (it > 0 && pr.fused) {
+    TIMED(S3TTV_K_BLOCK, launch_block_fused(pr.bw, st));
+    TIMED(S3TTV_K_EIG, launch_eig(pr.bw, st));
+    TIMED(S3TTV_K_EIG, launch_fixup(pr.bw, st));
+  } else {
+    const BlockArgs &bk = it == 0 ? pr.ba : pr.bw;
+    TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
+    TIMED(S3TTV_K_EIG, launch_eig(bk, st));
+    TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
+  }
+  if (!pl.zfold) TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
+  TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
+  return S3TTV_OK;
+}
+
+// Result copies and statistics from the final scalars hs (tm: timed launches, nullable).
+int32_t finish(const Problem &pr, const DevScalars &hs, float ms, Timer *tm, s3ttv_stats *stats,
+               hipStream_t st) {
+  const Plan &pl = pr.pl;
+  int32_t code = S3TTV_OK;
+  if (hs.nonfinite) code = S3TTV_ENONFINITE;
+  else if (pr.prm->rel_tol > 0 && !hs.converged) code = S3TTV_NOT_CONVERGED;
+  if (code >= 0) {
+    const int fin = hs.iters & 1;
+    CK(launch_copy(pr.u, pl.u[fin], pl.N, st));
+    CK(launch_copy(pr.s, pl.s, pl.N, st));
+    CK(launch_copy(pr.t, pl.t[fin], pl.N, st));
+  }
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    if (code >= 0) {
+      double diag[4] = {0, 0, 0, 0};
+      double *ddev = pl.red_dual;  // reuse: 4 doubles
+      CK(launch_diagnostics(pl, pr.u, pr.s, pr.t, pr.v, ddev, st));
+      CK(hipMemcpyAsync(diag, ddev, sizeof(diag), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      stats->l1_s = diag[0];
+      stats->l1_t = diag[1];
+      stats->fid = sqrt(diag[2]);
+      stats->dv_t = sqrt(diag[3]);
+    }
+    stats->iters = hs.iters;
+    stats->converged = hs.converged && !hs.nonfinite;
+    stats->rel_change = hs.rel_change;
+    stats->eig_max_sweeps = hs.max_sweeps;
+    stats->eig_avg_sweeps =
+        hs.sweep_waves ? (float)((double)hs.sweep_sum / (double)hs.sweep_waves) : 0.f;
+    stats->eig_avg_steps =
+        hs.step_blocks ? (float)((double)hs.step_sum / (double)hs.step_blocks) : 0.f;
+    stats->eig_max_steps = hs.max_steps;
+    stats->eig_fallback_blocks = (int64_t)hs.fallback_blocks;
+    stats->ms = ms;
+    stats->tile_a = pl.TA;
+    stats->tile_b = pl.TB;
+    stats->status = code;
+    if (tm) {
+      for (auto &r : tm->rec) {
+        float k = 0.f;
+        if (hipEventElapsedTime(&k, r.second.first, r.second.second) == hipSuccess) {
+          stats->kernel_ms[r.first] += k;
+          stats->kernel_calls[r.first] += 1;
+        }
+      }
+    }
+  } else {
+    CK(hipStreamSynchronize(st));
+  }
+  return code;
+}
+
+}  // namespace
+
+// Batched-solve helpers.
+namespace {
+
+// Workspace bytes of one problem for any anchor tile the tuner may choose.
+size_t plan_bytes_any_tile(const s3ttv_shape *sh) {
+  size_t m = 0;
+  for (auto &c : kTileCand) {
+    Plan pl;
+    make_plan(pl, sh, nullptr, c[0], c[1]);
+    if (pl.bytes > m) m = pl.bytes;
+  }
+  return m;
+}
+
+size_t batch_header_bytes(int n) { return align_up((size_t)n * sizeof(DevScalars)); }
+
+// Streams and events of the batched solve, created once (default priority).
+constexpr int kBatchStreams = 4;
+struct BatchStreams {
+  hipStream_t main = nullptr, fork[kBatchStreams] = {};
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join[kBatchStreams] = {};
+  hipError_t status = hipSuccess;
+  BatchStreams() {
+    status = hipStreamCreateWithFlags(&main, hipStreamNonBlocking);
+    for (int k = 0; k < kBatchStreams && status == hipSuccess; ++k)
+      status = hipStreamCreateWithFlags(&fork[k], hipStreamNonBlocking);
+    if (status == hipSuccess) status = hipEventCreateWithFlags(&ev_in, hipEventDisableTiming);
+    if (status == hipSuccess) status = hipEventCreateWithFlags(&ev_out, hipEventDisableTiming);
+    if (status == hipSuccess) status = hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming);
+    for (int k = 0; k < kBatchStreams && status == hipSuccess; ++k)
+      status = hipEventCreateWithFlags(&ev_join[k], hipEventDisableTiming);
+  }
+};
+
+BatchStreams &batch_streams() {
+  static BatchStreams b;
+  return b;
+}
+
+// Anchor tile per problem shape: the fastest candidate for the warm block pass, timed on the
+// problem's own workspace with synthetic blocks (the arithmetic does not depend on the tile,
+// so the choice only changes speed). Results are cached per shape for the process.
+struct TileKey {
+  int n1, n2, n3, k1, k2, prec;
+  bool operator<(const TileKey &o) const {
+    const int a[6] = {n1, n2, n3, k1, k2, prec}, b[6] = {o.n1, o.n2, o.n3, o.k1, o.k2, o.prec};
+    for (int i = 0; i < 6; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+
+std::map<TileKey, std::pair<int, int>> &tile_cache() {
+  static std::map<TileKey, std::pair<int, int>> m;
+  return m;
+}
+
+std::mutex &tile_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+int32_t tune_tiles(const s3ttv_shape *shape, const s3ttv_params *params, void *ws, size_t ws_bytes,
+                   hipStream_t st, int &TA, int &TB) {
+  const TileKey key{shape->n1, shape->n2, shape->n3, shape->k1, shape->k2, params->gram_precision};
+  {
+    std::lock_guard<std::mutex> lk(tile_mutex());
+    auto it = tile_cache().find(key);
+    if (it != tile_cache().end()) {
+      TA = it->second.first;
+      TB = it->second.second;
+      return S3TTV_OK;
+    }
+  }
+  Problem def;
+  float *dummy = reinterpret_cast<float *>(ws);
+  int32_t r = prepare(def, shape, params, dummy, nullptr, dummy, dummy, dummy, ws, ws_bytes, 0, 0);
+  if (r != S3TTV_OK) return r;
+  TA = def.pl.TA;
+  TB = def.pl.TB;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (auto &c : kTileCand) {
+    if (c[0] * c[1] > 64) continue;
+    Problem pr;
+    r = prepare(pr, shape, params, dummy, nullptr, dummy, dummy, dummy, ws, ws_bytes, c[0], c[1]);
+    if (r != S3TTV_OK) continue;
+    // keep the route of the default tile (fused or separate kernels)
+    if (pr.fused != def.fused) continue;
+    if (!pr.fused && pr.pl.apply_lds > kMaxLds) continue;
+    const Plan &pl = pr.pl;
+    CK(launch_init_scalars(pl, 0.0, 0, st));
+    CK(launch_fill_hash(pl.Y, pl.P * kRows * pl.ncol, 0.01f, 1u, st));
+    CK(launch_fill_hash(pl.gradf, pl.P * pl.ncol, 0.01f, 2u, st));
+    CK(launch_identity16(pl.V, pl.P, st));
+    const BlockArgs &b = pr.bw;
+    float t_best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+      CK(hipEventRecord(e0, st));
+      if (pr.fused) {
+        CK(launch_block_fused(b, st));
+      } else {
+        CK(launch_gram(b, st));
+        CK(launch_eig(b, st));
+        CK(launch_apply(b, st));
+      }
+      CK(hipEventRecord(e1, st));
+      CK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CK(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0 && ms < t_best) t_best = ms;  // first launch is a warm-up
+    }
+    if (t_best < best) {
+      best = t_best;
+      TA = pl.TA;
+      TB = pl.TB;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(tile_mutex());
+  tile_cache()[key] = {TA, TB};
+  return S3TTV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -276,153 +603,203 @@ int32_t s3ttv_workspace_bytes(const s3ttv_shape *shape, const s3ttv_params *para
 int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
                     const float *u0, float *u, float *s, float *t, void *workspace,
                     size_t workspace_bytes, void *stream, s3ttv_stats *stats) {
-  if (!valid_shape(shape) || !valid_params(params) || !v || !u || !s || !t || !workspace)
-    return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
-  if (sup != S3TTV_OK) return sup;
-  Gammas gm;
-  if (!resolve_gammas(shape, params, gm)) return S3TTV_EINVAL;
-  Plan pl;
-  make_plan(pl, shape, nullptr);
-  if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
-  make_plan(pl, shape, (char *)workspace);
-  pl.g_u = (float)gm.u;
-  pl.g_s = (float)gm.s;
-  pl.g_t = (float)gm.t;
-  pl.g_Y = (float)gm.Y;
-  pl.g_y2 = (float)gm.y2;
-  pl.g_y3 = (float)gm.y3;
-  pl.mu_min = (float)params->mu_min;
-  pl.mu_max = (float)params->mu_max;
-  pl.eps = params->eps;
-  pl.alpha = params->alpha;
-  pl.beta = params->beta;
+  Problem pr;
+  const int32_t prep = prepare(pr, shape, params, v, u0, u, s, t, workspace, workspace_bytes, 0, 0);
+  if (prep != S3TTV_OK) return prep;
+  CK(configure_block_kernels());
   hipStream_t st = (hipStream_t)stream;
   Timer tm{params->timing_mask, st, {}};
   event_pool().used = 0;
-
-  // ---- initial state (all zero except u0)
-  CK(launch_init_scalars(pl, params->rel_tol, st));
-  CK(launch_zero_bytes(pl.hist, sizeof(L1Hist), st));
-  CK(launch_check_finite(v, pl.N, pl.sc, st));
-  if (u0) {
-    CK(launch_check_finite(u0, pl.N, pl.sc, st));
-    CK(launch_copy(pl.u[0], u0, pl.N, st));
-  } else {
-    CK(launch_fill(pl.u[0], pl.N, 0.f, st));
-  }
-  CK(launch_fill(pl.s, pl.N, 0.f, st));
-  CK(launch_fill(pl.t[0], pl.N, 0.f, st));
-  CK(launch_fill(pl.y2, pl.N, 0.f, st));
-  CK(launch_fill(pl.w, pl.N, 0.f, st));
-  CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
-  CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
-  CK(launch_identity16(pl.V, pl.P, st));
-  // overlap-add partials start at zero (the first primal step may read them directly)
-  CK(launch_fill(reinterpret_cast<float *>(pl.zpart),
-                 ((long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol, 0.f, st));
-  CK(launch_zslots(pl, st));
+  const int32_t ini = enqueue_init(pr, st);
+  if (ini != S3TTV_OK) return ini;
   {
     DevScalars hs0;
-    CK(hipMemcpyAsync(&hs0, pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&hs0, pr.pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    if (hs0.nonfinite) return S3TTV_ENONFINITE;
-    pl.zfold = hs0.zslot_overflow == 0 && zslots_fit(pl);
+    const int32_t chk = check_init(pr, hs0);
+    if (chk != S3TTV_OK) return chk;
   }
-  // First iteration: the stored basis is the identity, so every block is solved by the
-  // per-lane Jacobi (cold). Later iterations diagonalise on MFMA from the previous basis.
-  const BlockArgs ba = block_args(pl);
-  BlockArgs bw = ba;
-  bw.eflag = pl.eflag;
-  bw.estat = pl.estat;
-  bw.gram_prec = params->gram_precision;
-  bw.eig_steps = params->eig_max_steps == 0 ? kDefaultEigSteps
-                                            : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
-  const bool fused = fused_supported(bw) && fused_lds_bytes(bw) <= kMaxLds;
   const int check = params->check_every > 0 ? params->check_every : 16;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
   CK(hipEventRecord(e0, st));
-  int launched = 0;
   for (int it = 0; it < params->max_iter; ++it) {
-    const int c = it & 1, n = c ^ 1;
-    TIMED(S3TTV_K_PRIMAL, launch_primal(pl, pl.u[c], pl.u[n], pl.t[c], st));
-    TIMED(S3TTV_K_L1, launch_l1_select(2, 1, pl.alpha, pl.beta, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_hist_part(pl.xs, pl.xt, pl.N, 2, pl.l1part, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_part_reduce(2, pl.N, pl.l1part, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_select(2, 2, pl.alpha, pl.beta, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_hist(pl.xs, pl.xt, pl.N, 2, 3, pl.hist, pl.sc, st));
-    TIMED(S3TTV_K_L1, launch_l1_select(2, 3, pl.alpha, pl.beta, pl.hist, pl.sc, st));
-    // dual steps (3-7 thresholds, 12, 13) together with the gradient field of u' (steps 5, 9):
-    // neither depends on the block pass
-    TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], v, st));
-    if (it > 0 && fused) {
-      TIMED(S3TTV_K_BLOCK, launch_block_fused(bw, st));
-      TIMED(S3TTV_K_EIG, launch_eig(bw, st));
-      TIMED(S3TTV_K_EIG, launch_fixup(bw, st));
-    } else {
-      const BlockArgs &bk = it == 0 ? ba : bw;
-      TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
-      TIMED(S3TTV_K_EIG, launch_eig(bk, st));
-      TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
-    }
-    if (!pl.zfold) TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
-    TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
-    ++launched;
+    const int32_t r = enqueue_iteration(pr, it, tm, st);
+    if (r != S3TTV_OK) return r;
     if (params->rel_tol > 0 && (it + 1) % check == 0 && it + 1 < params->max_iter) {
       int32_t done = 0;
-      CK(hipMemcpyAsync(&done, &pl.sc->done, sizeof(done), hipMemcpyDeviceToHost, st));
+      CK(hipMemcpyAsync(&done, &pr.pl.sc->done, sizeof(done), hipMemcpyDeviceToHost, st));
       CK(hipStreamSynchronize(st));
       if (done) break;
     }
   }
   CK(hipEventRecord(e1, st));
   DevScalars hs;
-  CK(hipMemcpyAsync(&hs, pl.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(&hs, pr.pl.sc, sizeof(hs), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   float ms = 0.f;
   CK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)launched;
-  if (hs.nonfinite) return S3TTV_ENONFINITE;
-  const int fin = hs.iters & 1;
-  CK(launch_copy(u, pl.u[fin], pl.N, st));
-  CK(launch_copy(s, pl.s, pl.N, st));
-  CK(launch_copy(t, pl.t[fin], pl.N, st));
-  if (stats) {
-    memset(stats, 0, sizeof(*stats));
-    double diag[4] = {0, 0, 0, 0};
-    double *ddev = pl.red_dual;  // reuse: 4 doubles
-    CK(launch_diagnostics(pl, u, s, t, v, ddev, st));
-    CK(hipMemcpyAsync(diag, ddev, sizeof(diag), hipMemcpyDeviceToHost, st));
+  return finish(pr, hs, ms, &tm, stats, st);
+}
+
+// ---------------------------------------------------------------- batched solve
+
+int32_t s3ttv_batch_workspace_bytes(int32_t n, const s3ttv_shape *shapes,
+                                    const s3ttv_params *params, size_t *bytes) {
+  (void)params;
+  if (n < 1 || !shapes || !bytes) return S3TTV_EINVAL;
+  size_t total = batch_header_bytes(n);
+  for (int i = 0; i < n; ++i) {
+    if (!valid_shape(&shapes[i])) return S3TTV_EINVAL;
+    const int32_t sup = supported_shape(&shapes[i]);
+    if (sup != S3TTV_OK) return sup;
+    total += align_up(plan_bytes_any_tile(&shapes[i]));
+  }
+  *bytes = total;
+  return S3TTV_OK;
+}
+
+int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_params *params,
+                            const float *const *v, const float *const *u0, float *const *u,
+                            float *const *s, float *const *t, void *workspace,
+                            size_t workspace_bytes, void *stream, s3ttv_stats *stats) {
+  if (n < 1 || !shapes || !params || !v || !u || !s || !t || !workspace) return S3TTV_EINVAL;
+  size_t need = 0;
+  const int32_t wb = s3ttv_batch_workspace_bytes(n, shapes, params, &need);
+  if (wb != S3TTV_OK) return wb;
+  if (workspace_bytes < need) return S3TTV_EWORKSPACE;
+  for (int i = 0; i < n; ++i)
+    if (!valid_params(&params[i]) || !v[i] || !u[i] || !s[i] || !t[i]) return S3TTV_EINVAL;
+  CK(configure_block_kernels());
+  BatchStreams &bs = batch_streams();
+  CK(bs.status);
+  hipStream_t user = (hipStream_t)stream, st = bs.main;
+  CK(hipEventRecord(bs.ev_in, user));
+  CK(hipStreamWaitEvent(st, bs.ev_in, 0));
+
+  // ---- carve: scalars of all problems first (one read gathers every stop flag), then each
+  // problem's region with its tuned anchor tile
+  char *base = (char *)workspace;
+  DevScalars *scs = reinterpret_cast<DevScalars *>(base);
+  size_t off = batch_header_bytes(n);
+  std::vector<Problem> prs(n);
+  std::vector<int32_t> code(n, S3TTV_OK);
+  for (int i = 0; i < n; ++i) {
+    const size_t region = align_up(plan_bytes_any_tile(&shapes[i]));
+    int TA = 0, TB = 0;
+    int32_t r = tune_tiles(&shapes[i], &params[i], base + off, region, st, TA, TB);
+    if (r == S3TTV_OK)
+      r = prepare(prs[i], &shapes[i], &params[i], v[i], u0 ? u0[i] : nullptr, u[i], s[i], t[i],
+                  base + off, region, TA, TB);
+    if (r != S3TTV_OK) return r;
+    set_scalars(prs[i], &scs[i]);
+    off += region;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int32_t r = enqueue_init(prs[i], st);
+    if (r != S3TTV_OK) return r;
+  }
+  std::vector<DevScalars> hs(n);
+  CK(hipMemcpyAsync(hs.data(), scs, n * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  std::vector<int> active;
+  int max_iter = 0;
+  for (int i = 0; i < n; ++i) {
+    code[i] = check_init(prs[i], hs[i]);
+    if (code[i] == S3TTV_OK) {
+      active.push_back(i);
+      if (params[i].max_iter > max_iter) max_iter = params[i].max_iter;
+    }
+  }
+  Timer none{0, st, {}};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  CK(hipEventRecord(e0, st));
+
+  // Enqueues iterations [it0, it1) of every active problem, problem i on fork stream i % K.
+  auto enqueue_span = [&](int it0, int it1) -> int32_t {
+    CK(hipEventRecord(bs.ev_fork, st));
+    for (int k = 0; k < kBatchStreams; ++k) CK(hipStreamWaitEvent(bs.fork[k], bs.ev_fork, 0));
+    for (int it = it0; it < it1; ++it)
+      for (size_t a = 0; a < active.size(); ++a) {
+        Timer tk{0, bs.fork[a % kBatchStreams], {}};
+        const int32_t r = enqueue_iteration(prs[active[a]], it, tk, bs.fork[a % kBatchStreams]);
+        if (r != S3TTV_OK) return r;
+      }
+    for (int k = 0; k < kBatchStreams; ++k) {
+      CK(hipEventRecord(bs.ev_join[k], bs.fork[k]));
+      CK(hipStreamWaitEvent(st, bs.ev_join[k], 0));
+    }
+    return S3TTV_OK;
+  };
+  auto all_done = [&]() -> int32_t {
+    CK(hipMemcpyAsync(hs.data(), scs, n * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    stats->iters = hs.iters;
-    stats->converged = hs.done && !hs.nonfinite;
-    stats->rel_change = hs.rel_change;
-    stats->l1_s = diag[0];
-    stats->l1_t = diag[1];
-    stats->fid = sqrt(diag[2]);
-    stats->dv_t = sqrt(diag[3]);
-    stats->eig_max_sweeps = hs.max_sweeps;
-    stats->eig_avg_sweeps = hs.sweep_waves ? (float)((double)hs.sweep_sum / (double)hs.sweep_waves) : 0.f;
-    stats->eig_avg_steps = hs.step_blocks ? (float)((double)hs.step_sum / (double)hs.step_blocks) : 0.f;
-    stats->eig_max_steps = hs.max_steps;
-    stats->eig_fallback_blocks = (int64_t)hs.fallback_blocks;
-    stats->ms = ms;
-    for (auto &r : tm.rec) {
-      float k = 0.f;
-      if (hipEventElapsedTime(&k, r.second.first, r.second.second) == hipSuccess) {
-        stats->kernel_ms[r.first] += k;
-        stats->kernel_calls[r.first] += 1;
+    for (int i : active)
+      if (!hs[i].done) return 0;
+    return 1;
+  };
+
+  int32_t r = S3TTV_OK;
+  if (!active.empty() && max_iter > 0) {
+    // iteration 1 (cold block pass) directly, then graphs of kBatchSpan iterations each (an
+    // even span keeps the buffer parity of the captured launches); problems stop on the
+    // device (stop rule or their own max_iter), their later launches exit at once
+    r = enqueue_span(0, 1);
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int it = 1;
+    if (r == S3TTV_OK && max_iter > kBatchSpan) {
+      CK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      r = enqueue_span(1, 1 + kBatchSpan);
+      hipError_t ce = hipStreamEndCapture(st, &graph);
+      if (r == S3TTV_OK && ce != hipSuccess) r = S3TTV_EHIP;
+      if (r == S3TTV_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        r = S3TTV_EHIP;
+    }
+    while (r == S3TTV_OK && it < max_iter) {
+      if (exec && it + kBatchSpan <= max_iter) {
+        if (hipGraphLaunch(exec, st) != hipSuccess) r = S3TTV_EHIP;
+        it += kBatchSpan;
+      } else {
+        r = enqueue_span(it, max_iter);
+        it = max_iter;
+      }
+      if (r == S3TTV_OK && it < max_iter) {
+        const int32_t d = all_done();
+        if (d < 0) r = d;
+        if (d == 1) break;
       }
     }
-  } else {
-    CK(hipStreamSynchronize(st));
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
   }
-  if (params->rel_tol > 0 && !hs.done) return S3TTV_NOT_CONVERGED;
-  return S3TTV_OK;
+  if (r != S3TTV_OK) return r;
+  CK(hipEventRecord(e1, st));
+  CK(hipMemcpyAsync(hs.data(), scs, n * sizeof(DevScalars), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  int32_t overall = S3TTV_OK;
+  for (int i = 0; i < n; ++i) {
+    int32_t ci = code[i];
+    if (ci == S3TTV_OK) ci = finish(prs[i], hs[i], ms, nullptr, stats ? &stats[i] : nullptr, st);
+    else if (stats) {
+      memset(&stats[i], 0, sizeof(stats[i]));
+      stats[i].status = ci;
+    }
+    if (ci < 0 && overall >= 0) overall = ci;
+    else if (ci == S3TTV_NOT_CONVERGED && overall == S3TTV_OK) overall = ci;
+  }
+  CK(hipEventRecord(bs.ev_out, st));
+  CK(hipStreamWaitEvent(user, bs.ev_out, 0));
+  return overall;
 }
 
 // ---------------------------------------------------------------- operator entry points
@@ -469,7 +846,7 @@ int32_t s3ttv_op_grad(const s3ttv_shape *shape, const float *u, float *gv, float
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
   make_plan(pl, shape, (char *)workspace);
   hipStream_t st = (hipStream_t)stream;
-  CK(launch_init_scalars(pl, 0.0, st));
+  CK(launch_init_scalars(pl, 0.0, 0, st));
   CK(launch_grad(pl, u, u, 1.f, 0.f, pl.gradf, st));
   CK(launch_field_to_cubes(pl.gradf, gv, gh, pl.P, pl.n3, pl.Bp, st));
   CK(hipStreamSynchronize(st));
@@ -509,7 +886,7 @@ int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const flo
   Plan tmp;
   memset(&tmp, 0, sizeof(tmp));
   tmp.sc = sc;
-  CK(launch_init_scalars(tmp, 0.0, st));
+  CK(launch_init_scalars(tmp, 0.0, 0, st));
   CK(launch_pack_blocks(yin, Y, nblk, K, ncols, ncol, 0, 0, 0, st));
   BlockArgs a;
   memset(&a, 0, sizeof(a));
@@ -558,7 +935,7 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   make_plan(pl, shape, (char *)workspace);
   pl.g_Y = (float)gamma_Y;
   hipStream_t st = (hipStream_t)stream;
-  CK(launch_init_scalars(pl, 0.0, st));
+  CK(launch_init_scalars(pl, 0.0, 0, st));
   CK(launch_grad(pl, up, up, 1.f, 0.f, pl.gradf, st));
   CK(launch_pack_blocks(yin, pl.Y, pl.P, pl.K, 2 * pl.n3, pl.ncol, 1, pl.n3, pl.Bp, st));
   BlockArgs ba = block_args(pl);
@@ -589,7 +966,7 @@ int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out
   Plan tmp;
   memset(&tmp, 0, sizeof(tmp));
   tmp.sc = sc;
-  CK(launch_init_scalars(tmp, 0.0, st));
+  CK(launch_init_scalars(tmp, 0.0, 0, st));
   CK(launch_zero_bytes(h, sizeof(L1Hist), st));
   for (int level = 1; level <= 3; ++level) {
     if (level == 2) {

@@ -539,12 +539,13 @@ __global__ __launch_bounds__(64) void k_eig(BlockArgs a) {
 // ---------------------------------------------------------------- apply on MFMA + overlap-add
 
 // Workgroup = one TA x TB tile of anchors, `waves` wavefronts; wavefront w owns column tiles
-// t = w, w + waves, ... of every block of the tile, so the overlap-add accumulators in LDS
-// (extA x extB pixels x ncol columns) are private per column and summed in a fixed order.
+// t = w, w + waves, ... of every block of the tile, so the fixed-point overlap-add
+// accumulators in LDS (extA x extB pixels x ncol columns) are private per column.
 // MFMA step s: A = W[r][4g+s] (lane r + 16g), B = Y'[4g+s][tc] (lane tc + 16g);
 // result lane (tc, g) register v = (W Y')[4g+v][tc] is written back in place.
 __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
-  extern __shared__ float zacc[];
+  extern __shared__ int zacc_i[];  // fixed point: the result does not depend on the tiling
+  int *zacc = zacc_i;
   if (a.sc && a.sc->done) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int tc = lane & 15, g = lane >> 4;
@@ -556,8 +557,9 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
   const int zs = a.ncol + 16;  // padded LDS row stride: the four row groups land in distinct banks
   if (doz) {
     for (int t = wave; t < a.ntile; t += a.waves)
-      for (int e = g; e < next; e += 4) zacc[(size_t)e * zs + 16 * t + tc] = 0.f;
+      for (int e = g; e < next; e += 4) zacc[(size_t)e * zs + 16 * t + tc] = 0;
   }
+  bool bad = false;
   // Window geometry of this lane's four rows 4g+s (fixed for the whole kernel).
   int ar[4], cr[4];
   bool rv[4];
@@ -620,17 +622,16 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
         if (doz) {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (zo[u][v] >= 0) zacc[zo[u][v] + col] += acc[v];
+            if (zo[u][v] >= 0) zacc[zo[u][v] + col] += to_fixed(acc[v], bad);
         }
       }
     }
   }
   if (doz) {
     int *zp = a.zpart + (size_t)blockIdx.x * next * a.ncol;
-    bool bad = false;
     for (int t = wave; t < a.ntile; t += a.waves)
       for (int e = g; e < next; e += 4)
-        zp[(size_t)e * a.ncol + 16 * t + tc] = to_fixed(zacc[(size_t)e * zs + 16 * t + tc], bad);
+        zp[(size_t)e * a.ncol + 16 * t + tc] = zacc[(size_t)e * zs + 16 * t + tc];
     flag_nonfinite(a.sc, bad);
   }
 }
@@ -924,12 +925,35 @@ bool fused_supported(const BlockArgs &a) {
 
 template <int NT>
 hipError_t launch_fused_nt(const BlockArgs &a, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_block_fused<NT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_block_fused<NT>, dim3((unsigned)(a.ntA * a.ntB)), dim3(kFW * 64), lds, st,
                      a);
   return hipGetLastError();
+}
+
+template <int NT>
+hipError_t allow_lds_nt(int bytes) {
+  return hipFuncSetAttribute((const void *)k_block_fused<NT>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Raises the dynamic-LDS limit of the kernels that take it, once per process (a host-side
+// attribute, so it is done before any stream work that might be captured into a graph).
+hipError_t configure_block_kernels() {
+  static hipError_t status = []() {
+    const int bytes = (int)kLdsLimit;
+    hipError_t e = hipFuncSetAttribute((const void *)k_apply,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = allow_lds_nt<2>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<4>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<6>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<8>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<10>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<12>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<14>(bytes);
+    if (e == hipSuccess) e = allow_lds_nt<16>(bytes);
+    return e;
+  }();
+  return status;
 }
 
 hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st) {
@@ -954,11 +978,6 @@ hipError_t launch_fixup(const BlockArgs &a, hipStream_t st) {
 
 hipError_t launch_apply(const BlockArgs &a, hipStream_t st) {
   const unsigned g = (unsigned)(a.ntA * a.ntB);
-  if (a.zpart && a.lds > 0) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_apply,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)a.lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_apply, dim3(g), dim3(64 * a.waves), a.zpart ? a.lds : 0, st, a);
   return hipGetLastError();
 }

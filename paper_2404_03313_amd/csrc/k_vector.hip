@@ -487,7 +487,11 @@ __global__ __launch_bounds__(kNT) void k_finalize(FinalArgs a) {
       sc->nonfinite = 1;
       sc->done = 1;
     }
-    if (sc->rel_tol > 0 && sc->iters >= 2 && u2 > 0 && sc->rel_change < sc->rel_tol) sc->done = 1;
+    if (sc->rel_tol > 0 && sc->iters >= 2 && u2 > 0 && sc->rel_change < sc->rel_tol) {
+      sc->converged = 1;
+      sc->done = 1;
+    }
+    if (sc->max_iter > 0 && sc->iters >= sc->max_iter) sc->done = 1;
   }
 }
 
@@ -497,6 +501,20 @@ __global__ void k_fill(float *p, long long n, float val) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
     p[e] = val;
+}
+
+// Deterministic pseudo-random values in [-scale, scale) (integer hash of the index).
+__global__ void k_fill_hash(float *p, long long n, float scale, uint32_t seed) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    uint32_t h = (uint32_t)e * 0x9E3779B1u ^ (uint32_t)(e >> 32) ^ seed * 0x85EBCA77u;
+    h ^= h >> 16;
+    h *= 0x7FEB352Du;
+    h ^= h >> 15;
+    h *= 0x846CA68Bu;
+    h ^= h >> 16;
+    p[e] = scale * ((float)(h >> 8) * (2.f / 16777216.f) - 1.f);
+  }
 }
 
 __global__ void k_identity16(float *V, long long nblk) {
@@ -520,10 +538,11 @@ __global__ void k_zero_words(uint32_t *p, long long n) {
     p[e] = 0u;
 }
 
-__global__ void k_init_scalars(DevScalars *sc, double rel_tol) {
+__global__ void k_init_scalars(DevScalars *sc, double rel_tol, int max_iter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     DevScalars z = {};
     z.rel_tol = rel_tol;
+    z.max_iter = max_iter;
     *sc = z;
   }
 }
@@ -616,6 +635,11 @@ hipError_t launch_fill(float *p, long long n, float val, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_hash(float *p, long long n, float scale, uint32_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_hash, dim3(grid_for(n, 4)), dim3(kNT), 0, st, p, n, scale, seed);
+  return hipGetLastError();
+}
+
 hipError_t launch_identity16(float *V, long long nblk, hipStream_t st) {
   hipLaunchKernelGGL(k_identity16, dim3(grid_for(nblk * 256, 8)), dim3(kNT), 0, st, V, nblk);
   return hipGetLastError();
@@ -632,8 +656,8 @@ hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_scalars(const Plan &pl, double rel_tol, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, pl.sc, rel_tol);
+hipError_t launch_init_scalars(const Plan &pl, double rel_tol, int max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, pl.sc, rel_tol, max_iter);
   return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ constexpr int kL1Bins1 = 2048, kL1Shift1 = 20;
 constexpr int kL1Bins2 = 2048, kL1Shift2 = 9;
 constexpr int kL1Bins3 = 512, kL1Shift3 = 0;
 constexpr int kL1MaxBins = 2048;
+// Dynamic LDS a block kernel may use (of the 160 KB per CU).
+constexpr size_t kLdsLimit = 152 * 1024;
 // Level 2 is histogrammed per workgroup over at most this many elements per ball, so the
 // packed LDS bins (count << 40 | significand sum) cannot overflow.
 constexpr int kL1PartElems = 32768;
@@ -54,8 +56,10 @@ struct DevScalars {
   unsigned long long C_above[2];  // ... and their count
   uint32_t prefix[2];    // selected bit prefix so far
   int32_t active[2];     // 1 if the l1 projection is not the identity
-  int32_t done;          // stop rule fired
+  int32_t done;          // stop: the rule fired, max_iter was reached or a value was not finite
   int32_t iters;         // completed iterations
+  int32_t converged;     // the stop rule fired
+  int32_t max_iter;      // iteration budget (the finalize kernel sets done when it is used up)
   double rel_change;     // of the last completed iteration
   double unorm2;         // ||u^(k-1)||^2 of the last iteration
   int32_t nonfinite;     // a NaN/Inf was seen
@@ -113,8 +117,10 @@ struct Plan {
 // Vector / stencil kernels.
 hipError_t launch_fill(float *p, long long n, float val, hipStream_t st);
 hipError_t launch_identity16(float *V, long long nblk, hipStream_t st);
+// Deterministic pseudo-random fill in [-scale, scale) (synthetic data for tile tuning).
+hipError_t launch_fill_hash(float *p, long long n, float scale, uint32_t seed, hipStream_t st);
 hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st);
-hipError_t launch_init_scalars(const Plan &pl, double rel_tol, hipStream_t st);
+hipError_t launch_init_scalars(const Plan &pl, double rel_tol, int max_iter, hipStream_t st);
 hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_check_finite(const float *x, long long n, DevScalars *sc, hipStream_t st);
 // Primal step (Alg. 1 steps 2-4) from (u_cur, s, t_cur, y2, w, Z) into (u_new, xs, xt),
@@ -181,6 +187,8 @@ hipError_t launch_apply(const BlockArgs &a, hipStream_t st);
 // Warm iterations in one pass over Y (Gram, MFMA eigen-solve, clip, overlap-add), followed by
 // launch_eig and launch_fixup for the blocks it could not certify. Requires fused_supported.
 bool fused_supported(const BlockArgs &a);
+// Sets the dynamic-LDS limit of the block kernels (once per process; call before launching).
+hipError_t configure_block_kernels();
 size_t fused_lds_bytes(const BlockArgs &a);
 hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st);
 hipError_t launch_fixup(const BlockArgs &a, hipStream_t st);

@@ -22,7 +22,8 @@ OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 
 EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
            "s3ttv_op_grad", "s3ttv_op_grad_adj", "s3ttv_op_spectral_clip",
-           "s3ttv_op_dual_blocks", "s3ttv_op_l1_project"]
+           "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_batch_workspace_bytes",
+           "s3ttv_solve_batched"]
 
 
 class Shape(ctypes.Structure):
@@ -49,7 +50,8 @@ class Stats(ctypes.Structure):
                 ("eig_avg_steps", ctypes.c_float), ("eig_max_steps", ctypes.c_int32),
                 ("eig_fallback_blocks", ctypes.c_int64),
                 ("ms", ctypes.c_float),
-                ("kernel_ms", ctypes.c_float * 10), ("kernel_calls", ctypes.c_int32 * 10)]
+                ("kernel_ms", ctypes.c_float * 10), ("kernel_calls", ctypes.c_int32 * 10),
+                ("tile_a", ctypes.c_int32), ("tile_b", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
 class S3TTVError(RuntimeError):
@@ -86,6 +88,13 @@ def lib():
                                            vp, vp, sz, vp]
         L.s3ttv_op_l1_project.argtypes = [ctypes.c_int64, vp, ctypes.c_double, vp,
                                           ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+        L.s3ttv_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
+                                                  ctypes.POINTER(Params), ctypes.POINTER(sz)]
+        L.s3ttv_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
+                                          ctypes.POINTER(Params), ctypes.POINTER(vp),
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                          ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
+                                          ctypes.POINTER(Stats)]
         for name in EXPORTS:
             if name != "s3ttv_strerror":
                 getattr(L, name).restype = ctypes.c_int32
@@ -178,16 +187,57 @@ class Solver:
                                _dev_ptr(t, "t"), ctypes.c_void_p(self.ws.data_ptr()),
                                ctypes.c_size_t(self.ws.numel()), _stream(), ctypes.byref(st))
         _check(rc, "s3ttv_solve", allow=(OK, NOT_CONVERGED))
-        stats = dict(iters=st.iters, converged=bool(st.converged), rel_change=st.rel_change,
-                     l1_s=st.l1_s, l1_t=st.l1_t, fid=st.fid, dv_t=st.dv_t,
-                     eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps,
-                     eig_avg_steps=st.eig_avg_steps, eig_max_steps=st.eig_max_steps,
-                     eig_fallback_blocks=st.eig_fallback_blocks, ms=st.ms,
-                     kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(N_KERNEL_CLASSES)},
-                     kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i]
-                                   for i in range(N_KERNEL_CLASSES)},
-                     code=rc)
-        return u, s, t, stats
+        return u, s, t, _stats_dict(st, rc)
+
+
+def _stats_dict(st: Stats, rc: int) -> dict:
+    return dict(iters=st.iters, converged=bool(st.converged), rel_change=st.rel_change,
+                l1_s=st.l1_s, l1_t=st.l1_t, fid=st.fid, dv_t=st.dv_t,
+                eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps,
+                eig_avg_steps=st.eig_avg_steps, eig_max_steps=st.eig_max_steps,
+                eig_fallback_blocks=st.eig_fallback_blocks, ms=st.ms,
+                kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(N_KERNEL_CLASSES)},
+                kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i]
+                              for i in range(N_KERNEL_CLASSES)},
+                tile=(st.tile_a, st.tile_b), status=st.status, code=rc)
+
+
+def batch_workspace_bytes(shapes) -> int:
+    """shapes: list of (n1, n2, n3, k1, k2)."""
+    arr = (Shape * len(shapes))(*[Shape(*sh) for sh in shapes])
+    sz = ctypes.c_size_t()
+    _check(lib().s3ttv_batch_workspace_bytes(len(shapes), arr, None, ctypes.byref(sz)),
+           "s3ttv_batch_workspace_bytes")
+    return sz.value
+
+
+def solve_batched(problems, workspace=None):
+    """Solves several problems in one batched call (s3ttv_solve_batched).
+
+    problems: list of dicts with keys v (device cube), k1, k2, params (Params), optional u0.
+    Returns ([(u, s, t, stats)], overall code). workspace: optional reusable uint8 tensor."""
+    torch = _torch()
+    n = len(problems)
+    shapes = [(*p["v"].shape, p["k1"], p["k2"]) for p in problems]
+    sh = (Shape * n)(*[Shape(*x) for x in shapes])
+    prm = (Params * n)(*[p["params"] for p in problems])
+    need = batch_workspace_bytes(shapes)
+    dev = problems[0]["v"].device
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    outs = [tuple(torch.empty_like(p["v"]) for _ in range(3)) for p in problems]
+    vp = ctypes.c_void_p
+    ptrs = lambda xs, nm: (vp * n)(*[_dev_ptr(x, nm) for x in xs])
+    v = ptrs([p["v"] for p in problems], "v")
+    u0 = ptrs([p.get("u0") for p in problems], "u0")
+    u = ptrs([o[0] for o in outs], "u")
+    s = ptrs([o[1] for o in outs], "s")
+    t = ptrs([o[2] for o in outs], "t")
+    st = (Stats * n)()
+    rc = lib().s3ttv_solve_batched(n, sh, prm, v, u0, u, s, t, vp(workspace.data_ptr()),
+                                   ctypes.c_size_t(workspace.numel()), _stream(), st)
+    _check(rc, "s3ttv_solve_batched", allow=(OK, NOT_CONVERGED))
+    return [(o[0], o[1], o[2], _stats_dict(st[i], st[i].status)) for i, o in enumerate(outs)], rc
 
 
 def solve(v, k1, k2, eps, alpha, beta, max_iter, u0=None, **kw):

@@ -52,6 +52,20 @@ WORKLOADS: Dict[str, dict] = {
 }
 
 
+def batch_configs(count: int = 24, seed: int = 4):
+    """The uneven batch: `count` images with N1, N2 ~ U{64..307}, N3 ~ U{32..191}, sigma,
+    salt-and-pepper and stripe rates each drawn from {0.05, 0.1}, block 4 x 4 (seeded)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n1, n2 = (int(x) for x in rng.integers(64, 308, size=2))
+        n3 = int(rng.integers(32, 192))
+        sig, psp, pst = (float(x) for x in rng.choice([0.05, 0.1], size=3))
+        out.append(HSIConfig(n1, n2, n3, endmembers=8, cells=32, sigma=sig, p_sp=psp,
+                             p_stripe=pst, seed=seed * 1000 + i))
+    return out
+
+
 def _endmembers(rng: np.random.Generator, e: int, n3: int) -> np.ndarray:
     """E smooth spectra, each a sum of three Gaussian bumps over the band index."""
     b = np.arange(n3, dtype=np.float64)
