@@ -1,4 +1,4 @@
-"""ctypes binding of libs3ttv.so (the C ABI declared in include/s3ttv.h).
+"""ctypes binding of libs3ttv.so (the C ABI declared in include/s3ttv.h and s3ttv_cnn.h).
 
 Argument marshalling only: every step of the solver runs in the HIP kernels of the library.
 torch is used for device memory and the current stream. Loading fails loudly when the
@@ -23,7 +23,8 @@ OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
            "s3ttv_op_grad", "s3ttv_op_grad_adj", "s3ttv_op_spectral_clip",
            "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_batch_workspace_bytes",
-           "s3ttv_solve_batched"]
+           "s3ttv_solve_batched", "s3ttv_cnn_param_count", "s3ttv_cnn_workspace_bytes",
+           "s3ttv_cnn_forward", "s3ttv_cnn_grad", "s3ttv_cnn_train_step"]
 
 
 class Shape(ctypes.Structure):
@@ -52,6 +53,11 @@ class Stats(ctypes.Structure):
                 ("ms", ctypes.c_float),
                 ("kernel_ms", ctypes.c_float * 10), ("kernel_calls", ctypes.c_int32 * 10),
                 ("tile_a", ctypes.c_int32), ("tile_b", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+class CnnShape(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+                ("nb", ctypes.c_int32)]
 
 
 class S3TTVError(RuntimeError):
@@ -95,8 +101,18 @@ def lib():
                                           ctypes.POINTER(vp), ctypes.POINTER(vp),
                                           ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
                                           ctypes.POINTER(Stats)]
+        cs = ctypes.POINTER(CnnShape)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.s3ttv_cnn_param_count.argtypes = []
+        L.s3ttv_cnn_workspace_bytes.argtypes = [cs, ctypes.c_int32, ctypes.POINTER(sz)]
+        L.s3ttv_cnn_forward.argtypes = [cs, vp, vp, vp, vp, sz, vp]
+        L.s3ttv_cnn_grad.argtypes = [cs, vp, vp, vp, vp, dp, vp, sz, vp]
+        L.s3ttv_cnn_train_step.argtypes = [cs, vp, vp, vp, ctypes.c_int32, ctypes.c_float, vp, vp,
+                                           dp, vp, sz, vp]
         for name in EXPORTS:
-            if name != "s3ttv_strerror":
+            if name == "s3ttv_cnn_param_count":
+                L.s3ttv_cnn_param_count.restype = ctypes.c_int64
+            elif name != "s3ttv_strerror":
                 getattr(L, name).restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -319,3 +335,76 @@ def op_l1_project(x, radius):
                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                                      _stream()), "s3ttv_op_l1_project")
     return out, tau.value
+
+
+# ---------------------------------------------------------------- learned initial estimate
+
+def cnn_param_count() -> int:
+    return int(lib().s3ttv_cnn_param_count())
+
+
+def _cnn_shape(v) -> CnnShape:
+    """v: one (n1, n2, n3) volume or a stack (nb, n1, n2, n3)."""
+    if v.dim() == 3:
+        return CnnShape(*v.shape, 1)
+    if v.dim() == 4:
+        nb, n1, n2, n3 = v.shape
+        return CnnShape(n1, n2, n3, nb)
+    raise ValueError(f"expected a (n1, n2, n3) or (nb, n1, n2, n3) tensor, got {tuple(v.shape)}")
+
+
+def cnn_workspace_bytes(v_shape, training: bool) -> int:
+    """v_shape: (n1, n2, n3) or (nb, n1, n2, n3)."""
+    d = tuple(int(x) for x in v_shape)
+    sh = CnnShape(*d, 1) if len(d) == 3 else CnnShape(d[1], d[2], d[3], d[0])
+    sz = ctypes.c_size_t()
+    _check(lib().s3ttv_cnn_workspace_bytes(ctypes.byref(sh), int(bool(training)), ctypes.byref(sz)),
+           "s3ttv_cnn_workspace_bytes")
+    return sz.value
+
+
+def _cnn_ws(v, training, workspace):
+    need = cnn_workspace_bytes(v.shape, training)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, v.device)
+    return workspace
+
+
+def cnn_forward(params, v, out=None, workspace=None):
+    """u0 = v + f(v) (s3ttv_cnn_forward). params: float32 device vector."""
+    torch = _torch()
+    sh = _cnn_shape(v)
+    ws = _cnn_ws(v, False, workspace)
+    u0 = torch.empty_like(v) if out is None else out
+    _check(lib().s3ttv_cnn_forward(ctypes.byref(sh), _dev_ptr(params, "params"), _dev_ptr(v, "v"),
+                                   _dev_ptr(u0, "u0"), ctypes.c_void_p(ws.data_ptr()),
+                                   ctypes.c_size_t(ws.numel()), _stream()), "s3ttv_cnn_forward")
+    return u0
+
+
+def cnn_grad(params, v, target, workspace=None):
+    """(loss, gradient) of mean((v + f(v) - target)^2) (s3ttv_cnn_grad)."""
+    torch = _torch()
+    sh = _cnn_shape(v)
+    ws = _cnn_ws(v, True, workspace)
+    grad = torch.empty_like(params)
+    loss = ctypes.c_double()
+    _check(lib().s3ttv_cnn_grad(ctypes.byref(sh), _dev_ptr(params, "params"), _dev_ptr(v, "v"),
+                                _dev_ptr(target, "target"), _dev_ptr(grad, "grad"),
+                                ctypes.byref(loss), ctypes.c_void_p(ws.data_ptr()),
+                                ctypes.c_size_t(ws.numel()), _stream()), "s3ttv_cnn_grad")
+    return loss.value, grad
+
+
+def cnn_train_step(params, adam_m, adam_v, step, lr, v, target, workspace=None):
+    """One Adam step in place on params (s3ttv_cnn_train_step); returns the loss before it."""
+    sh = _cnn_shape(v)
+    ws = _cnn_ws(v, True, workspace)
+    loss = ctypes.c_double()
+    _check(lib().s3ttv_cnn_train_step(ctypes.byref(sh), _dev_ptr(params, "params"),
+                                      _dev_ptr(adam_m, "adam_m"), _dev_ptr(adam_v, "adam_v"),
+                                      int(step), float(lr), _dev_ptr(v, "v"),
+                                      _dev_ptr(target, "target"), ctypes.byref(loss),
+                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                      _stream()), "s3ttv_cnn_train_step")
+    return loss.value

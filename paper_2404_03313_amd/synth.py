@@ -49,6 +49,9 @@ WORKLOADS: Dict[str, dict] = {
                              p_stripe=0.05, seed=1), k=(3, 3), iters=200),
     "c2": dict(cfg=HSIConfig(256, 256, 128, endmembers=12, cells=64, sigma=0.05, p_sp=0.05,
                              p_stripe=0.1, seed=2), k=(4, 4), iters=500),
+    # learned initial estimate: applied to one large scene, compared with the zero start
+    "c5": dict(cfg=HSIConfig(512, 512, 191, endmembers=12, cells=128, sigma=0.1, p_sp=0.1,
+                             p_stripe=0.1, seed=5), k=(4, 4), rel_tol=1e-4),
 }
 
 
@@ -143,3 +146,46 @@ def small_random(n1: int, n2: int, n3: int, seed: int = 0) -> np.ndarray:
     """Plain uniform [0,1) cube for operator-level tests (float64)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(0.0, 1.0, size=(n1, n2, n3))
+
+
+def cnn_train_configs(count: int = 2000, seed0: int = 5000, n: int = 64, n3: int = 64):
+    """Training scenes for the initial-estimate network: `count` n x n x n3 images with seeds
+    seed0, seed0 + 1, ..., sigma, salt-and-pepper and stripe rates each drawn from
+    {0.05, 0.1} and 4..12 endmembers (seeded)."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        sig, psp, pst = (float(x) for x in rng.choice([0.05, 0.1], size=3))
+        e = int(rng.integers(4, 13))
+        out.append(HSIConfig(n, n, n3, endmembers=e, cells=16, sigma=sig, p_sp=psp,
+                             p_stripe=pst, seed=seed0 + i))
+    return out
+
+
+CNN_CHANNELS = (1, 32, 32, 32, 32, 1)
+
+
+def cnn_init(seed: int = 0, last_scale: float = 0.1) -> np.ndarray:
+    """Initial parameters of the network (float32 vector in the documented layout: per
+    layer weights [27][cout][cin] then cout biases): He-normal weights (std sqrt(2/(27 cin))),
+    the last layer scaled by last_scale, zero biases."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l in range(5):
+        ci, co = CNN_CHANNELS[l], CNN_CHANNELS[l + 1]
+        std = np.sqrt(2.0 / (27 * ci)) * (last_scale if l == 4 else 1.0)
+        parts.append(rng.normal(0.0, std, size=27 * co * ci))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cnn_random_params(seed: int = 0, bias: float = 0.05) -> np.ndarray:
+    """Parameters for numerics tests: He-normal weights and N(0, bias) biases, so that every
+    layer has active and inactive ReLUs."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l in range(5):
+        ci, co = CNN_CHANNELS[l], CNN_CHANNELS[l + 1]
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (27 * ci)), size=27 * co * ci))
+        parts.append(rng.normal(0.0, bias, size=co))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,5 +1,5 @@
 """Host-only checks of the C ABI: the library loads, exports every function declared in
-include/s3ttv.h, and rejects invalid arguments before touching the GPU."""
+include/*.h, and rejects invalid arguments before touching the GPU."""
 import ctypes
 import os
 import re
@@ -69,7 +69,7 @@ def test_null_pointers_rejected():
 
 
 @pytest.mark.parametrize("cname,pyty", [("s3ttv_shape", "Shape"), ("s3ttv_params", "Params"),
-                                        ("s3ttv_stats", "Stats")])
+                                        ("s3ttv_stats", "Stats"), ("s3ttv_cnn_shape", "CnnShape")])
 def test_struct_layouts_match_header(tmp_path, cname, pyty):
     """ctypes mirrors of the public structs agree with the C header field by field (offsets
     and total size, as gcc lays them out)."""
@@ -83,6 +83,7 @@ def test_struct_layouts_match_header(tmp_path, cname, pyty):
         lines.append(f'printf("{name} %zu\\n", offsetof({cname}, {name}));')
     src = tmp_path / "layout.c"
     src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"s3ttv.h\"\n"
+                   "#include \"s3ttv_cnn.h\"\n"
                    "int main(void) {\n" + "\n".join(lines) + "\nreturn 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
@@ -92,3 +93,48 @@ def test_struct_layouts_match_header(tmp_path, cname, pyty):
     assert int(out["size"]) == ctypes.sizeof(cls)
     for name, *_ in cls._fields_:
         assert int(out[name]) == getattr(cls, name).offset, name
+
+
+# ---------------------------------------------------------------- learned initial estimate
+
+def test_cnn_param_count_and_workspace():
+    assert nt.cnn_param_count() == 84801
+    small = nt.cnn_workspace_bytes((8, 8, 8), False)
+    train = nt.cnn_workspace_bytes((8, 8, 8), True)
+    assert train > small > 2 * 8 ** 3 * 32 * 2
+    # inference keeps two BF16 activation buffers of 32 channels per voxel
+    big = nt.cnn_workspace_bytes((512, 512, 191), False)
+    assert 2 * 512 * 512 * 191 * 64 <= big < 2 * 512 * 512 * 191 * 64 + (1 << 20)
+    assert nt.cnn_workspace_bytes((4, 8, 8, 8), True) > train
+
+
+@pytest.mark.parametrize("shape,code", [((0, 4, 4, 1), nt.EINVAL), ((4, 4, 4, 0), nt.EINVAL),
+                                        ((4, -1, 4, 1), nt.EINVAL),
+                                        ((1024, 1024, 1024, 2), nt.EUNSUPPORTED)])
+def test_cnn_shape_validation(shape, code):
+    sz = ctypes.c_size_t()
+    sh = nt.CnnShape(*shape)
+    assert nt.lib().s3ttv_cnn_workspace_bytes(ctypes.byref(sh), 0, ctypes.byref(sz)) == code
+    assert nt.lib().s3ttv_cnn_workspace_bytes(None, 0, ctypes.byref(sz)) == nt.EINVAL
+
+
+def test_cnn_arguments_rejected_before_any_gpu_call():
+    L = nt.lib()
+    sh = ctypes.byref(nt.CnnShape(4, 4, 4, 1))
+    d = ctypes.c_void_p(256)   # never dereferenced: validation fails first
+    odd = ctypes.c_void_p(258)
+    big = 1 << 40
+    loss = ctypes.c_double()
+    assert L.s3ttv_cnn_forward(sh, None, d, d, d, big, None) == nt.EINVAL
+    assert L.s3ttv_cnn_forward(sh, d, d, d, d, big, None) == nt.EINVAL       # v aliases u0
+    assert L.s3ttv_cnn_forward(sh, d, odd, ctypes.c_void_p(512), d, big, None) == nt.EINVAL
+    assert L.s3ttv_cnn_forward(sh, d, ctypes.c_void_p(512), ctypes.c_void_p(768), d, 16,
+                               None) == nt.EWORKSPACE
+    assert L.s3ttv_cnn_forward(sh, d, ctypes.c_void_p(512), ctypes.c_void_p(768), None, big,
+                               None) == nt.EINVAL
+    assert L.s3ttv_cnn_grad(sh, d, d, None, d, ctypes.byref(loss), d, big, None) == nt.EINVAL
+    assert L.s3ttv_cnn_grad(sh, d, d, d, d, None, d, 16, None) == nt.EWORKSPACE
+    for step, lr in ((0, 1e-3), (1, 0.0), (1, -1e-3), (1, float("nan")), (1, float("inf"))):
+        assert L.s3ttv_cnn_train_step(sh, d, d, d, step, lr, d, d, None, d, big, None) == nt.EINVAL
+    assert L.s3ttv_cnn_train_step(sh, d, d, None, 1, 1e-3, d, d, None, d, big, None) == nt.EINVAL
+    assert L.s3ttv_cnn_train_step(sh, d, d, d, 1, 1e-3, d, d, None, d, 16, None) == nt.EWORKSPACE
