@@ -12,6 +12,9 @@ Prints one JSON line. Besides the throughput it reports
     tolerance 1e-4;
   - cpu_baseline: the FP64 oracle timed on this host on a bounded sample (the first three
     iterations of the same workload).
+Other workloads (--workload): c4, the uneven batch of 24 images in one batched call; c5, the
+learned initial estimate (training on solver-generated pairs, then a 512 x 512 x 191 scene
+solved from zero and from the network's estimate).
 """
 from __future__ import annotations
 
@@ -133,6 +136,81 @@ def bench_batched(nt, synth, torch, prec) -> int:
     return 0 if same else 4
 
 
+def bench_warm_start(nt, synth, torch, args) -> int:
+    """The learned initial estimate: the network is trained on the GPU on seeded 64^3 scenes
+    whose targets the batched solver computes (rel-tol 1e-5), then the 512 x 512 x 191 scene
+    is solved to rel-tol 1e-4 from zero and from the network's estimate. A tighter solve of
+    the same scene (rel-tol 1e-6) is the yardstick for both results."""
+    import numpy as np
+    from paper_2404_03313_amd import warmstart as ws
+    dev = torch.device("cuda:0")
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    V, U, pair_iters = ws.make_pairs(synth.cnn_train_configs(count=args.pairs), rel_tol=1e-5,
+                                     max_iter=3000, log=log)
+    t_pairs = time.perf_counter() - t0
+    ident = float(((V - U) ** 2).mean())
+    tr = ws.Trainer(synth.cnn_init(0), device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = tr.train(V, U, steps=args.train_steps, batch=8, lr=1e-3, log=log, log_every=250)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del V, U
+    torch.cuda.empty_cache()
+
+    w = synth.WORKLOADS["c5"]
+    cfg, (k1, k2), tol = w["cfg"], w["k"], w["rel_tol"]
+    log(f"scene {cfg.n1}x{cfg.n2}x{cfg.n3}")
+    d = synth.make_hsi(cfg)
+    v = torch.from_numpy(d["v"]).to(dev)
+    sv = nt.Solver(cfg.n1, cfg.n2, cfg.n3, k1, k2, device=dev)
+    sv.solve(v, nt.make_params(max_iter=2, **d["radii"]))   # first-launch set-up, untimed
+    log("cold and warm solves")
+    r = ws.solve_cold_warm(v, d["radii"], tr.params, k=(k1, k2), rel_tol=tol,
+                           max_iter=args.tol_cap, solver=sv)
+    log("reference solve (rel-tol 1e-6)")
+    ref = sv.solve(v, nt.make_params(max_iter=args.ref_iters, rel_tol=1e-6, check_every=64,
+                                     **d["radii"]))
+    uref = ref[0]
+
+    def dist(a, b):
+        return float((a - b).norm() / b.norm())
+
+    cold, warm = r["cold"], r["warm"]
+    keys = ("fid", "l1_s", "l1_t", "dv_t")
+    out = {
+        "metric": "P-PDS time to rel-tol 1e-4, 512×512×191 HSI, learned warm start vs zero start",
+        "value": r["t_warm"], "unit": "s", "n_gpus": 1, "steps": warm[3]["iters"], "warmup": 1,
+        "ms_per_step": 1e3 * r["t_warm"] / max(warm[3]["iters"], 1), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (network: bf16 weights)",
+        "data": "synthetic",
+        "config": {"workload": f"S3TTV P-PDS, synthetic HSI {cfg.n1}x{cfg.n2}x{cfg.n3}, "
+                               f"sigma {cfg.sigma}, salt-and-pepper {cfg.p_sp}, stripes "
+                               f"{cfg.p_stripe}, block {k1}x{k2}, rel-tol {tol}, seed {cfg.seed}"},
+        "cold": {"s": r["t_cold"], "iters": cold[3]["iters"],
+                 "converged": cold[3]["converged"], **{k: cold[3][k] for k in keys}},
+        "warm": {"s": r["t_warm"], "iters": warm[3]["iters"], "network_ms": 1e3 * r["t_net"],
+                 "converged": warm[3]["converged"], **{k: warm[3][k] for k in keys}},
+        "speedup_time": r["t_cold"] / r["t_warm"],
+        "speedup_iters": cold[3]["iters"] / max(warm[3]["iters"], 1),
+        "rel_l2_warm_vs_cold": dist(warm[0], cold[0]),
+        "reference": {"rel_tol": 1e-6, "iters": ref[3]["iters"], "converged": ref[3]["converged"],
+                      "rel_l2_cold": dist(cold[0], uref), "rel_l2_warm": dist(warm[0], uref),
+                      "rel_l2_u0": dist(r["u0"], uref), "rel_l2_v": dist(v, uref)},
+        "training": {"pairs": args.pairs, "pair_shape": [64, 64, 64], "pair_rel_tol": 1e-5,
+                     "pair_iters_mean": float(np.mean(pair_iters)), "pair_s": t_pairs,
+                     "steps": args.train_steps, "batch": 8, "train_s": t_train,
+                     "ms_per_step": 1e3 * t_train / max(args.train_steps, 1),
+                     "loss_identity": ident, "loss_final": float(np.mean(losses[-100:]))},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,16 +220,21 @@ def main() -> int:
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol-cap", type=int, default=20000)
     ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
-                    help="c2: the single 256x256x128 image (default); c4: the uneven batch of 24")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
+                    help="c2: the single 256x256x128 image (default); c4: the uneven batch of 24; "
+                         "c5: learned initial estimate vs zero start on 512x512x191")
+    ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
+    ap.add_argument("--train-steps", type=int, default=2500, help="c5: Adam steps (batch 8)")
+    ap.add_argument("--ref-iters", type=int, default=10000,
+                    help="c5: iteration cap of the rel-tol 1e-6 reference solve")
     ap.add_argument("--gram-precision", choices=["fp32", "bf16", "fp16"], default="fp32",
                     help="input precision of the block Gram products (accumulation stays FP32)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the solver has no "
-              "multi-GPU path in this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the solver is a "
+              "single-GPU library", file=sys.stderr)
         return 2
 
     import numpy as np  # noqa: F401
@@ -163,6 +246,8 @@ def main() -> int:
     prec = {"fp32": nt.GRAM_FP32, "bf16": nt.GRAM_BF16, "fp16": nt.GRAM_FP16}[args.gram_precision]
     if args.workload == "c4":
         return bench_batched(nt, synth, torch, prec)
+    if args.workload == "c5":
+        return bench_warm_start(nt, synth, torch, args)
     w = synth.WORKLOADS["c2"]
     cfg = w["cfg"]
     k1, k2 = w["k"]

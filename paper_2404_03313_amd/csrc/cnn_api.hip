@@ -69,7 +69,7 @@ Ws carve(const CnnShape &s, bool training, void *base) {
     for (int k = 0; k < 4; ++k) w.act[k] = (uint16_t *)take(act);
     for (int k = 0; k < 2; ++k) w.g[k] = (uint16_t *)take(act);
     w.du = (float *)take((size_t)s.N * sizeof(float));
-    w.wpart = (float *)take((size_t)cnn_wgrad_parts(s) * (L::kMid + 32) * sizeof(float));
+    w.wpart = (float *)take(cnn_wgrad_part_floats(s) * sizeof(float));
   } else {
     for (int k = 0; k < 2; ++k) w.act[k] = (uint16_t *)take(act);
   }

@@ -259,77 +259,239 @@ __global__ __launch_bounds__(kNT) void k_cnn_out_bwd(CnnShape s, const float *du
 
 // ------------------------------------------------------------ weight gradients
 
-// Partial, over the workgroup's voxel range, of dW[t][co][ci] = sum_e g[e][co] x[nb_t(e)][ci]
-// and db[co] = sum_e g[e][co]. CIN, COUT in {1, 32}: one-channel tensors are FP32 cubes,
-// 32-channel ones BF16 [voxel][32]. A thread owns output channel co = tid / (256 / COUT) and
-// input channels ci0 .. ci0 + CPT - 1, ci0 = (tid % (256 / COUT)) * CPT.
-template <int CIN, int COUT>
-__global__ __launch_bounds__(kNT) void k_cnn_wgrad(CnnShape s, const void *xin, const void *gout,
-                                                   float *part) {
-  constexpr int TPC = kNT / COUT;
-  constexpr int CPT = CIN >= TPC ? CIN / TPC : 1;
-  const int co = threadIdx.x / TPC;
-  const int ci0 = (threadIdx.x % TPC) * CPT;
-  const bool live = ci0 < CIN;
-  float acc[27][CPT];
-  float accb = 0.f;
+constexpr int kWC = 32;  // bands per chunk of the 32 -> 32 weight gradient
+constexpr int kTS = 40;  // LDS row stride (elements) of its transposed tiles: 32 + 8 padding
+
+__device__ inline uint32_t half_of(const uint4 &a, int h) {
+  const uint32_t w = h < 2 ? a.x : h < 4 ? a.y : h < 6 ? a.z : a.w;
+  return (h & 1) ? (w >> 16) : (w & 0xffffu);
+}
+// Channels 8q..8q+7 of two consecutive voxels (k, k+1) -> column pair (k, k+1) of rows
+// 8q..8q+7 of a [channel][k] tile (row stride kTS elements). dst points at row 8q, column k.
+__device__ inline void put_pair_transposed(uint16_t *dst, const uint4 &va, const uint4 &vb) {
+  uint32_t *d = reinterpret_cast<uint32_t *>(dst);
 #pragma unroll
-  for (int t = 0; t < 27; ++t)
+  for (int h = 0; h < 8; ++h) d[h * (kTS / 2)] = half_of(va, h) | (half_of(vb, h) << 16);
+}
+
+// 32 -> 32 layers, on MFMA: dW[t][co][ci] = sum_e g[e][co] x[e + off_t][ci] and
+// db[co] = sum_e g[e][co], partial over the workgroup's chunks. A chunk is 32 consecutive
+// bands b' = b0 .. b0 + 31 of one line (i, j); with t = (di, dj, db) its contribution is
+//   sum_k g[(i, j), b0 + k - db][co] * x[(i + di, j + dj), b0 + k][ci],
+// a 32 x 32 x 32 (co x ci x k) contraction. LDS holds the 9 neighbour lines of x and three
+// band-shifted copies of the g line, both transposed to [channel][k] so that every MFMA
+// operand is one 16-byte read (g as A with rows co, x as B with columns ci, K = k). Values
+// beyond the volume (or the band range) are zero, so each pair (e, e + off_t) inside the
+// volume is counted exactly once. Wave w owns the taps t = w, w + 4, ..., so its 7 taps x 4
+// output blocks stay in registers for the whole chunk range.
+__global__ __launch_bounds__(kNT) void k_cnn_wgrad_mid(CnnShape s, const uint16_t *x,
+                                                       const uint16_t *g, float *part) {
+  __shared__ __align__(16) uint16_t xs[9 * 32 * kTS];  // [neighbour line r = t / 3][ci][k]
+  __shared__ __align__(16) uint16_t gs[3 * 32 * kTS];  // [band shift d = t % 3][co][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kb = lane >> 4;
+  const int cpl = (s.n3 + kWC - 1) / kWC;
+  const long long nchunks = (long long)s.nb * s.n1 * s.n2 * cpl;
+  const long long c0 = nchunks * blockIdx.x / gridDim.x;
+  const long long c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
+  f4 acc[7][2][2];
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) acc[t][k] = 0.f;
-  const int chunk = (int)(((long long)s.N + gridDim.x - 1) / gridDim.x);
-  const int beg = (int)min((long long)blockIdx.x * chunk, (long long)s.N);
-  const int end = (int)min((long long)beg + chunk, (long long)s.N);
-  if (beg < end) {
-    Vox p = vox_of(beg, s);
-    for (int e = beg; e < end; ++e, vox_next(p, s)) {
-      float g;
-      if constexpr (COUT == 1) g = reinterpret_cast<const float *>(gout)[e];
-      else g = bf2f(reinterpret_cast<const uint16_t *>(gout)[(size_t)e * 32 + co]);
-      if (g == 0.f) continue;  // masked by the ReLU: contributes nothing
-      accb += g;
-      if (!live) continue;
+  for (int m = 0; m < 7; ++m)
 #pragma unroll
-      for (int t = 0; t < 27; ++t) {
-        const int q = neighbour(p, t, s, false);
-        if (q < 0) continue;
-        if constexpr (CIN == 1) {
-          acc[t][0] = fmaf(g, reinterpret_cast<const float *>(xin)[q], acc[t][0]);
-        } else if constexpr (CPT == 4) {
-          const uint2 r = *reinterpret_cast<const uint2 *>(
-              reinterpret_cast<const uint16_t *>(xin) + (size_t)q * 32 + ci0);
-          acc[t][0] = fmaf(g, bf2f((uint16_t)(r.x & 0xffffu)), acc[t][0]);
-          acc[t][1] = fmaf(g, bf2f((uint16_t)(r.x >> 16)), acc[t][1]);
-          acc[t][2] = fmaf(g, bf2f((uint16_t)(r.y & 0xffffu)), acc[t][2]);
-          acc[t][3] = fmaf(g, bf2f((uint16_t)(r.y >> 16)), acc[t][3]);
-        } else {
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int k = 0; k < CPT; ++k)
-            acc[t][k] = fmaf(
-                g, bf2f(reinterpret_cast<const uint16_t *>(xin)[(size_t)q * 32 + ci0 + k]),
-                acc[t][k]);
-        }
+      for (int b = 0; b < 2; ++b) acc[m][a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+  for (long long c = c0; c < c1; ++c) {
+    const int line = (int)(c / cpl);
+    const int b0 = (int)(c - (long long)line * cpl) * kWC;
+    const int i = line / s.n2, j = line - i * s.n2, il = i % s.n1;
+    __syncthreads();  // the previous chunk's operands have been read
+    for (int task = tid; task < 9 * 64; task += kNT) {
+      const int r = task >> 6, kp = (task >> 2) & 15, q = task & 3;
+      const int di = r / 3 - 1, dj = r % 3 - 1;
+      const bool ok = il + di >= 0 && il + di < s.n1 && j + dj >= 0 && j + dj < s.n2;
+      const int bb = b0 + 2 * kp;
+      const size_t base = ok ? (size_t)(((i + di) * s.n2 + (j + dj)) * s.n3) : 0;
+      const uint4 va = ok && bb < s.n3 ? *reinterpret_cast<const uint4 *>(x + (base + bb) * 32 + 8 * q)
+                                       : zero4;
+      const uint4 vb = ok && bb + 1 < s.n3
+                           ? *reinterpret_cast<const uint4 *>(x + (base + bb + 1) * 32 + 8 * q)
+                           : zero4;
+      put_pair_transposed(xs + (r * 32 + 8 * q) * kTS + 2 * kp, va, vb);
+    }
+    for (int task = tid; task < 3 * 64; task += kNT) {
+      const int d = task >> 6, kp = (task >> 2) & 15, q = task & 3;
+      const int bb = b0 + 2 * kp - (d - 1);
+      const size_t base = (size_t)line * s.n3;
+      const uint4 va = bb >= 0 && bb < s.n3
+                           ? *reinterpret_cast<const uint4 *>(g + (base + bb) * 32 + 8 * q)
+                           : zero4;
+      const uint4 vb = bb + 1 >= 0 && bb + 1 < s.n3
+                           ? *reinterpret_cast<const uint4 *>(g + (base + bb + 1) * 32 + 8 * q)
+                           : zero4;
+      put_pair_transposed(gs + (d * 32 + 8 * q) * kTS + 2 * kp, va, vb);
+    }
+    __syncthreads();
+    if (tid < 32) {
+#pragma unroll
+      for (int k = 0; k < kWC; ++k) bsum += bf2f(gs[(32 + tid) * kTS + k]);
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      const int t = wave + 4 * m;
+      if (t < 27) {
+        const int r = t / 3, d = t % 3;
+        const bf8 a0 = *reinterpret_cast<const bf8 *>(gs + (d * 32 + li) * kTS + 8 * kb);
+        const bf8 a1 = *reinterpret_cast<const bf8 *>(gs + (d * 32 + 16 + li) * kTS + 8 * kb);
+        const bf8 x0 = *reinterpret_cast<const bf8 *>(xs + (r * 32 + li) * kTS + 8 * kb);
+        const bf8 x1 = *reinterpret_cast<const bf8 *>(xs + (r * 32 + 16 + li) * kTS + 8 * kb);
+        acc[m][0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, x0, acc[m][0][0], 0, 0, 0);
+        acc[m][0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, x1, acc[m][0][1], 0, 0, 0);
+        acc[m][1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x0, acc[m][1][0], 0, 0, 0);
+        acc[m][1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x1, acc[m][1][1], 0, 0, 0);
       }
     }
   }
-  // partial layout: [27][COUT][CIN] weights, then COUT biases
-  float *pw = part + (size_t)blockIdx.x * (27 * COUT * CIN + COUT);
-  if (live) {
+  // result lane (column li, group kb), register rr: co = 16 coh + 4 kb + rr, ci = 16 cih + li
+  float *pw = part + (size_t)blockIdx.x * (L::kMid + 32);
 #pragma unroll
-    for (int t = 0; t < 27; ++t)
+  for (int m = 0; m < 7; ++m) {
+    const int t = wave + 4 * m;
+    if (t < 27) {
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) pw[(t * COUT + co) * CIN + ci0 + k] = acc[t][k];
+      for (int coh = 0; coh < 2; ++coh)
+#pragma unroll
+        for (int cih = 0; cih < 2; ++cih)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr)
+            pw[(t * 32 + 16 * coh + 4 * kb + rr) * 32 + 16 * cih + li] = acc[m][coh][cih][rr];
+    }
   }
-  if (threadIdx.x % TPC == 0) pw[27 * COUT * CIN + co] = accb;
+  if (tid < 32) pw[L::kMid + tid] = bsum;
 }
 
-// out[k] = sum over the nparts partials of n floats, fixed order.
-__global__ __launch_bounds__(kNT) void k_cnn_sum_parts(const float *part, int nparts, int n,
-                                                       float *out) {
-  for (int k = blockIdx.x * kNT + threadIdx.x; k < n; k += gridDim.x * kNT) {
+// 1 -> 32 (IN1: x = v, FP32; g BF16 [voxel][32]) and 32 -> 1 (x BF16 [voxel][32]; g = du,
+// FP32) layers: dW[t][c] = sum_e g[e](c) x[e + off_t](c), the 32-channel side indexed by c,
+// and the biases, partial over the workgroup's chunks (32 bands of one line, as in the
+// 32 -> 32 kernel). LDS holds the one-channel side with a band halo of one (IN1: v on the 9
+// neighbour lines; else du on the line itself) and the 32-channel side channels-last (IN1:
+// g on the line; else x on the 9 neighbour lines). Thread (c = tid % 32, sub = tid / 32) owns
+// the taps t = sub, sub + 8, ... and keeps its 32 values of the line-side operand in
+// registers for the chunk.
+template <bool IN1>
+__global__ __launch_bounds__(kNT) void k_cnn_wgrad_edge(CnnShape s, const void *xin,
+                                                        const void *gin, float *part) {
+  __shared__ float one[9][kWC + 2];
+  __shared__ __align__(16) uint16_t many[9][kWC][32];
+  const int tid = threadIdx.x, c = tid & 31, sub = tid >> 5;
+  const int cpl = (s.n3 + kWC - 1) / kWC;
+  const long long nchunks = (long long)s.nb * s.n1 * s.n2 * cpl;
+  const long long c0 = nchunks * blockIdx.x / gridDim.x;
+  const long long c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
+  const float *one_src = reinterpret_cast<const float *>(IN1 ? xin : gin);
+  const uint16_t *many_src = reinterpret_cast<const uint16_t *>(IN1 ? gin : xin);
+  constexpr int kLines1 = IN1 ? 9 : 1;   // lines of the one-channel side
+  constexpr int kLinesM = IN1 ? 1 : 9;   // lines of the 32-channel side
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float accb = 0.f;
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+  for (long long ch = c0; ch < c1; ++ch) {
+    const int line = (int)(ch / cpl);
+    const int b0 = (int)(ch - (long long)line * cpl) * kWC;
+    const int i = line / s.n2, j = line - i * s.n2, il = i % s.n1;
+    __syncthreads();
+    for (int task = tid; task < kLines1 * (kWC + 2); task += kNT) {
+      const int r = task / (kWC + 2), k = task - r * (kWC + 2);
+      const int di = IN1 ? r / 3 - 1 : 0, dj = IN1 ? r % 3 - 1 : 0;
+      const int bb = b0 - 1 + k;
+      const bool ok = il + di >= 0 && il + di < s.n1 && j + dj >= 0 && j + dj < s.n2 &&
+                      bb >= 0 && bb < s.n3;
+      one[r][k] = ok ? one_src[((i + di) * s.n2 + (j + dj)) * s.n3 + bb] : 0.f;
+    }
+    for (int task = tid; task < kLinesM * kWC * 4; task += kNT) {
+      const int r = task / (kWC * 4), k = (task >> 2) % kWC, q = task & 3;
+      const int di = IN1 ? 0 : r / 3 - 1, dj = IN1 ? 0 : r % 3 - 1;
+      const int bb = b0 + k;
+      const bool ok = il + di >= 0 && il + di < s.n1 && j + dj >= 0 && j + dj < s.n2 &&
+                      bb < s.n3;
+      reinterpret_cast<uint4 *>(&many[r][k][0])[q] =
+          ok ? *reinterpret_cast<const uint4 *>(
+                   many_src + ((size_t)((i + di) * s.n2 + (j + dj)) * s.n3 + bb) * 32 + 8 * q)
+             : zero4;
+    }
+    __syncthreads();
+    float reg[IN1 ? kWC : kWC + 2];
+    if constexpr (IN1) {
+#pragma unroll
+      for (int k = 0; k < kWC; ++k) reg[k] = bf2f(many[0][k][c]);
+      if (sub == 0) {
+#pragma unroll
+        for (int k = 0; k < kWC; ++k) accb += reg[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kWC + 2; ++k) reg[k] = one[0][k];
+      if (tid == 0) {
+#pragma unroll
+        for (int k = 1; k <= kWC; ++k) accb += reg[k];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int t = sub + 8 * m;
+      if (t < 27) {
+        const int r = t / 3, d = t % 3;  // d = db + 1
+        float a = 0.f;
+        if constexpr (IN1) {
+          // g at band b0 + k of the line, v at band b0 + k + db of neighbour line r
+#pragma unroll
+          for (int k = 0; k < kWC; ++k) a = fmaf(reg[k], one[r][k + d], a);
+        } else {
+          // du at band b0 + k - db of the line, x at band b0 + k of neighbour line r
+#pragma unroll
+          for (int k = 0; k < kWC; ++k) a = fmaf(reg[k + 2 - d], bf2f(many[r][k][c]), a);
+        }
+        acc[m] += a;
+      }
+    }
+  }
+  // partial layout: 864 weights (index t * 32 + c in both layers), then 32 (IN1) or 1 bias
+  float *pw = part + (size_t)blockIdx.x * (IN1 ? L::kEdge + 32 : L::kEdge + 1);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int t = sub + 8 * m;
+    if (t < 27) pw[t * 32 + c] = acc[m];
+  }
+  if (IN1 ? sub == 0 : tid == 0) pw[L::kEdge + (IN1 ? c : 0)] = accb;
+}
+
+// out[o] = sum over the nparts partials (each n floats), in a fixed order: 16 slices of the
+// parts per output (four interleaved running sums each), combined in LDS.
+__global__ __launch_bounds__(1024) void k_cnn_sum_parts(const float *part, int nparts, int n,
+                                                        float *out) {
+  __shared__ float red[16][64];
+  const int lane = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + lane;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+  if (o < n) {
+    int p = sl;
+    for (; p + 48 < nparts; p += 64) {
+      a0 += part[(size_t)p * n + o];
+      a1 += part[(size_t)(p + 16) * n + o];
+      a2 += part[(size_t)(p + 32) * n + o];
+      a3 += part[(size_t)(p + 48) * n + o];
+    }
+    for (; p < nparts; p += 16) a0 += part[(size_t)p * n + o];
+  }
+  red[sl][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (sl == 0 && o < n) {
     float a = 0.f;
-    for (int p = 0; p < nparts; ++p) a += part[(size_t)p * n + k];
-    out[k] = a;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) a += red[k][lane];
+    out[o] = a;
   }
 }
 
@@ -442,27 +604,46 @@ hipError_t cnn_layer_out_bwd(const CnnShape &s, const float *du, const float *ed
   return hipGetLastError();
 }
 
-int cnn_wgrad_parts(const CnnShape &s) {
-  const int g = grid_for(s.N, 1024);
-  return g > 1024 ? 1024 : g;
+namespace {
+int mid_parts(const CnnShape &s) {
+  const long long chunks = (long long)s.nb * s.n1 * s.n2 * ((s.n3 + kWC - 1) / kWC);
+  const long long p = (chunks + 31) / 32;
+  return (int)(p < 1 ? 1 : p > 1024 ? 1024 : p);
+}
+int edge_parts(const CnnShape &s) {
+  const long long chunks = (long long)s.nb * s.n1 * s.n2 * ((s.n3 + kWC - 1) / kWC);
+  const long long p = (chunks + 15) / 16;
+  return (int)(p < 1 ? 1 : p > 4096 ? 4096 : p);
+}
+}  // namespace
+
+size_t cnn_wgrad_part_floats(const CnnShape &s) {
+  const size_t a = (size_t)mid_parts(s) * (L::kMid + 32);
+  const size_t b = (size_t)edge_parts(s) * (L::kEdge + 32);
+  return a > b ? a : b;
 }
 
 hipError_t cnn_wgrad(const CnnShape &s, int cin, int cout, const void *x, const void *g,
                      float *part, float *out, hipStream_t st) {
-  const int np = cnn_wgrad_parts(s);
-  if (cin == 1 && cout == 32)
-    hipLaunchKernelGGL((k_cnn_wgrad<1, 32>), dim3(np), dim3(kNT), 0, st, s, x, g, part);
-  else if (cin == 32 && cout == 32)
-    hipLaunchKernelGGL((k_cnn_wgrad<32, 32>), dim3(np), dim3(kNT), 0, st, s, x, g, part);
-  else if (cin == 32 && cout == 1)
-    hipLaunchKernelGGL((k_cnn_wgrad<32, 1>), dim3(np), dim3(kNT), 0, st, s, x, g, part);
-  else
+  int np;
+  if (cin == 32 && cout == 32) {
+    np = mid_parts(s);
+    hipLaunchKernelGGL(k_cnn_wgrad_mid, dim3(np), dim3(kNT), 0, st, s, (const uint16_t *)x,
+                       (const uint16_t *)g, part);
+  } else if (cin == 1 && cout == 32) {
+    np = edge_parts(s);
+    hipLaunchKernelGGL(k_cnn_wgrad_edge<true>, dim3(np), dim3(kNT), 0, st, s, x, g, part);
+  } else if (cin == 32 && cout == 1) {
+    np = edge_parts(s);
+    hipLaunchKernelGGL(k_cnn_wgrad_edge<false>, dim3(np), dim3(kNT), 0, st, s, x, g, part);
+  } else {
     return hipErrorInvalidValue;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = 27 * cout * cin + cout;
-  hipLaunchKernelGGL(k_cnn_sum_parts, dim3(grid_for(n, kNT)), dim3(kNT), 0, st,
-                     (const float *)part, np, n, out);
+  hipLaunchKernelGGL(k_cnn_sum_parts, dim3((n + 63) / 64), dim3(1024), 0, st, (const float *)part,
+                     np, n, out);
   return hipGetLastError();
 }
 

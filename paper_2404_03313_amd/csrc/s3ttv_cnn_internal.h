@@ -45,7 +45,7 @@ hipError_t cnn_layer_out(const CnnShape &s, const uint16_t *x, const float *edge
                          double *loss, hipStream_t st);
 hipError_t cnn_layer_out_bwd(const CnnShape &s, const float *du, const float *edge,
                              const uint16_t *x, uint16_t *dx, hipStream_t st);
-int cnn_wgrad_parts(const CnnShape &s);
+size_t cnn_wgrad_part_floats(const CnnShape &s);
 hipError_t cnn_wgrad(const CnnShape &s, int cin, int cout, const void *x, const void *g,
                      float *part, float *out, hipStream_t st);
 hipError_t cnn_adam(float *w, float *m, float *v, const float *g, int n, float lr, int step,

@@ -6,6 +6,7 @@ only sequences calls, draws seeded mini-batch orders and moves tensors.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import time
 from typing import List, Optional
 
@@ -32,10 +33,16 @@ def make_pairs(cfgs: List[synth.HSIConfig], k=(4, 4), rel_tol: float = 1e-5,
     ws = None
     iters = []
     t0 = time.time()
-    for g0 in range(0, n, group):
+    starts = list(range(0, n, group))
+    # the host builds the next group's scenes while the device solves the current one
+    ex = cf.ThreadPoolExecutor(max_workers=4)
+    pending = [ex.submit(synth.make_hsi, c) for c in cfgs[:group]]
+    for gi, g0 in enumerate(starts):
+        data = [f.result() for f in pending]
+        nxt = cfgs[g0 + group:g0 + 2 * group]
+        pending = [ex.submit(synth.make_hsi, c) for c in nxt]
         probs = []
-        for i in range(g0, min(n, g0 + group)):
-            d = synth.make_hsi(cfgs[i])
+        for i, d in enumerate(data, start=g0):
             V[i].copy_(torch.from_numpy(d["v"]))
             prm = nt.make_params(max_iter=max_iter, rel_tol=rel_tol, **d["radii"])
             probs.append(dict(v=V[i], k1=k[0], k2=k[1], params=prm))
@@ -49,6 +56,7 @@ def make_pairs(cfgs: List[synth.HSIConfig], k=(4, 4), rel_tol: float = 1e-5,
         if log:
             log(f"pairs {min(n, g0 + group)}/{n}: {time.time() - t0:.1f} s, "
                 f"mean iterations {np.mean(iters):.0f}")
+    ex.shutdown()
     return V, U, iters
 
 
@@ -103,12 +111,12 @@ class Trainer:
 
 
 def solve_cold_warm(v, radii: dict, params, k=(4, 4), rel_tol: float = 1e-4,
-                    max_iter: int = 5000):
+                    max_iter: int = 5000, solver: Optional[nt.Solver] = None):
     """Solve one scene from u0 = 0 and from u0 = v + f(v); returns a dict with both results,
-    their statistics and the network's own time."""
+    their statistics and the network's own time (the warm time includes it)."""
     torch = _torch()
     n1, n2, n3 = v.shape
-    sv = nt.Solver(n1, n2, n3, k[0], k[1], device=v.device)
+    sv = solver or nt.Solver(n1, n2, n3, k[0], k[1], device=v.device)
     prm = nt.make_params(max_iter=max_iter, rel_tol=rel_tol, **radii)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
