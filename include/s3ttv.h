@@ -143,6 +143,15 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
                     const float *u0, float *u, float *s, float *t, void *workspace,
                     size_t workspace_bytes, void *stream, s3ttv_stats *stats);
 
+/* As s3ttv_solve, with optional starting values for the sparse and stripe components as well
+ * (Alg. 1 leaves every initial value free): u0, s0, t0 are device cubes or null (zero start);
+ * they are read once, checked for NaN/Inf (ENONFINITE) and may alias nothing the call
+ * writes. The dual variables start at zero. */
+int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                         const float *u0, const float *s0, const float *t0, float *u, float *s,
+                         float *t, void *workspace, size_t workspace_bytes, void *stream,
+                         s3ttv_stats *stats);
+
 /* ---------------- Batched solve ---------------- */
 
 /* Bytes of device workspace s3ttv_solve_batched needs for n problems of the given shapes

@@ -61,6 +61,7 @@ def lib():
         L.ora_s3ttv.argtypes = [ctypes.c_int] * 5 + [_dp]
         L.ora_s3ttv.restype = ctypes.c_double
         L.ora_solve.argtypes = [_ip, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                _dp, _dp,
                                 _dp, _dp]
         L.ora_solve.restype = ctypes.c_int
         L.ora_set_threads.argtypes = [ctypes.c_int]
@@ -221,8 +222,10 @@ def default_gammas(k1: int, k2: int) -> dict:
 
 def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: int,
           mu_min: float = 0.0, mu_max: float = 1.0, gammas: Optional[dict] = None,
-          rel_tol: float = 0.0, u0=None, trace: bool = False, duals: bool = False) -> dict:
-    """Alg. 1 in float64. Returns dict(u, s, t, stats[, trace][, Y, y2, y3])."""
+          rel_tol: float = 0.0, u0=None, trace: bool = False, duals: bool = False,
+          s0=None, t0=None) -> dict:
+    """Alg. 1 in float64. Returns dict(u, s, t, stats[, trace][, Y, y2, y3]).
+    u0, s0, t0: optional initial values (zero when None); the duals start at zero."""
     v = _f64(v)
     n1, n2, n3 = v.shape
     g = gammas or {}
@@ -240,8 +243,10 @@ def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: 
     y2 = np.empty_like(v) if duals else None
     y3 = np.empty_like(v) if duals else None
     u0a = _f64(u0) if u0 is not None else None
-    rc = lib().ora_solve(dims, _p(prm), int(max_iter), _p(v), _p(u0a), _p(u), _p(s), _p(t),
-                         _p(st), _p(tr), _p(Y), _p(y2), _p(y3))
+    s0a = _f64(s0) if s0 is not None else None
+    t0a = _f64(t0) if t0 is not None else None
+    rc = lib().ora_solve(dims, _p(prm), int(max_iter), _p(v), _p(u0a), _p(s0a), _p(t0a), _p(u),
+                         _p(s), _p(t), _p(st), _p(tr), _p(Y), _p(y2), _p(y3))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     out = dict(u=u, s=s, t=t, stats=dict(iters=int(st[0]), rel_change=st[1],

@@ -392,6 +392,8 @@ double ora_s3ttv(int n1, int n2, int n3, int k1, int k2, const double *u) {
 /* prm: [0] eps [1] alpha [2] beta [3] mu_min [4] mu_max
         [5] gamma_u [6] gamma_s [7] gamma_t [8] gamma_Y [9] gamma_y2 [10] gamma_y3 [11] rel_tol
    Step sizes that are all zero select the Lemma-2 defaults.
+   Initial values (Alg. 1 leaves them free): u0, s0, t0 (nullable: zero); all duals start at
+   zero.
    dims: [0] N1 [1] N2 [2] N3 [3] k1 [4] k2.
    stats (out, 8 doubles): [0] iterations run [1] last relative change [2] converged flag
         [3] ||D_v t|| [4] ||u+s+t-v|| - eps [5] ||s||_1 - alpha [6] ||t||_1 - beta
@@ -400,8 +402,8 @@ double ora_s3ttv(int n1, int n2, int n3, int k1, int k2, const double *u) {
    Y_out, y2_out, y3_out (nullable): final dual variables (Y in the T layout).
    Returns 0, or -1 for invalid arguments. */
 int ora_solve(const int *dims, const double *prm, int max_iter, const double *v, const double *u0,
-              double *u, double *s, double *t, double *stats, double *trace, double *Y_out,
-              double *y2_out, double *y3_out) {
+              const double *s0, const double *t0, double *u, double *s, double *t,
+              double *stats, double *trace, double *Y_out, double *y2_out, double *y3_out) {
   const int n1 = dims[0], n2 = dims[1], n3 = dims[2], k1 = dims[3], k2 = dims[4];
   if (n1 < 2 || n2 < 2 || n3 < 2 || k1 < 1 || k2 < 1 || k1 > n1 || k2 > n2 || max_iter < 1)
     return -1;
@@ -435,8 +437,8 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
 
   for (size_t e = 0; e < N; ++e) {
     u[e] = u0 ? u0[e] : 0.0;
-    s[e] = 0.0;
-    t[e] = 0.0;
+    s[e] = s0 ? s0[e] : 0.0;
+    t[e] = t0 ? t0[e] : 0.0;
   }
   int it = 0, converged = 0, worst_sweeps = 0;
   double rel = 0.0;

@@ -270,7 +270,7 @@ struct Problem {
   BlockArgs ba, bw;  // block-pass arguments: cold (first iteration) and warm
   bool fused = false;
   const s3ttv_params *prm = nullptr;
-  const float *v = nullptr, *u0 = nullptr;
+  const float *v = nullptr, *u0 = nullptr, *s0 = nullptr, *t0 = nullptr;
   float *u = nullptr, *s = nullptr, *t = nullptr;
 };
 
@@ -338,8 +338,18 @@ int32_t enqueue_init(const Problem &pr, hipStream_t st) {
   } else {
     CK(launch_fill(pl.u[0], pl.N, 0.f, st));
   }
-  CK(launch_fill(pl.s, pl.N, 0.f, st));
-  CK(launch_fill(pl.t[0], pl.N, 0.f, st));
+  if (pr.s0) {
+    CK(launch_check_finite(pr.s0, pl.N, pl.sc, st));
+    CK(launch_copy(pl.s, pr.s0, pl.N, st));
+  } else {
+    CK(launch_fill(pl.s, pl.N, 0.f, st));
+  }
+  if (pr.t0) {
+    CK(launch_check_finite(pr.t0, pl.N, pl.sc, st));
+    CK(launch_copy(pl.t[0], pr.t0, pl.N, st));
+  } else {
+    CK(launch_fill(pl.t[0], pl.N, 0.f, st));
+  }
   CK(launch_fill(pl.y2, pl.N, 0.f, st));
   CK(launch_fill(pl.w, pl.N, 0.f, st));
   CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
@@ -603,9 +613,19 @@ int32_t s3ttv_workspace_bytes(const s3ttv_shape *shape, const s3ttv_params *para
 int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
                     const float *u0, float *u, float *s, float *t, void *workspace,
                     size_t workspace_bytes, void *stream, s3ttv_stats *stats) {
+  return s3ttv_solve_from(shape, params, v, u0, nullptr, nullptr, u, s, t, workspace,
+                          workspace_bytes, stream, stats);
+}
+
+int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                         const float *u0, const float *s0, const float *t0, float *u, float *s,
+                         float *t, void *workspace, size_t workspace_bytes, void *stream,
+                         s3ttv_stats *stats) {
   Problem pr;
   const int32_t prep = prepare(pr, shape, params, v, u0, u, s, t, workspace, workspace_bytes, 0, 0);
   if (prep != S3TTV_OK) return prep;
+  pr.s0 = s0;
+  pr.t0 = t0;
   CK(configure_block_kernels());
   hipStream_t st = (hipStream_t)stream;
   Timer tm{params->timing_mask, st, {}};

@@ -5,15 +5,14 @@
 // Weights: FP32 masters (Adam), BF16 working copies; biases FP32. Activations and their
 // gradients are stored in BF16, channels-last ([voxel][32]); every sum is formed in FP32.
 //
-// The 32 -> 32 layers are implicit GEMMs on v_mfma_f32_16x16x32_bf16: a wavefront forms 16
-// consecutive voxels x 16 output channels, one MFMA per tap with all 32 input channels as the
-// K = 32 dimension, so 27 MFMAs (x 2 channel halves) per tile. Lane (i + 16 kb) supplies, as
-// the A operand, input channels 8kb..8kb+7 of the neighbour of voxel i (one 16-byte load),
-// and as the B operand the weights [tap][co = i][8kb..8kb+7] from LDS. The data gradient of
-// the same layers runs through the same kernel with mirrored taps and transposed weights.
-// The 1 -> 32 and 32 -> 1 layers and the weight gradients run on FP32 VALU; weight
-// gradients are summed per workgroup over a fixed voxel range and then over workgroups in a
-// fixed order, so every result is reproducible.
+// The 32 -> 32 layers are implicit GEMMs on v_mfma_f32_16x16x32_bf16 with the 32 input
+// channels as K: workgroups stage the 9 neighbour lines of a 32-band chunk in LDS and each
+// wave keeps the weights of its taps in registers. The data gradient of these layers runs
+// through the same kernel with a mirrored, transposed weight copy; their weight gradient is a
+// contraction over voxels on the same MFMA from LDS tiles transposed to [channel][band]. The
+// 1 -> 32 and 32 -> 1 layers and their weight gradients run on FP32 VALU. Weight gradients are
+// summed per workgroup over a fixed range and then over workgroups in a fixed order, so every
+// result is reproducible.
 #include "s3ttv_cnn_internal.h"
 
 namespace s3ttv {
@@ -120,55 +119,118 @@ __global__ __launch_bounds__(kNT) void k_cnn_in(CnnShape s, const float *v, cons
 
 // ------------------------------------------------------------ 32 -> 32 on MFMA
 
-// MODE 0 (forward):       out = relu(conv(in, W) + bias), W as [tap][co][ci]
-// MODE 1 (data gradient): out = (act > 0) * conv_mirrored(in, W), W as [tap][ci][co]
+constexpr int kCB = 32;       // bands per chunk of the 32 -> 32 convolution
+constexpr int kXS = 40;       // LDS row stride (elements) of a staged voxel: 32 channels + 8
+constexpr int kRS = 33;       // row stride (floats) of the wave-partial tile
+
+// MODE 0 (forward):       out = relu(conv(in, W) + bias)
+// MODE 1 (data gradient): out = (act > 0) * conv(in, W), W the mirrored transposed copy
+//                         (tap 26 - t, [ci][co]), which turns the adjoint into a plain
+//                         convolution.
+// W: BF16 [27][32 (output channel n)][32 (input channel k)]. A workgroup takes a contiguous
+// range of chunks (32 bands b0 .. b0 + 31 of one line (i, j)). Per chunk it stages the 9
+// neighbour lines, bands b0 - 1 .. b0 + 32, channels-last in LDS; wave w owns the taps
+// t = w, w + 4, ... and keeps their weights in registers for the whole range (B operand:
+// lane (n, kb) holds W[t][n][8kb .. 8kb + 7]). A tap is then, per 16-band half and 16-channel
+// half, one MFMA whose A operand (lane (m, kb): channels 8kb .. 8kb + 7 of band b0 + m + db of
+// line t / 3) is one 16-byte LDS read. The four waves' partial tiles are summed in LDS in a
+// fixed order and the epilogue (bias + ReLU, or the ReLU mask) writes 8 bytes per thread.
 template <int MODE>
-__global__ __launch_bounds__(kNT) void k_cnn_mid(CnnShape s, const uint16_t *in, const uint16_t *W,
-                                                 const float *bias, const uint16_t *act,
-                                                 uint16_t *out) {
-  __shared__ __align__(16) uint16_t w[L::kMid];
-  for (int k = threadIdx.x; k < L::kMid / 8; k += kNT)
-    reinterpret_cast<uint4 *>(w)[k] = reinterpret_cast<const uint4 *>(W)[k];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, kb = lane >> 4;
-  const int ntiles = (s.N + 15) / 16;
-  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
-    const int e = tile * 16 + i;  // voxel of this lane's A-operand row
-    const bool valid = e < s.N;
-    const Vox p = vox_of(valid ? e : 0, s);
-    f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-    for (int t = 0; t < 27; ++t) {
-      const int q = valid ? neighbour(p, t, s, MODE == 1) : -1;
-      bf8 a;
-      if (q >= 0) {
-        a = *reinterpret_cast<const bf8 *>(in + (size_t)q * 32 + 8 * kb);
-      } else {
+__global__ __launch_bounds__(kNT) void k_cnn_conv32(CnnShape s, const uint16_t *in,
+                                                    const uint16_t *W, const float *bias,
+                                                    const uint16_t *act, uint16_t *out) {
+  __shared__ __align__(16) uint16_t xs[9 * (kCB + 2) * kXS];
+  __shared__ float red[4][kCB * kRS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kb = lane >> 4;
+  bf8 wb[7][2];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) a[k] = (__bf16)0.f;
-      }
-      const bf8 b0 = *reinterpret_cast<const bf8 *>(w + (t * 32 + i) * 32 + 8 * kb);
-      const bf8 b1 = *reinterpret_cast<const bf8 *>(w + (t * 32 + 16 + i) * 32 + 8 * kb);
-      acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc1, 0, 0, 0);
+  for (int m = 0; m < 7; ++m) {
+    const int t = wave + 4 * m < 27 ? wave + 4 * m : 26;
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+      wb[m][nt] = *reinterpret_cast<const bf8 *>(W + (t * 32 + nt * 16 + li) * 32 + 8 * kb);
+  }
+  // epilogue ownership: voxel ev = tid / 8 of the chunk, channels 4 ec .. 4 ec + 3
+  const int ev = tid >> 3, ec = tid & 7;
+  float bv[4] = {0.f, 0.f, 0.f, 0.f};
+  if (MODE == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) bv[k] = bias[4 * ec + k];
+  }
+  const int cpl = (s.n3 + kCB - 1) / kCB;
+  const long long nchunks = (long long)s.nb * s.n1 * s.n2 * cpl;
+  const long long c0 = nchunks * blockIdx.x / gridDim.x;
+  const long long c1 = nchunks * (blockIdx.x + 1) / gridDim.x;
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+  for (long long c = c0; c < c1; ++c) {
+    const int line = (int)(c / cpl);
+    const int b0 = (int)(c - (long long)line * cpl) * kCB;
+    const int i = line / s.n2, j = line - i * s.n2, il = i % s.n1;
+    __syncthreads();  // xs and red of the previous chunk are no longer read
+    for (int task = tid; task < 9 * (kCB + 2) * 4; task += kNT) {
+      const int r = task / ((kCB + 2) * 4), rem = task - r * ((kCB + 2) * 4);
+      const int k = rem >> 2, q = rem & 3;
+      const int di = r / 3 - 1, dj = r % 3 - 1, bb = b0 - 1 + k;
+      const bool ok = il + di >= 0 && il + di < s.n1 && j + dj >= 0 && j + dj < s.n2 &&
+                      bb >= 0 && bb < s.n3;
+      uint4 val = zero4;
+      if (ok)
+        val = *reinterpret_cast<const uint4 *>(
+            in + ((size_t)((i + di) * s.n2 + (j + dj)) * s.n3 + bb) * 32 + 8 * q);
+      *reinterpret_cast<uint4 *>(xs + (r * (kCB + 2) + k) * kXS + 8 * q) = val;
     }
-    // result lane (c, g), register r: voxel 4g + r of the tile, output channel c (and 16 + c)
-    const int c = lane & 15, g = lane >> 4;
+    __syncthreads();
+    f4 acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int eo = tile * 16 + 4 * g + r;
-      if (eo >= s.N) continue;
-      float y0 = acc0[r], y1 = acc1[r];
-      if (MODE == 0) {
-        y0 = fmaxf(y0 + bias[c], 0.f);
-        y1 = fmaxf(y1 + bias[16 + c], 0.f);
-      } else {
-        if (!(bf2f(act[(size_t)eo * 32 + c]) > 0.f)) y0 = 0.f;
-        if (!(bf2f(act[(size_t)eo * 32 + 16 + c]) > 0.f)) y1 = 0.f;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+      const int t = wave + 4 * m;
+      if (t < 27) {
+        const int r = t / 3, d = t % 3;  // band b0 + m' + db sits at staged index m' + d
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const bf8 a = *reinterpret_cast<const bf8 *>(
+              xs + (r * (kCB + 2) + mt * 16 + li + d) * kXS + 8 * kb);
+          acc[mt][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[m][0], acc[mt][0], 0, 0, 0);
+          acc[mt][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wb[m][1], acc[mt][1], 0, 0, 0);
+        }
       }
-      out[(size_t)eo * 32 + c] = f2bf(y0);
-      out[(size_t)eo * 32 + 16 + c] = f2bf(y1);
+    }
+    // result lane (c = li, g = kb), register rr: band mt*16 + 4g + rr, channel nt*16 + c
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          red[wave][(mt * 16 + 4 * kb + rr) * kRS + nt * 16 + li] = acc[mt][nt][rr];
+    __syncthreads();
+    const int bb = b0 + ev;
+    if (bb < s.n3) {
+      const size_t e = (size_t)line * s.n3 + bb;
+      float y[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int o = ev * kRS + 4 * ec + k;
+        y[k] = ((red[0][o] + red[1][o]) + (red[2][o] + red[3][o])) + bv[k];
+      }
+      if (MODE == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) y[k] = fmaxf(y[k], 0.f);
+      } else {
+        const uint2 am = *reinterpret_cast<const uint2 *>(act + e * 32 + 4 * ec);
+        if (!(bf2f((uint16_t)(am.x & 0xffffu)) > 0.f)) y[0] = 0.f;
+        if (!(bf2f((uint16_t)(am.x >> 16)) > 0.f)) y[1] = 0.f;
+        if (!(bf2f((uint16_t)(am.y & 0xffffu)) > 0.f)) y[2] = 0.f;
+        if (!(bf2f((uint16_t)(am.y >> 16)) > 0.f)) y[3] = 0.f;
+      }
+      *reinterpret_cast<uint2 *>(out + e * 32 + 4 * ec) =
+          make_uint2((uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16),
+                     (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16));
     }
   }
 }
@@ -378,8 +440,7 @@ __global__ __launch_bounds__(kNT) void k_cnn_wgrad_mid(CnnShape s, const uint16_
 // 32 -> 32 kernel). LDS holds the one-channel side with a band halo of one (IN1: v on the 9
 // neighbour lines; else du on the line itself) and the 32-channel side channels-last (IN1:
 // g on the line; else x on the 9 neighbour lines). Thread (c = tid % 32, sub = tid / 32) owns
-// the taps t = sub, sub + 8, ... and keeps its 32 values of the line-side operand in
-// registers for the chunk.
+// the taps t = sub, sub + 8, ...
 template <bool IN1>
 __global__ __launch_bounds__(kNT) void k_cnn_wgrad_edge(CnnShape s, const void *xin,
                                                         const void *gin, float *part) {
@@ -416,13 +477,16 @@ __global__ __launch_bounds__(kNT) void k_cnn_wgrad_edge(CnnShape s, const void *
       const int bb = b0 + k;
       const bool ok = il + di >= 0 && il + di < s.n1 && j + dj >= 0 && j + dj < s.n2 &&
                       bb < s.n3;
-      reinterpret_cast<uint4 *>(&many[r][k][0])[q] =
-          ok ? *reinterpret_cast<const uint4 *>(
-                   many_src + ((size_t)((i + di) * s.n2 + (j + dj)) * s.n3 + bb) * 32 + 8 * q)
-             : zero4;
+      uint4 val = zero4;
+      if (ok)
+        val = *reinterpret_cast<const uint4 *>(
+            many_src + ((size_t)((i + di) * s.n2 + (j + dj)) * s.n3 + bb) * 32 + 8 * q);
+      reinterpret_cast<uint4 *>(&many[r][k][0])[q] = val;
     }
     __syncthreads();
-    float reg[IN1 ? kWC : kWC + 2];
+    // the 32-channel operand of the line (IN1) stays in registers for all taps; the other
+    // operands are read from LDS (the band shift d varies per thread, so it indexes LDS)
+    float reg[kWC];
     if constexpr (IN1) {
 #pragma unroll
       for (int k = 0; k < kWC; ++k) reg[k] = bf2f(many[0][k][c]);
@@ -430,13 +494,9 @@ __global__ __launch_bounds__(kNT) void k_cnn_wgrad_edge(CnnShape s, const void *
 #pragma unroll
         for (int k = 0; k < kWC; ++k) accb += reg[k];
       }
-    } else {
+    } else if (tid == 0) {
 #pragma unroll
-      for (int k = 0; k < kWC + 2; ++k) reg[k] = one[0][k];
-      if (tid == 0) {
-#pragma unroll
-        for (int k = 1; k <= kWC; ++k) accb += reg[k];
-      }
+      for (int k = 1; k <= kWC; ++k) accb += one[0][k];
     }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -451,7 +511,7 @@ __global__ __launch_bounds__(kNT) void k_cnn_wgrad_edge(CnnShape s, const void *
         } else {
           // du at band b0 + k - db of the line, x at band b0 + k of neighbour line r
 #pragma unroll
-          for (int k = 0; k < kWC; ++k) a = fmaf(reg[k + 2 - d], bf2f(many[r][k][c]), a);
+          for (int k = 0; k < kWC; ++k) a = fmaf(one[0][k + 2 - d], bf2f(many[r][k][c]), a);
         }
         acc[m] += a;
       }
@@ -511,8 +571,9 @@ __global__ __launch_bounds__(kNT) void k_cnn_adam(float *w, float *m, float *v, 
 }
 
 // Working copies of the masters: the edge layers as BF16-rounded FP32 weights plus FP32
-// biases; the 32 -> 32 weights as BF16 in forward order [t][co][ci] and transposed [t][ci][co]
-// for the data gradient (skipped when bwd is null).
+// biases; the 32 -> 32 weights as BF16 in forward order [t][co][ci] and, for the data
+// gradient, mirrored and transposed: bwd[26 - t][ci][co] = W[t][co][ci] (skipped when bwd is
+// null).
 __global__ __launch_bounds__(kNT) void k_cnn_copies(const float *master, float *edge,
                                                     uint16_t *fwd, uint16_t *bwd) {
   for (int k = blockIdx.x * kNT + threadIdx.x; k < L::total; k += gridDim.x * kNT) {
@@ -532,7 +593,7 @@ __global__ __launch_bounds__(kNT) void k_cnn_copies(const float *master, float *
         const int t = o / 1024, co = (o / 32) % 32, ci = o % 32;
         const uint16_t h = f2bf(x);
         fwd[l * L::kMid + o] = h;
-        if (bwd) bwd[l * L::kMid + t * 1024 + ci * 32 + co] = h;
+        if (bwd) bwd[l * L::kMid + (26 - t) * 1024 + ci * 32 + co] = h;
       }
     }
   }
@@ -562,17 +623,25 @@ hipError_t cnn_layer_in(const CnnShape &s, const float *v, const float *edge, ui
   return hipGetLastError();
 }
 
+namespace {
+int conv32_grid(const CnnShape &s) {
+  const long long chunks = (long long)s.nb * s.n1 * s.n2 * ((s.n3 + kCB - 1) / kCB);
+  const long long g = (chunks + 3) / 4;
+  return (int)(g < 1 ? 1 : g > 4096 ? 4096 : g);
+}
+}  // namespace
+
 hipError_t cnn_layer_mid(const CnnShape &s, const uint16_t *in, const uint16_t *W,
                          const float *bias, uint16_t *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_cnn_mid<0>, dim3(grid_for((s.N + 15) / 16, 4 * 8)), dim3(kNT), 0, st, s,
-                     in, W, bias, (const uint16_t *)nullptr, out);
+  hipLaunchKernelGGL(k_cnn_conv32<0>, dim3(conv32_grid(s)), dim3(kNT), 0, st, s, in, W, bias,
+                     (const uint16_t *)nullptr, out);
   return hipGetLastError();
 }
 
 hipError_t cnn_layer_mid_bwd(const CnnShape &s, const uint16_t *gin, const uint16_t *Wt,
                              const uint16_t *act, uint16_t *gout, hipStream_t st) {
-  hipLaunchKernelGGL(k_cnn_mid<1>, dim3(grid_for((s.N + 15) / 16, 4 * 8)), dim3(kNT), 0, st, s,
-                     gin, Wt, (const float *)nullptr, act, gout);
+  hipLaunchKernelGGL(k_cnn_conv32<1>, dim3(conv32_grid(s)), dim3(kNT), 0, st, s, gin, Wt,
+                     (const float *)nullptr, act, gout);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", 
 N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 
-EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
+EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_solve_from", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
            "s3ttv_op_grad", "s3ttv_op_grad_adj", "s3ttv_op_spectral_clip",
            "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_batch_workspace_bytes",
            "s3ttv_solve_batched", "s3ttv_cnn_param_count", "s3ttv_cnn_workspace_bytes",
@@ -82,6 +82,8 @@ def lib():
                                             ctypes.POINTER(sz)]
         L.s3ttv_solve.argtypes = [ctypes.POINTER(Shape), ctypes.POINTER(Params), vp, vp, vp, vp, vp,
                                   vp, sz, vp, ctypes.POINTER(Stats)]
+        L.s3ttv_solve_from.argtypes = [ctypes.POINTER(Shape), ctypes.POINTER(Params), vp, vp, vp,
+                                       vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Stats)]
         L.s3ttv_strerror.argtypes = [ctypes.c_int32]
         L.s3ttv_strerror.restype = ctypes.c_char_p
         L.s3ttv_op_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
@@ -190,7 +192,8 @@ class Solver:
         self.device = device
         self.ws = _workspace(workspace_bytes(n1, n2, n3, k1, k2), device)
 
-    def solve(self, v, params: Params, u0=None, out=None):
+    def solve(self, v, params: Params, u0=None, out=None, s0=None, t0=None):
+        """s3ttv_solve, or s3ttv_solve_from when s0 or t0 is given."""
         torch = _torch()
         if tuple(v.shape) != self.dims:
             raise ValueError(f"v has shape {tuple(v.shape)}, expected {self.dims}")
@@ -198,11 +201,20 @@ class Solver:
             out = tuple(torch.empty_like(v) for _ in range(3))
         u, s, t = out
         st = Stats()
-        rc = lib().s3ttv_solve(ctypes.byref(self.shape), ctypes.byref(params), _dev_ptr(v, "v"),
-                               _dev_ptr(u0, "u0"), _dev_ptr(u, "u"), _dev_ptr(s, "s"),
-                               _dev_ptr(t, "t"), ctypes.c_void_p(self.ws.data_ptr()),
-                               ctypes.c_size_t(self.ws.numel()), _stream(), ctypes.byref(st))
-        _check(rc, "s3ttv_solve", allow=(OK, NOT_CONVERGED))
+        ws = (ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()), _stream(),
+              ctypes.byref(st))
+        if s0 is None and t0 is None:
+            name = "s3ttv_solve"
+            rc = lib().s3ttv_solve(ctypes.byref(self.shape), ctypes.byref(params),
+                                   _dev_ptr(v, "v"), _dev_ptr(u0, "u0"), _dev_ptr(u, "u"),
+                                   _dev_ptr(s, "s"), _dev_ptr(t, "t"), *ws)
+        else:
+            name = "s3ttv_solve_from"
+            rc = lib().s3ttv_solve_from(ctypes.byref(self.shape), ctypes.byref(params),
+                                        _dev_ptr(v, "v"), _dev_ptr(u0, "u0"), _dev_ptr(s0, "s0"),
+                                        _dev_ptr(t0, "t0"), _dev_ptr(u, "u"), _dev_ptr(s, "s"),
+                                        _dev_ptr(t, "t"), *ws)
+        _check(rc, name, allow=(OK, NOT_CONVERGED))
         return u, s, t, _stats_dict(st, rc)
 
 
@@ -256,11 +268,11 @@ def solve_batched(problems, workspace=None):
     return [(o[0], o[1], o[2], _stats_dict(st[i], st[i].status)) for i, o in enumerate(outs)], rc
 
 
-def solve(v, k1, k2, eps, alpha, beta, max_iter, u0=None, **kw):
+def solve(v, k1, k2, eps, alpha, beta, max_iter, u0=None, s0=None, t0=None, **kw):
     """One-shot solve of Prob. (18) by Alg. 1 on the GPU; returns (u, s, t, stats)."""
     n1, n2, n3 = v.shape
     sv = Solver(n1, n2, n3, k1, k2, device=v.device)
-    return sv.solve(v, make_params(eps, alpha, beta, max_iter, **kw), u0=u0)
+    return sv.solve(v, make_params(eps, alpha, beta, max_iter, **kw), u0=u0, s0=s0, t0=t0)
 
 
 # ---------------------------------------------------------------- operator entry points

@@ -36,8 +36,9 @@ def _parity(device, d, k, iters, tol=1e-4, **kw):
     v = d["v"]
     u, s, t, st = nt.solve(_t(v, device), k1, k2, max_iter=iters, **d["radii"], **kw)
     kw_o = {key: val for key, val in kw.items() if key in ("rel_tol", "gammas")}
-    if "u0" in kw:
-        kw_o["u0"] = _np(kw["u0"])
+    for key in ("u0", "s0", "t0"):
+        if key in kw:
+            kw_o[key] = _np(kw[key])
     r = oracle.solve(d["v64"], k1, k2, max_iter=iters, **d["radii"], **kw_o)
     errs = {name: rel_l2(_np(g), r[name]) for name, g in (("u", u), ("s", s), ("t", t))}
     _say("rel L2 vs oracle:", errs, "gpu iters", st["iters"], "oracle iters", r["stats"]["iters"],
@@ -81,6 +82,25 @@ def test_solve_parity_custom_steps_and_warm_start(device):
     g["gamma_u"] = 1.0 / (8 * 16 * 4 + 1)   # the printed (more conservative) value of eq. stepsize_denoising
     u0 = _t(np.clip(d["v"], 0, 1), device)
     _parity(device, d, (2, 2), 40, gammas=g, u0=u0)
+
+
+def test_solve_from_primal_starts(device):
+    """s3ttv_solve_from: u0, s0 and t0 all given (Alg. 1 leaves every initial value free)."""
+    _say("solve from u0, s0, t0")
+    cfg = synth.HSIConfig(14, 12, 9, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=13)
+    d = synth.make_hsi(cfg)
+    rng = np.random.Generator(np.random.PCG64(14))
+    v = d["v"].astype(np.float64)
+    u0 = np.clip(v, 0, 1)
+    r = v - u0 + rng.normal(0, 0.05, size=v.shape)
+    s0 = np.where(np.abs(r) > 0.1, r, 0.0)
+    t0 = np.broadcast_to(rng.uniform(-0.2, 0.2, size=(1,) + v.shape[1:]), v.shape)
+    _parity(device, d, (2, 2), 50, u0=_t(u0, device), s0=_t(s0, device), t0=_t(t0, device))
+    bad = s0.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(nt.S3TTVError) as e:
+        nt.solve(_t(d["v"], device), 2, 2, max_iter=5, **d["radii"], s0=_t(bad, device))
+    assert e.value.code == nt.ENONFINITE
 
 
 @pytest.mark.parametrize("steps", [-1, 1])
