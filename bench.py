@@ -258,6 +258,64 @@ def bench_warm_start(nt, synth, torch, args) -> int:
     return 0
 
 
+CNN_FLOP_PER_VOXEL = 2 * 27 * (32 + 3 * 32 * 32 + 32)   # forward: 1->32, 3 x 32->32, 32->1
+
+
+def bench_cnn(nt, synth, torch, args) -> int:
+    """Network kernels alone: Adam steps at batch 8 x 64^3 and the forward pass over the
+    512 x 512 x 191 scene, timed with events on the stream the kernels run on."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    rng = np.random.Generator(np.random.PCG64(7))
+    v = torch.from_numpy(rng.uniform(0, 1, size=(8, 64, 64, 64)).astype(np.float32)).to(dev)
+    tgt = (v + 0.05 * torch.randn(v.shape, generator=torch.Generator(device=dev).manual_seed(8),
+                                  device=dev)).contiguous()
+    params = torch.from_numpy(synth.cnn_init(0)).to(dev)
+    m, v2 = torch.zeros_like(params), torch.zeros_like(params)
+    ws = nt._workspace(nt.cnn_workspace_bytes(v.shape, True), dev)
+    for k in range(1, args.warmup + 1):
+        nt.cnn_train_step(params, m, v2, k, 1e-3, v, tgt, workspace=ws)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(args.warmup + 1, args.warmup + args.steps + 1):
+        nt.cnn_train_step(params, m, v2, k, 1e-3, v, tgt, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / args.steps
+    cfg = synth.WORKLOADS["c5"]["cfg"]
+    big = torch.from_numpy(rng.uniform(0, 1, size=(cfg.n1, cfg.n2, cfg.n3)).astype(np.float32)).to(dev)
+    wsb = nt._workspace(nt.cnn_workspace_bytes(big.shape, False), dev)
+    out = torch.empty_like(big)
+    nt.cnn_forward(params, big, out=out, workspace=wsb)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        e0.record()
+        nt.cnn_forward(params, big, out=out, workspace=wsb)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    fwd_ms = min(times)
+    nvox = big.numel()
+    achieved = CNN_FLOP_PER_VOXEL * nvox / (fwd_ms * 1e-3) / 1e12
+    res = {
+        "metric": "initial-estimate network: Adam step (batch 8 x 64^3) and forward (512x512x191)",
+        "value": 1e3 / step_ms, "unit": "train steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": step_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (fp32 sums)", "data": "synthetic",
+        "config": {"workload": "CNN 1-32-32-32-32-1, 3x3x3, train batch 8 x 64^3, forward "
+                               f"{cfg.n1}x{cfg.n2}x{cfg.n3}"},
+        "forward_ms": fwd_ms,
+        "roofline": {"kernel": "whole forward pass (dominated by k_cnn_conv32<0>)",
+                     "bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "flop_per_voxel": CNN_FLOP_PER_VOXEL},
+    }
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,9 +325,10 @@ def main() -> int:
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol-cap", type=int, default=20000)
     ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "cnn"], default="c2",
                     help="c2: the single 256x256x128 image (default); c4: the uneven batch of 24; "
-                         "c5: learned initial estimate vs zero start on 512x512x191")
+                         "c5: learned initial estimate vs zero start on 512x512x191; cnn: the "
+                         "network kernels alone")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
     ap.add_argument("--train-steps", type=int, default=2500, help="c5: Adam steps (batch 8)")
     ap.add_argument("--ref-iters", type=int, default=10000,
@@ -295,6 +354,8 @@ def main() -> int:
         return bench_batched(nt, synth, torch, prec)
     if args.workload == "c5":
         return bench_warm_start(nt, synth, torch, args)
+    if args.workload == "cnn":
+        return bench_cnn(nt, synth, torch, args)
     w = synth.WORKLOADS["c2"]
     cfg = w["cfg"]
     k1, k2 = w["k"]
