@@ -61,8 +61,7 @@ def lib():
         L.ora_s3ttv.argtypes = [ctypes.c_int] * 5 + [_dp]
         L.ora_s3ttv.restype = ctypes.c_double
         L.ora_solve.argtypes = [_ip, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                _dp, _dp,
-                                _dp, _dp]
+                                _dp, _dp, _dp, _dp, _dp]
         L.ora_solve.restype = ctypes.c_int
         L.ora_set_threads.argtypes = [ctypes.c_int]
         L.ora_get_threads.restype = ctypes.c_int
@@ -214,39 +213,52 @@ def s3ttv(u, k1: int, k2: int) -> float:
     return float(lib().ora_s3ttv(*u.shape, k1, k2, _p(u)))
 
 
-def default_gammas(k1: int, k2: int) -> dict:
+REGULARIZERS = {"s3ttv": 0, "stv": 1, "sstv": 2, "hsstv": 3}
+
+
+def default_gammas(k1: int, k2: int, regularizer: str = "s3ttv", omega: float = 0.05) -> dict:
+    """Lemma-2 step sizes for the stacked operator. S3TTV: column sums 8K+1, 1, 3; row sums 4,
+    2, 3. STV (blocks of D u): 4K+1 and block rows 2. SSTV (||D D_s u||_1): 9 and rows 4.
+    HSSTV (+ omega ||D u||_1): 9 + 4 omega; its second field steps with 1/(2 omega)."""
     K = k1 * k2
-    return dict(gamma_u=1.0 / (8 * K + 1), gamma_s=1.0, gamma_t=1.0 / 3, gamma_Y=0.25,
-                gamma_y2=0.5, gamma_y3=1.0 / 3)
+    g_u = {"s3ttv": 1.0 / (8 * K + 1), "stv": 1.0 / (4 * K + 1), "sstv": 1.0 / 9,
+           "hsstv": 1.0 / (9 + 4 * omega)}[regularizer]
+    return dict(gamma_u=g_u, gamma_s=1.0, gamma_t=1.0 / 3,
+                gamma_Y=0.5 if regularizer == "stv" else 0.25, gamma_y2=0.5, gamma_y3=1.0 / 3)
 
 
 def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: int,
           mu_min: float = 0.0, mu_max: float = 1.0, gammas: Optional[dict] = None,
           rel_tol: float = 0.0, u0=None, trace: bool = False, duals: bool = False,
-          s0=None, t0=None) -> dict:
-    """Alg. 1 in float64. Returns dict(u, s, t, stats[, trace][, Y, y2, y3]).
-    u0, s0, t0: optional initial values (zero when None); the duals start at zero."""
+          s0=None, t0=None, regularizer: str = "s3ttv", omega: float = 0.05) -> dict:
+    """Alg. 1 in float64. Returns dict(u, s, t, stats[, trace][, Y or Z, y2, y3]).
+    u0, s0, t0: optional initial values (zero when None); the duals start at zero.
+    regularizer: "s3ttv" (Prob. (18)), or the compared P-PDS-applicable terms "stv",
+    "sstv", "hsstv" (weight omega) in its place (Sec. IV-A). Z (SSTV, HSSTV): the dual
+    fields (z1v, z1h, z2v, z2h) stacked, shape (4, N1, N2, N3)."""
+    reg = REGULARIZERS[regularizer]
     v = _f64(v)
     n1, n2, n3 = v.shape
     g = gammas or {}
     prm = np.array([eps, alpha, beta, mu_min, mu_max,
                     g.get("gamma_u", 0.0), g.get("gamma_s", 0.0), g.get("gamma_t", 0.0),
                     g.get("gamma_Y", 0.0), g.get("gamma_y2", 0.0), g.get("gamma_y3", 0.0),
-                    rel_tol], dtype=np.float64)
+                    rel_tol, reg, omega], dtype=np.float64)
     dims = (ctypes.c_int * 5)(n1, n2, n3, k1, k2)
     u = np.empty_like(v)
     s = np.empty_like(v)
     t = np.empty_like(v)
     st = np.zeros(8)
     tr = np.zeros(max_iter) if trace else None
-    Y = np.empty((n1 * n2, k1 * k2, 2 * n3)) if duals else None
+    Y = np.empty((n1 * n2, k1 * k2, 2 * n3)) if duals and reg <= 1 else None
+    Z = np.empty((4,) + v.shape) if duals and reg >= 2 else None
     y2 = np.empty_like(v) if duals else None
     y3 = np.empty_like(v) if duals else None
     u0a = _f64(u0) if u0 is not None else None
     s0a = _f64(s0) if s0 is not None else None
     t0a = _f64(t0) if t0 is not None else None
     rc = lib().ora_solve(dims, _p(prm), int(max_iter), _p(v), _p(u0a), _p(s0a), _p(t0a), _p(u),
-                         _p(s), _p(t), _p(st), _p(tr), _p(Y), _p(y2), _p(y3))
+                         _p(s), _p(t), _p(st), _p(tr), _p(Y), _p(Z), _p(y2), _p(y3))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     out = dict(u=u, s=s, t=t, stats=dict(iters=int(st[0]), rel_change=st[1],
@@ -256,5 +268,6 @@ def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: 
     if trace:
         out["trace"] = tr[:out["stats"]["iters"]]
     if duals:
-        out.update(Y=Y, y2=y2, y3=y3)
+        out.update(y2=y2, y3=y3)
+        out.update(Y=Y) if reg <= 1 else out.update(Z=Z)
     return out

@@ -389,42 +389,92 @@ double ora_s3ttv(int n1, int n2, int n3, int k1, int k2, const double *u) {
 
 /* ---------------- Alg. 1: P-PDS solver for Prob. (18) ---------------- */
 
+/* Regularisers on the P-PDS skeleton of Alg. 1 (Sec. IV-A replaces the S3TTV term of
+   Prob. (18) by those of the compared P-PDS-applicable methods and solves each by P-PDS):
+     0 S3TTV: sum_l ||P_l D D_s u||_*          (dual: blocks Y_l, step 10 = spectral clip)
+     1 STV:   sum_l ||P_l D u||_*              (blocks of first-order spatial differences)
+     2 SSTV:  ||D D_s u||_1                    (dual: field Z, step = clip to [-1, 1])
+     3 HSSTV: ||D D_s u||_1 + omega ||D u||_1  (two fields, the second with step 1/(2 omega)) */
+enum { REG_S3TTV = 0, REG_STV = 1, REG_SSTV = 2, REG_HSSTV = 3 };
+
+/* gv, gh = D_v x, D_h x, after D_s when spectral != 0. tmp: N scratch doubles. */
+static void grad_pair(int n1, int n2, int n3, int spectral, const double *x, double *gv,
+                      double *gh, double *tmp) {
+  const double *src = x;
+  if (spectral) {
+    ora_ds(n1, n2, n3, x, tmp);
+    src = tmp;
+  }
+  ora_dv(n1, n2, n3, src, gv);
+  ora_dh(n1, n2, n3, src, gh);
+}
+
+/* out = D_v^T zv + D_h^T zh, then D_s^T of it when spectral != 0. a, c: N scratch doubles. */
+static void grad_pair_adj(int n1, int n2, int n3, int spectral, const double *zv, const double *zh,
+                          double *out, double *a, double *c) {
+  const size_t N = (size_t)n1 * n2 * n3;
+  ora_dv_t(n1, n2, n3, zv, a);
+  ora_dh_t(n1, n2, n3, zh, c);
+  for (size_t e = 0; e < N; ++e) a[e] += c[e];
+  if (spectral) ora_ds_t(n1, n2, n3, a, out);
+  else memcpy(out, a, N * sizeof(double));
+}
+
 /* prm: [0] eps [1] alpha [2] beta [3] mu_min [4] mu_max
         [5] gamma_u [6] gamma_s [7] gamma_t [8] gamma_Y [9] gamma_y2 [10] gamma_y3 [11] rel_tol
-   Step sizes that are all zero select the Lemma-2 defaults.
+        [12] regulariser (REG_*) [13] omega (HSSTV weight, > 0 for REG_HSSTV)
+   Step sizes that are all zero select the Lemma-2 defaults of the regulariser's stacked
+   operator: gamma_u = 1/(8K+1) (S3TTV), 1/(4K+1) (STV), 1/9 (SSTV), 1/(9 + 4 omega) (HSSTV);
+   gamma_Y (the step of the regulariser's dual) = 1/4, except 1/2 for STV; gamma_s = 1,
+   gamma_t = 1/3, gamma_y2 = 1/2, gamma_y3 = 1/3. The HSSTV second field always steps with
+   1/(2 omega).
    Initial values (Alg. 1 leaves them free): u0, s0, t0 (nullable: zero); all duals start at
    zero.
-   dims: [0] N1 [1] N2 [2] N3 [3] k1 [4] k2.
+   dims: [0] N1 [1] N2 [2] N3 [3] k1 [4] k2 (blocks; unused by SSTV and HSSTV).
    stats (out, 8 doubles): [0] iterations run [1] last relative change [2] converged flag
         [3] ||D_v t|| [4] ||u+s+t-v|| - eps [5] ||s||_1 - alpha [6] ||t||_1 - beta
         [7] worst SVD sweep count (-1 if some block did not converge).
    trace (nullable, max_iter doubles): relative change after each iteration.
-   Y_out, y2_out, y3_out (nullable): final dual variables (Y in the T layout).
+   Y_out (S3TTV, STV), z_out (SSTV, HSSTV: 4N doubles z1v, z1h, z2v, z2h), y2_out, y3_out
+   (nullable): final dual variables (Y in the T layout).
    Returns 0, or -1 for invalid arguments. */
 int ora_solve(const int *dims, const double *prm, int max_iter, const double *v, const double *u0,
               const double *s0, const double *t0, double *u, double *s, double *t,
-              double *stats, double *trace, double *Y_out, double *y2_out, double *y3_out) {
+              double *stats, double *trace, double *Y_out, double *z_out, double *y2_out,
+              double *y3_out) {
   const int n1 = dims[0], n2 = dims[1], n3 = dims[2], k1 = dims[3], k2 = dims[4];
   if (n1 < 2 || n2 < 2 || n3 < 2 || k1 < 1 || k2 < 1 || k1 > n1 || k2 > n2 || max_iter < 1)
     return -1;
   const double eps = prm[0], alpha = prm[1], beta = prm[2], lo = prm[3], hi = prm[4];
   double g_u = prm[5], g_s = prm[6], g_t = prm[7], g_Y = prm[8], g_y2 = prm[9], g_y3 = prm[10];
   const double tol = prm[11];
+  const int reg = (int)prm[12];
+  const double omega = prm[13];
+  if (reg < REG_S3TTV || reg > REG_HSSTV) return -1;
+  if (reg == REG_HSSTV && !(omega > 0)) return -1;
+  const int blocks = reg == REG_S3TTV || reg == REG_STV;
+  const int spectral = reg != REG_STV;
   const int K = k1 * k2, C = 2 * n3;
   if (g_u == 0 && g_s == 0 && g_t == 0 && g_Y == 0 && g_y2 == 0 && g_y3 == 0) {
-    g_u = 1.0 / (8.0 * K + 1.0);
+    g_u = reg == REG_S3TTV ? 1.0 / (8.0 * K + 1.0)
+          : reg == REG_STV ? 1.0 / (4.0 * K + 1.0)
+          : reg == REG_SSTV ? 1.0 / 9.0
+                            : 1.0 / (9.0 + 4.0 * omega);
     g_s = 1.0;
     g_t = 1.0 / 3.0;
-    g_Y = 0.25;
+    g_Y = reg == REG_STV ? 0.5 : 0.25;
     g_y2 = 0.5;
     g_y3 = 1.0 / 3.0;
   }
+  const double g_Z2 = reg == REG_HSSTV ? 1.0 / (2.0 * omega) : 0.0;
   if (!(eps > 0 && alpha > 0 && beta > 0 && lo < hi && g_u > 0 && g_s > 0 && g_t > 0 && g_Y > 0 &&
         g_y2 > 0 && g_y3 > 0))
     return -1;
   const size_t N = (size_t)n1 * n2 * n3, L = (size_t)n1 * n2, BL = (size_t)K * C;
 
-  double *Y = (double *)calloc(L * BL, sizeof(double));
+  double *Y = blocks ? (double *)calloc(L * BL, sizeof(double)) : NULL;
+  double *T = blocks ? (double *)malloc(L * BL * sizeof(double)) : NULL;
+  double *Z = !blocks ? (double *)calloc(4 * N, sizeof(double)) : NULL;  /* z1v z1h z2v z2h */
   double *y2 = (double *)calloc(N, sizeof(double));
   double *y3 = (double *)calloc(N, sizeof(double));
   double *un = (double *)malloc(N * sizeof(double));
@@ -433,7 +483,10 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   double *w = (double *)malloc(N * sizeof(double));
   double *tmp = (double *)malloc(N * sizeof(double));
   double *up = (double *)malloc(N * sizeof(double));
-  double *T = (double *)malloc(L * BL * sizeof(double));
+  double *gv = (double *)malloc(N * sizeof(double));
+  double *gh = (double *)malloc(N * sizeof(double));
+  double *s1 = (double *)malloc(N * sizeof(double));
+  double *s2 = (double *)malloc(N * sizeof(double));
 
   for (size_t e = 0; e < N; ++e) {
     u[e] = u0 ? u0[e] : 0.0;
@@ -443,8 +496,20 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   int it = 0, converged = 0, worst_sweeps = 0;
   double rel = 0.0;
   for (it = 0; it < max_iter;) {
-    /* Step 2: u+ = P_box(u - g_u (sum_l D_s^T D^T P_l^T Y_l + y3)). */
-    ora_struct_tensor_adj(n1, n2, n3, k1, k2, Y, w);
+    /* Step 2: u+ = P_box(u - g_u (A^T(dual of the regulariser) + y3)); for S3TTV
+       A^T Y = sum_l D_s^T D^T P_l^T Y_l. */
+    if (reg == REG_S3TTV) {
+      ora_struct_tensor_adj(n1, n2, n3, k1, k2, Y, w);
+    } else if (reg == REG_STV) {
+      ora_blocks_scatter(n1, n2, n3, k1, k2, Y, gv, gh);
+      grad_pair_adj(n1, n2, n3, 0, gv, gh, w, s1, s2);
+    } else {
+      grad_pair_adj(n1, n2, n3, 1, Z, Z + N, w, s1, s2);
+      if (reg == REG_HSSTV) {
+        grad_pair_adj(n1, n2, n3, 0, Z + 2 * N, Z + 3 * N, gv, s1, s2);
+        for (size_t e = 0; e < N; ++e) w[e] += omega * gv[e];
+      }
+    }
     for (size_t e = 0; e < N; ++e) tmp[e] = u[e] - g_u * (w[e] + y3[e]);
     ora_proj_box((int64_t)N, tmp, lo, hi, un);
     /* Step 3: s+ = P_{B1,alpha}(s - g_s y3). */
@@ -456,22 +521,40 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
     ora_proj_l1((int64_t)N, tmp, beta, tn);
     /* Steps 5-7: extrapolation (u' kept in up; s', t' formed where used). */
     for (size_t e = 0; e < N; ++e) up[e] = 2.0 * un[e] - u[e];
-    /* Steps 8-11: Y'_l = Y_l + g_Y P_l D D_s u';  Y_l = Y'_l - g_Y prox_{1/g_Y ||.||_*}(Y'_l/g_Y). */
-    ora_struct_tensor(n1, n2, n3, k1, k2, up, T);
-    int sweeps_max = 0, failed = 0;
+    /* Steps 8-11 for the regulariser's dual: Y'_l = Y_l + g_Y A_l u',
+       Y_l = Y'_l - g_Y prox_{(1/g_Y) R}(Y'_l / g_Y): a spectral clip of each block for the
+       nuclear norms, a clip of each entry to [-1, 1] for the l1 norms. */
+    if (blocks) {
+      grad_pair(n1, n2, n3, spectral, up, gv, gh, s1);
+      ora_blocks_extract(n1, n2, n3, k1, k2, gv, gh, T);
+      int sweeps_max = 0, failed = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : sweeps_max) reduction(| : failed)
-    for (size_t l = 0; l < L; ++l) {
-      double *Yl = Y + l * BL;
-      const double *Tl = T + l * BL;
-      double *Yp = (double *)malloc(BL * sizeof(double));
-      for (size_t e = 0; e < BL; ++e) Yp[e] = Yl[e] + g_Y * Tl[e];
-      const int sw = ora_dual_nuclear(K, C, g_Y, Yp, Yl);
-      if (sw < 0) failed = 1;
-      if (sw > sweeps_max) sweeps_max = sw;
-      free(Yp);
+      for (size_t l = 0; l < L; ++l) {
+        double *Yl = Y + l * BL;
+        const double *Tl = T + l * BL;
+        double *Yp = (double *)malloc(BL * sizeof(double));
+        for (size_t e = 0; e < BL; ++e) Yp[e] = Yl[e] + g_Y * Tl[e];
+        const int sw = ora_dual_nuclear(K, C, g_Y, Yp, Yl);
+        if (sw < 0) failed = 1;
+        if (sw > sweeps_max) sweeps_max = sw;
+        free(Yp);
+      }
+      if (failed) worst_sweeps = -1;
+      else if (worst_sweeps >= 0 && sweeps_max > worst_sweeps) worst_sweeps = sweeps_max;
+    } else {
+      grad_pair(n1, n2, n3, 1, up, gv, gh, s1);
+      for (size_t e = 0; e < N; ++e) {
+        Z[e] = fmin(1.0, fmax(-1.0, Z[e] + g_Y * gv[e]));
+        Z[N + e] = fmin(1.0, fmax(-1.0, Z[N + e] + g_Y * gh[e]));
+      }
+      if (reg == REG_HSSTV) {
+        grad_pair(n1, n2, n3, 0, up, gv, gh, s1);
+        for (size_t e = 0; e < N; ++e) {
+          Z[2 * N + e] = fmin(1.0, fmax(-1.0, Z[2 * N + e] + g_Z2 * omega * gv[e]));
+          Z[3 * N + e] = fmin(1.0, fmax(-1.0, Z[3 * N + e] + g_Z2 * omega * gh[e]));
+        }
+      }
     }
-    if (failed) worst_sweeps = -1;
-    else if (worst_sweeps >= 0 && sweeps_max > worst_sweeps) worst_sweeps = sweeps_max;
     /* Step 12: y2 = y2 + g_y2 D_v t'. */
     for (size_t e = 0; e < N; ++e) tmp[e] = 2.0 * tn[e] - t[e];
     ora_dv(n1, n2, n3, tmp, w);
@@ -517,10 +600,13 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   stats[5] = (double)l1s - alpha;
   stats[6] = (double)l1t - beta;
   stats[7] = worst_sweeps;
-  if (Y_out) memcpy(Y_out, Y, L * BL * sizeof(double));
+  if (Y_out && Y) memcpy(Y_out, Y, L * BL * sizeof(double));
+  if (z_out && Z) memcpy(z_out, Z, 4 * N * sizeof(double));
   if (y2_out) memcpy(y2_out, y2, N * sizeof(double));
   if (y3_out) memcpy(y3_out, y3, N * sizeof(double));
   free(Y);
+  free(T);
+  free(Z);
   free(y2);
   free(y3);
   free(un);
@@ -529,6 +615,9 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   free(w);
   free(tmp);
   free(up);
-  free(T);
+  free(gv);
+  free(gh);
+  free(s1);
+  free(s2);
   return 0;
 }
