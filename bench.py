@@ -329,6 +329,8 @@ def main() -> int:
                     help="c2: the single 256x256x128 image (default); c4: the uneven batch of 24; "
                          "c5: learned initial estimate vs zero start on 512x512x191; cnn: the "
                          "network kernels alone")
+    ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv"], default="s3ttv",
+                    help="c2: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
     ap.add_argument("--train-steps", type=int, default=2500, help="c5: Adam steps (batch 8)")
     ap.add_argument("--ref-iters", type=int, default=10000,
@@ -367,28 +369,40 @@ def main() -> int:
     solver = nt.Solver(n1, n2, n3, k1, k2, device=dev)
     rad = d["radii"]
 
+    reg = args.regularizer
+    l1_reg = reg in ("sstv", "hsstv")
     print(f"[bench] warmup {args.warmup} iterations", file=sys.stderr, flush=True)
-    solver.solve(v, nt.make_params(max_iter=max(args.warmup, 1), gram_precision=prec, **rad))
+    solver.solve(v, nt.make_params(max_iter=max(args.warmup, 1), gram_precision=prec,
+                                   regularizer=reg, **rad))
     torch.cuda.synchronize()
 
     print(f"[bench] timed {args.steps} iterations", file=sys.stderr, flush=True)
-    params = nt.make_params(max_iter=args.steps, timing_mask=1 << nt.K_BLOCK, gram_precision=prec,
-                            **rad)
+    cls = nt.K_DUAL if l1_reg else nt.K_BLOCK
+    params = nt.make_params(max_iter=args.steps, timing_mask=1 << cls, gram_precision=prec,
+                            regularizer=reg, **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u, s, t, st = solver.solve(v, params)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = args.steps / wall
-    block_calls = st["kernel_calls"]["block"]
+    name = nt.KERNEL_NAMES[cls]
+    block_calls = st["kernel_calls"][name]
     if block_calls < 1:
-        print("bench.py: the fused block pass did not run", file=sys.stderr)
+        print(f"bench.py: the timed kernel ({name}) did not run", file=sys.stderr)
         return 3
-    block_ms = st["kernel_ms"]["block"] / block_calls
-    block_bytes = block_pass_algorithmic_bytes(n1, n2, n3, k1, k2)
+    block_ms = st["kernel_ms"][name] / block_calls
+    if l1_reg:
+        # the dual sweep is the largest pass of the l1 variants: 36 B read and 16 B written per
+        # voxel for the vector duals and s, t, plus the l1 dual field(s) read and written
+        kname = "k_dual_grad"
+        block_bytes = n1 * n2 * n3 * (52 + 16 * (2 if reg == "hsstv" else 1))
+    else:
+        kname = "k_block_fused"
+        block_bytes = block_pass_algorithmic_bytes(n1, n2, n3, k1, k2)
     achieved = block_bytes / (block_ms * 1e-3) / 1e9
 
-    traffic = measured_traffic("k_block_fused")
+    traffic = measured_traffic(kname) if reg == "s3ttv" else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -402,13 +416,14 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32" if args.gram_precision == "fp32" else f"f32 ({args.gram_precision} Gram inputs)",
         "data": "synthetic",
-        "config": {"workload": f"S3TTV P-PDS, synthetic HSI {n1}x{n2}x{n3}, block {k1}x{k2}, "
+        "config": {"workload": f"{reg.upper()} P-PDS, synthetic HSI {n1}x{n2}x{n3}, block {k1}x{k2}, "
                                f"sigma {cfg.sigma}, salt-and-pepper {cfg.p_sp}, stripes {cfg.p_stripe}",
                    "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed,
-                   "gram_precision": args.gram_precision},
+                   "gram_precision": args.gram_precision, "regularizer": reg},
         "loop_ms_per_step": st["ms"] / args.steps,
-        "iteration_algorithmic_bytes": iteration_algorithmic_bytes(n1, n2, n3, k1, k2),
-        "roofline": {"kernel": "k_block_fused", "bound": "hbm", "achieved": achieved,
+        "iteration_algorithmic_bytes": (None if l1_reg
+                                        else iteration_algorithmic_bytes(n1, n2, n3, k1, k2)),
+        "roofline": {"kernel": kname, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic[0] if traffic else None, "avg_launch_ms": block_ms,
                      "launches_timed": block_calls,
@@ -439,7 +454,7 @@ def main() -> int:
     if not args.skip_tol:
         print(f"[bench] time to rel-tol 1e-4 (cap {args.tol_cap})", file=sys.stderr, flush=True)
         p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=1e-4, check_every=32,
-                            gram_precision=prec, **rad)
+                            gram_precision=prec, regularizer=reg, **rad)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, _, st2 = solver.solve(v, p2)

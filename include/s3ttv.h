@@ -61,7 +61,8 @@ typedef struct {
  *  mu_min < mu_max: box of u (eq. constraint_box); [0, 1] for normalised images.
  *  gamma_*: diagonal step sizes of Alg. 1 (eq. stepsize_denoising). If all six are 0 the
  *    Lemma-2 values of the stacked operator are used: gamma_u = 1/(8*k1*k2 + 1),
- *    gamma_s = 1, gamma_t = 1/3, gamma_Y = 1/4, gamma_y2 = 1/2, gamma_y3 = 1/3.
+ *    gamma_s = 1, gamma_t = 1/3, gamma_Y = 1/4, gamma_y2 = 1/2, gamma_y3 = 1/3 (for the
+ *    regulariser variants see `regularizer`).
  *  max_iter >= 1 iterations at most.
  *  rel_tol: 0 runs exactly max_iter iterations; > 0 stops after the first iteration
  *    k >= 2 with ||u^(k) - u^(k-1)|| / ||u^(k-1)|| < rel_tol (eq. StopCri_simulated).
@@ -79,7 +80,16 @@ typedef struct {
  *    precision of the per-block Gram products Y' Y'^T on MFMA from the second iteration on
  *    (accumulation is FP32; the eigen-solve, the clip W Y' and every update stay FP32). The
  *    reduced modes trade the accuracy of W (inputs rounded to 8 or 11 significand bits) for
- *    fewer MFMA instructions; see the error report of the tests. */
+ *    fewer MFMA instructions; see the error report of the tests.
+ *  regularizer: the term minimised in place of S3TTV on the same P-PDS skeleton (Sec. IV-A
+ *    compares methods this way): S3TTV_REG_S3TTV (default, Prob. (18)),
+ *    S3TTV_REG_STV (sum_l ||P_l D u||_*, blocks of first-order differences),
+ *    S3TTV_REG_SSTV (||D D_s u||_1) or S3TTV_REG_HSSTV (||D D_s u||_1 + omega ||D u||_1).
+ *    For the l1 terms the dual of the regulariser is a field clipped to [-1, 1] each
+ *    iteration (gamma_Y is its step; the HSSTV second field steps with 1/(2 omega)) and no
+ *    block pass runs. Default steps (all gammas 0), by Lemma 2: gamma_u = 1/(8K+1), 1/(4K+1),
+ *    1/9, 1/(9 + 4 omega); gamma_Y = 1/4, 1/2 (STV), 1/4, 1/4; the other four as above.
+ *  omega: HSSTV weight; 0 selects 0.05 (the value of the paper's comparison); finite, >= 0. */
 typedef struct {
   double eps, alpha, beta;
   double mu_min, mu_max;
@@ -90,9 +100,12 @@ typedef struct {
   int32_t timing_mask;
   int32_t eig_max_steps;
   int32_t gram_precision;
+  int32_t regularizer;
+  double omega;
 } s3ttv_params;
 
 enum { S3TTV_GRAM_FP32 = 0, S3TTV_GRAM_BF16 = 1, S3TTV_GRAM_FP16 = 2 };
+enum { S3TTV_REG_S3TTV = 0, S3TTV_REG_STV = 1, S3TTV_REG_SSTV = 2, S3TTV_REG_HSSTV = 3 };
 
 /* Kernel classes for timing_mask / s3ttv_stats.kernel_ms. */
 enum {

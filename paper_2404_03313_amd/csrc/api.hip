@@ -179,16 +179,26 @@ struct Gammas {
   double u, s, t, Y, y2, y3;
 };
 
+// HSSTV weight in effect (0 selects the comparison value 0.05).
+double hsstv_omega(const s3ttv_params *pr) { return pr->omega > 0 ? pr->omega : 0.05; }
+
 bool resolve_gammas(const s3ttv_shape *sh, const s3ttv_params *pr, Gammas &g) {
   const bool all0 = pr->gamma_u == 0 && pr->gamma_s == 0 && pr->gamma_t == 0 && pr->gamma_Y == 0 &&
                     pr->gamma_y2 == 0 && pr->gamma_y3 == 0;
   if (all0) {
     // Lemma 2 on the stacked operator: column sums 8K+1 (u), 1 (s), 3 (t); row sums 4 (Y),
-    // 2 (y2), 3 (y3).
-    g.u = 1.0 / (8.0 * sh->k1 * sh->k2 + 1.0);
+    // 2 (y2), 3 (y3). Variants: u column sums 4K+1 (STV), 9 (SSTV), 9 + 4 omega (HSSTV);
+    // the STV block rows sum to 2.
+    const double K = (double)sh->k1 * sh->k2, om = hsstv_omega(pr);
+    switch (pr->regularizer) {
+      case S3TTV_REG_STV: g.u = 1.0 / (4.0 * K + 1.0); break;
+      case S3TTV_REG_SSTV: g.u = 1.0 / 9.0; break;
+      case S3TTV_REG_HSSTV: g.u = 1.0 / (9.0 + 4.0 * om); break;
+      default: g.u = 1.0 / (8.0 * K + 1.0); break;
+    }
     g.s = 1.0;
     g.t = 1.0 / 3.0;
-    g.Y = 0.25;
+    g.Y = pr->regularizer == S3TTV_REG_STV ? 0.5 : 0.25;
     g.y2 = 0.5;
     g.y3 = 1.0 / 3.0;
   } else {
@@ -210,6 +220,8 @@ bool valid_params(const s3ttv_params *pr) {
   if (!(pr->rel_tol >= 0 && isfinite(pr->rel_tol))) return false;
   if (pr->eig_max_steps > 255) return false;
   if (pr->gram_precision < S3TTV_GRAM_FP32 || pr->gram_precision > S3TTV_GRAM_FP16) return false;
+  if (pr->regularizer < S3TTV_REG_S3TTV || pr->regularizer > S3TTV_REG_HSSTV) return false;
+  if (!(pr->omega >= 0 && isfinite(pr->omega))) return false;
   return true;
 }
 
@@ -296,6 +308,9 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
   pl.g_y3 = (float)gm.y3;
   pl.mu_min = (float)params->mu_min;
   pl.mu_max = (float)params->mu_max;
+  pl.reg = params->regularizer;
+  pl.omega = (float)hsstv_omega(params);
+  pl.g_Z2 = (float)(1.0 / (2.0 * hsstv_omega(params)));
   pl.eps = params->eps;
   pl.alpha = params->alpha;
   pl.beta = params->beta;
@@ -354,6 +369,7 @@ int32_t enqueue_init(const Problem &pr, hipStream_t st) {
   CK(launch_fill(pl.w, pl.N, 0.f, st));
   CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
   CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
+  if (pl.reg == kRegHSSTV) CK(launch_fill(pl.gradf, pl.P * pl.ncol, 0.f, st));
   CK(launch_identity16(pl.V, pl.P, st));
   // overlap-add partials start at zero (the first primal step may read them directly)
   CK(launch_fill(reinterpret_cast<float *>(pl.zpart),
@@ -383,6 +399,11 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
   // dual steps (3-7 thresholds, 12, 13) together with the gradient field of u' (steps 5, 9):
   // neither depends on the block pass
   TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], pr.v, st));
+  if (pl.reg >= kRegSSTV) {
+    // l1 regulariser: its dual step ran inside the dual sweep; there are no blocks
+    TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));
+    return S3TTV_OK;
+  }
   if (it > 0 && pr.fused) {
     TIMED(S3TTV_K_BLOCK, launch_block_fused(pr.bw, st));
     TIMED(S3TTV_K_EIG, launch_eig(pr.bw, st));
@@ -710,7 +731,10 @@ int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_pa
   for (int i = 0; i < n; ++i) {
     const size_t region = align_up(plan_bytes_any_tile(&shapes[i]));
     int TA = 0, TB = 0;
-    int32_t r = tune_tiles(&shapes[i], &params[i], base + off, region, st, TA, TB);
+    // the l1 regularisers have no block pass: nothing to tune
+    int32_t r = params[i].regularizer >= S3TTV_REG_SSTV
+                    ? S3TTV_OK
+                    : tune_tiles(&shapes[i], &params[i], base + off, region, st, TA, TB);
     if (r == S3TTV_OK)
       r = prepare(prs[i], &shapes[i], &params[i], v[i], u0 ? u0[i] : nullptr, u[i], s[i], t[i],
                   base + off, region, TA, TB);

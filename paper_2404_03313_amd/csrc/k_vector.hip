@@ -81,6 +81,8 @@ struct PrimalArgs {
   float g_u, g_s, g_t, lo, hi;
   const float *u, *s, *t, *y2, *w, *Z;
   const int *zpart, *zslot;  // with zslot: read the overlap-add partials instead of Z
+  const float *Z2;           // second dual field (HSSTV), same layout as Z
+  float omega;               // its weight
   float *un, *xs, *xt;
   double *red;
   DevScalars *sc;
@@ -98,6 +100,9 @@ __device__ inline float zfold_val(const int *zpart, int4 off, int col) {
 // Alg. 1 steps 2-4 before the l1 projections:
 //   u+ = P_box(u - g_u (D_s^T (D_v^T Zv + D_h^T Zh) + y3))        (eq. prox_box_constraint)
 //   xs = s - g_s y3,   xt = t - g_t (D_v^T y2 + y3),   y3 = kappa * w.
+// MODE 0: the field is adjoined by D_s^T D^T (S3TTV: the overlap-add sum of the blocks; SSTV:
+// the dual field itself); MODE 1: by D^T (STV); MODE 2: D_s^T D^T Z + omega D^T Z2 (HSSTV).
+template <int MODE>
 __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
   __shared__ unsigned long long h[2][kL1Bins1];
   __shared__ double sh[4];
@@ -132,7 +137,13 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
       q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
       q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
     }
-    const float adj = q1 - q0;
+    float adj = MODE == 1 ? q0 : q1 - q0;
+    if (MODE == 2) {
+      const float *Zp = a.Z2 + (size_t)pix * ncol;
+      const float *Zi = a.Z2 + (size_t)pim * ncol;
+      const float *Zj = a.Z2 + (size_t)pjm * ncol;
+      adj += a.omega * ((Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]));
+    }
     const float y3 = kappa * a.w[e];
     const float uo = a.u[e];
     const float un = box(uo - a.g_u * (adj + y3), a.lo, a.hi);
@@ -371,9 +382,18 @@ __global__ __launch_bounds__(kNT) void k_dual(DualArgs a) {
 struct DualGradArgs {
   DualArgs d;
   int Bp, ncol;
-  float *g;
+  float *g;        // gradient field (S3TTV, STV) or the dual field Z updated in place (SSTV, HSSTV)
+  float *g2;       // second dual field Z2 (HSSTV)
+  float gZ, gZ2, omega;
 };
 
+__device__ inline float clip1(float x) { return fminf(1.f, fmaxf(-1.f, x)); }
+
+// REG 0 (S3TTV): g = (D_v D_s u', D_h D_s u') for the block pass. REG 1 (STV): g = (D_v u',
+// D_h u'). REG 2 (SSTV): the l1 dual step Z = clip(Z + gZ D D_s u') to [-1, 1] (the Moreau
+// form of the prox of ||.||_1), in place. REG 3 (HSSTV): as REG 2 plus
+// Z2 = clip(Z2 + gZ2 omega D u').
+template <int REG>
 __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
   __shared__ double sh[4];
   const DualArgs &a = ag.d;
@@ -415,12 +435,28 @@ __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
       const int b1 = wrap_up(b + 1, n3);
       const size_t o00 = (size_t)pix * n3;
 #define UP(o, bb) (2.f * a.un[(o) + (bb)] + -1.f * a.uo[(o) + (bb)])
-      const float d00 = UP(o00, b1) - up;
-      const float d10 = UP(o10, b1) - UP(o10, b);
-      const float d01 = UP(o01, b1) - UP(o01, b);
+      const float u10 = UP(o10, b), u01 = UP(o01, b);
+      if (REG == 1) {
+        gv = u10 - up;
+        gh = u01 - up;
+      } else {
+        const float d00 = UP(o00, b1) - up;
+        const float d10 = UP(o10, b1) - u10;
+        const float d01 = UP(o01, b1) - u01;
+        gv = d10 - d00;
+        gh = d01 - d00;
+      }
 #undef UP
-      gv = d10 - d00;
-      gh = d01 - d00;
+      if (REG >= 2) {
+        const size_t o = (size_t)pix * ag.ncol + b;
+        gv = clip1(ag.g[o] + ag.gZ * gv);
+        gh = clip1(ag.g[o + Bp] + ag.gZ * gh);
+        if (REG == 3) {
+          const float s2 = ag.gZ2 * ag.omega;
+          ag.g2[o] = clip1(ag.g2[o] + s2 * (u10 - up));
+          ag.g2[o + Bp] = clip1(ag.g2[o + Bp] + s2 * (u01 - up));
+        }
+      }
     }
     ag.g[(size_t)pix * ag.ncol + b] = gv;
     ag.g[(size_t)pix * ag.ncol + Bp + b] = gh;
@@ -672,9 +708,15 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
   a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.Bp = pl.Bp; a.ncol = pl.ncol; a.N = pl.N;
   a.g_u = pl.g_u; a.g_s = pl.g_s; a.g_t = pl.g_t; a.lo = pl.mu_min; a.hi = pl.mu_max;
   a.u = u_cur; a.s = pl.s; a.t = t_cur; a.y2 = pl.y2; a.w = pl.w; a.Z = pl.Z;
-  a.zpart = pl.zpart; a.zslot = pl.zfold ? pl.zslot : nullptr;
+  a.zpart = pl.zpart; a.zslot = pl.zfold && pl.reg <= kRegSTV ? pl.zslot : nullptr;
+  a.Z2 = pl.gradf; a.omega = pl.omega;
   a.un = u_new; a.xs = pl.xs; a.xt = pl.xt; a.red = pl.red_primal; a.sc = pl.sc; a.hist = pl.hist;
-  hipLaunchKernelGGL(k_primal, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  if (pl.reg == kRegSTV)
+    hipLaunchKernelGGL(k_primal<1>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  else if (pl.reg == kRegHSSTV)
+    hipLaunchKernelGGL(k_primal<2>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_primal<0>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 
@@ -734,8 +776,16 @@ hipError_t launch_dual_grad(const Plan &pl, const float *u_cur, const float *u_n
   a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.N = pl.N; a.g_y2 = pl.g_y2; a.g_y3 = pl.g_y3;
   a.un = u_new; a.uo = u_cur; a.xs = pl.xs; a.xt = pl.xt; a.to = t_cur; a.v = v;
   a.s = pl.s; a.tn = t_new; a.y2 = pl.y2; a.w = pl.w; a.red = pl.red_dual; a.sc = pl.sc;
-  g.Bp = pl.Bp; g.ncol = pl.ncol; g.g = pl.gradf;
-  hipLaunchKernelGGL(k_dual_grad, dim3(pl.red_blocks), dim3(kNT), 0, st, g);
+  g.Bp = pl.Bp; g.ncol = pl.ncol;
+  g.g = pl.reg >= kRegSSTV ? pl.Z : pl.gradf;
+  g.g2 = pl.gradf;
+  g.gZ = pl.g_Y; g.gZ2 = pl.g_Z2; g.omega = pl.omega;
+  switch (pl.reg) {
+    case kRegSTV: hipLaunchKernelGGL(k_dual_grad<1>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
+    case kRegSSTV: hipLaunchKernelGGL(k_dual_grad<2>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
+    case kRegHSSTV: hipLaunchKernelGGL(k_dual_grad<3>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
+    default: hipLaunchKernelGGL(k_dual_grad<0>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
+  }
   return hipGetLastError();
 }
 

@@ -6,6 +6,10 @@
 
 namespace s3ttv {
 
+// Regularisers on the P-PDS skeleton (values of s3ttv_params.regularizer): the S3TTV term of
+// Prob. (18), or the terms of the compared P-PDS-applicable methods in its place.
+constexpr int kRegS3TTV = 0, kRegSTV = 1, kRegSSTV = 2, kRegHSSTV = 3;
+
 // Overlap-add partials (P_l^T of step 2) are accumulated in 32-bit fixed point with this
 // scale: every entry of Y+_l lies in [-1, 1] (its spectral norm is at most 1), so a pixel's
 // sum over at most 16 windows stays below 2^30. Integer addition is associative, so the
@@ -93,6 +97,9 @@ struct Plan {
   size_t apply_lds;
   // step sizes and box (float for the vector arithmetic), radii (double)
   float g_u, g_s, g_t, g_Y, g_y2, g_y3, mu_min, mu_max;
+  // regulariser (kReg*), HSSTV weight and the step of its second dual field
+  int reg;
+  float omega, g_Z2;
   double eps, alpha, beta;
   // grids of the reduction kernels
   int red_blocks;

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libs3ttv.so")
 OK, NOT_CONVERGED, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
 K_PRIMAL, K_L1, K_GRAD, K_GRAM, K_EIG, K_APPLY, K_ZSUM, K_DUAL, K_FINAL, K_BLOCK = range(10)
 GRAM_FP32, GRAM_BF16, GRAM_FP16 = 0, 1, 2
+REG_S3TTV, REG_STV, REG_SSTV, REG_HSSTV = 0, 1, 2, 3
+REGULARIZERS = {"s3ttv": REG_S3TTV, "stv": REG_STV, "sstv": REG_SSTV, "hsstv": REG_HSSTV}
 KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", "final", "block"]
 N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
@@ -40,7 +42,8 @@ class Params(ctypes.Structure):
                 ("gamma_y2", ctypes.c_double), ("gamma_y3", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("rel_tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("timing_mask", ctypes.c_int32),
-                ("eig_max_steps", ctypes.c_int32), ("gram_precision", ctypes.c_int32)]
+                ("eig_max_steps", ctypes.c_int32), ("gram_precision", ctypes.c_int32),
+                ("regularizer", ctypes.c_int32), ("omega", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -167,12 +170,16 @@ def default_gammas(k1: int, k2: int) -> dict:
 
 def make_params(eps, alpha, beta, max_iter, mu_min=0.0, mu_max=1.0, gammas: Optional[dict] = None,
                 rel_tol=0.0, check_every=16, timing_mask=0, eig_max_steps=0,
-                gram_precision=0) -> Params:
+                gram_precision=0, regularizer=REG_S3TTV, omega=0.0) -> Params:
+    """regularizer: REG_* value or one of "s3ttv", "stv", "sstv", "hsstv"."""
+    if isinstance(regularizer, str):
+        regularizer = REGULARIZERS[regularizer]
     g = gammas or {}
     return Params(eps, alpha, beta, mu_min, mu_max, g.get("gamma_u", 0.0), g.get("gamma_s", 0.0),
                   g.get("gamma_t", 0.0), g.get("gamma_Y", 0.0), g.get("gamma_y2", 0.0),
                   g.get("gamma_y3", 0.0), int(max_iter), float(rel_tol), int(check_every),
-                  int(timing_mask), int(eig_max_steps), int(gram_precision))
+                  int(timing_mask), int(eig_max_steps), int(gram_precision), int(regularizer),
+                  float(omega))
 
 
 def workspace_bytes(n1, n2, n3, k1, k2) -> int:

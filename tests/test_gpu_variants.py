@@ -1,0 +1,65 @@
+"""GPU parity of the regulariser variants (s3ttv_params.regularizer) with the FP64 oracle:
+STV, SSTV and HSSTV in place of S3TTV on the P-PDS skeleton of Alg. 1 (Sec. IV-A). Same bar
+as the S3TTV solve: relative L2 <= 1e-4 per output after a fixed iteration count."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2404_03313_amd import native as nt
+from paper_2404_03313_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-12)
+
+
+CASES = [((20, 18, 13), (3, 3), 100), ((13, 11, 7), (2, 3), 60), ((16, 16, 16), (4, 4), 40)]
+
+
+@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv"])
+@pytest.mark.parametrize("shape,k,iters", CASES)
+def test_variant_parity(device, reg, shape, k, iters):
+    print(f"variant {reg} shape={shape} k={k} iters={iters}", flush=True)
+    cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2,
+                          seed=21)
+    d = synth.make_hsi(cfg)
+    v = torch.from_numpy(d["v"]).to(device)
+    mask = (1 << nt.K_BLOCK) | (1 << nt.K_GRAM) | (1 << nt.K_DUAL)
+    u, s, t, st = nt.solve(v, k[0], k[1], max_iter=iters, regularizer=reg, timing_mask=mask,
+                           **d["radii"])
+    r = oracle.solve(d["v64"], k[0], k[1], max_iter=iters, regularizer=reg, omega=0.05,
+                     **d["radii"])
+    errs = {n: _rel(g.cpu().numpy().astype(np.float64), r[n]) for n, g in (("u", u), ("s", s), ("t", t))}
+    print("  rel L2 vs oracle:", errs, flush=True)
+    for n, e in errs.items():
+        assert e <= 1e-4, (n, e)
+    assert st["iters"] == iters
+    calls = st["kernel_calls"]
+    assert calls["dual"] == iters
+    if reg in ("sstv", "hsstv"):   # no blocks: the dual step runs inside the dual sweep
+        assert calls["block"] == 0 and calls["gram"] == 0
+    else:
+        assert calls["block"] + calls["gram"] >= iters
+
+
+def test_variants_batched_identical_to_standalone(device):
+    """One batched call with all four regularisers side by side; each result equals the
+    standalone solve bitwise."""
+    cfgs = [synth.HSIConfig(24, 20, 16, endmembers=3, cells=5, sigma=0.05, p_sp=0.05,
+                            p_stripe=0.1, seed=30 + i) for i in range(4)]
+    regs = ["s3ttv", "stv", "sstv", "hsstv"]
+    probs = []
+    for cfg, reg in zip(cfgs, regs):
+        d = synth.make_hsi(cfg)
+        prm = nt.make_params(max_iter=400, rel_tol=1e-4, regularizer=reg, **d["radii"])
+        probs.append(dict(v=torch.from_numpy(d["v"]).to(device), k1=3, k2=3, params=prm))
+    res, _ = nt.solve_batched(probs)
+    for p, (u, s, t, st), reg in zip(probs, res, regs):
+        u1, s1, t1, st1 = nt.Solver(24, 20, 16, 3, 3, device=device).solve(p["v"], p["params"])
+        print(f"  {reg}: batched {st['iters']} standalone {st1['iters']} iterations", flush=True)
+        assert st["iters"] == st1["iters"]
+        for a, b in ((u, u1), (s, s1), (t, t1)):
+            assert torch.equal(a, b)
