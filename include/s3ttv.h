@@ -20,7 +20,11 @@
  *    along i, j and b (Sec. II-A).
  *  - Blocks: one k1 x k2 window per pixel anchor (p, q) on the torus, L = N1*N2 blocks;
  *    block row r = a*k2 + c covers pixel ((p+a) mod N1, (q+c) mod N2). Supported K = k1*k2
- *    is 1..16.
+ *    is 1..100: up to 16 rows the blocks are handled in registers and MFMA tiles (fused
+ *    pass, warm-started MFMA eigen-solve); 17..100 rows (the paper's experiments use 10 x 10)
+ *    take a one-workgroup-per-block path (FP32 Gram, warm-started parallel Jacobi with a
+ *    certificate, low-rank clip, gathered overlap-add). The operator entry point
+ *    s3ttv_op_dual_blocks supports K <= 16.
  *  - Array arguments named "device" must be device pointers (hipMalloc / torch CUDA
  *    tensors) on the current HIP device; "host" arguments are host memory. The caller owns
  *    every buffer; the library never allocates device memory and keeps no state between
@@ -44,7 +48,7 @@ enum {
   S3TTV_OK = 0,
   S3TTV_NOT_CONVERGED = 1,
   S3TTV_EINVAL = -1,       /* bad shape, radius, box, step size, null pointer */
-  S3TTV_EUNSUPPORTED = -2, /* valid for the method but outside this build (e.g. K > 16) */
+  S3TTV_EUNSUPPORTED = -2, /* valid for the method but not supported here (e.g. K > 100) */
   S3TTV_EWORKSPACE = -3,   /* workspace smaller than the queried size */
   S3TTV_EHIP = -4,         /* HIP runtime error */
   S3TTV_ENONFINITE = -5    /* NaN/Inf met in the input or in the iterates */

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libs3ttv.so")
-SOURCES = ["k_vector.hip", "k_l1.hip", "k_blocks.hip", "api.hip", "k_cnn.hip", "cnn_api.hip"]
+SOURCES = ["k_vector.hip", "k_l1.hip", "k_blocks.hip", "k_bigblocks.hip", "api.hip", "k_cnn.hip",
+           "cnn_api.hip"]
 ARCH = os.environ.get("S3TTV_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall", "-Wno-unused-function",

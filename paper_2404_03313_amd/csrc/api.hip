@@ -27,6 +27,9 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = kLdsLimit;
 constexpr int kDefaultEigSteps = 24;
+// Jacobi sweeps at most per block on the K > 16 path (from the identity about 8 suffice for
+// K = 100; warm started fewer).
+constexpr int kBigMaxSweeps = 30;
 // Iterations per captured graph of the batched solve (even: the u / t buffer parity of the
 // captured launches then holds for every replay).
 constexpr int kBatchSpan = 16;
@@ -54,7 +57,7 @@ bool valid_shape(const s3ttv_shape *sh) {
 }
 
 int32_t supported_shape(const s3ttv_shape *sh) {
-  if (sh->k1 * sh->k2 > kRows) return S3TTV_EUNSUPPORTED;
+  if (sh->k1 * sh->k2 > kBigMax) return S3TTV_EUNSUPPORTED;
   const long long N = (long long)sh->n1 * sh->n2 * sh->n3;
   if (N >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
   return S3TTV_OK;
@@ -106,7 +109,20 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int forceTA = 0, int
   pl.ntile = pl.ncol / 16;
   pl.P = (long long)sh->n1 * sh->n2;
   pl.N = pl.P * sh->n3;
-  choose_tiles(pl, forceTA, forceTB);
+  pl.big = pl.K > kRows;
+  if (pl.big) {
+    // no anchor tiles: one workgroup per block, the overlap-add is a gather
+    pl.TA = pl.TB = 1;
+    pl.extA = pl.k1;
+    pl.extB = pl.k2;
+    pl.ntA = pl.n1;
+    pl.ntB = pl.n2;
+    pl.apply_waves = 1;
+    pl.zslots_n = 1;
+  } else {
+    choose_tiles(pl, forceTA, forceTB);
+    pl.zslots_n = (long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1;
+  }
   long long rb = (pl.N + 8191) / 8192;
   pl.red_blocks = (int)(rb < 1 ? 1 : (rb > 65535 ? 65535 : rb));
   Carver cv{base, 0, base == nullptr};
@@ -123,15 +139,15 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int forceTA = 0, int
   pl.gradf = cv.take<float>((size_t)pl.P * pl.ncol);
   pl.Z = cv.take<float>((size_t)pl.P * pl.ncol);
   // one extra all-zero slot at the end (named by the primal step's slot table for absent terms)
-  pl.zpart = cv.take<int>(((size_t)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol);
+  pl.zpart = cv.take<int>((size_t)pl.zslots_n * pl.ncol);
   pl.zslot = cv.take<int>((size_t)pl.P * 4);
   pl.G = cv.take<float>((size_t)pl.P * 256);
   pl.W = cv.take<float>((size_t)pl.P * 256);
-  pl.V = cv.take<float>((size_t)pl.P * 256);
+  pl.V = cv.take<float>((size_t)pl.P * (pl.big ? (size_t)pl.K * pl.K : 256));
   pl.eflag = cv.take<int>((size_t)pl.P);
   pl.estat = cv.take<int>((size_t)(pl.P + 63) / 64 * 4);
   pl.l1part = cv.take<unsigned long long>((size_t)2 * l1_part_blocks(pl.N) * kL1Bins2);
-  pl.Y = cv.take<float>((size_t)pl.P * kRows * pl.ncol);
+  pl.Y = cv.take<float>((size_t)pl.P * (pl.big ? pl.K : kRows) * pl.ncol);
   pl.red_primal = cv.take<double>((size_t)pl.red_blocks * 4);
   pl.red_dual = cv.take<double>((size_t)(pl.red_blocks > 4 ? pl.red_blocks : 4));
   pl.sc = cv.take<DevScalars>(1);
@@ -330,7 +346,7 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
   pr.bw.eig_steps = params->eig_max_steps == 0
                         ? kDefaultEigSteps
                         : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
-  pr.fused = fused_supported(pr.bw) && fused_lds_bytes(pr.bw) <= kMaxLds;
+  pr.fused = !pl.big && fused_supported(pr.bw) && fused_lds_bytes(pr.bw) <= kMaxLds;
   return S3TTV_OK;
 }
 
@@ -368,12 +384,16 @@ int32_t enqueue_init(const Problem &pr, hipStream_t st) {
   CK(launch_fill(pl.y2, pl.N, 0.f, st));
   CK(launch_fill(pl.w, pl.N, 0.f, st));
   CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
-  CK(launch_fill(pl.Y, pl.P * kRows * pl.ncol, 0.f, st));
+  CK(launch_fill(pl.Y, pl.P * (pl.big ? pl.K : kRows) * pl.ncol, 0.f, st));
   if (pl.reg == kRegHSSTV) CK(launch_fill(pl.gradf, pl.P * pl.ncol, 0.f, st));
+  if (pl.big) {
+    CK(launch_big_identity(pl.V, pl.P, pl.K, st));
+    CK(launch_fill(pl.Z, pl.P * pl.ncol, 0.f, st));
+    return S3TTV_OK;
+  }
   CK(launch_identity16(pl.V, pl.P, st));
   // overlap-add partials start at zero (the first primal step may read them directly)
-  CK(launch_fill(reinterpret_cast<float *>(pl.zpart),
-                 ((long long)pl.ntA * pl.ntB * pl.extA * pl.extB + 1) * pl.ncol, 0.f, st));
+  CK(launch_fill(reinterpret_cast<float *>(pl.zpart), pl.zslots_n * pl.ncol, 0.f, st));
   CK(launch_zslots(pl, st));
   return S3TTV_OK;
 }
@@ -381,7 +401,7 @@ int32_t enqueue_init(const Problem &pr, hipStream_t st) {
 // After enqueue_init has completed: the input check and the overlap-add route.
 int32_t check_init(Problem &pr, const DevScalars &hs0) {
   if (hs0.nonfinite) return S3TTV_ENONFINITE;
-  pr.pl.zfold = hs0.zslot_overflow == 0 && zslots_fit(pr.pl);
+  pr.pl.zfold = !pr.pl.big && hs0.zslot_overflow == 0 && zslots_fit(pr.pl);
   return S3TTV_OK;
 }
 
@@ -401,6 +421,16 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
   TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], pr.v, st));
   if (pl.reg >= kRegSSTV) {
     // l1 regulariser: its dual step ran inside the dual sweep; there are no blocks
+    TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));
+    return S3TTV_OK;
+  }
+  if (pl.big) {
+    BigArgs ba;
+    ba.n1 = pl.n1; ba.n2 = pl.n2; ba.k1 = pl.k1; ba.k2 = pl.k2; ba.K = pl.K; ba.ncol = pl.ncol;
+    ba.nblk = pl.P; ba.gradf = pl.gradf; ba.gY = pl.g_Y; ba.Y = pl.Y; ba.V = pl.V;
+    ba.first = it == 0; ba.max_sweeps = kBigMaxSweeps; ba.sc = pl.sc;
+    TIMED(S3TTV_K_BLOCK, launch_big_block(ba, st));
+    TIMED(S3TTV_K_ZSUM, launch_big_overlap(ba, pl.Z, st));
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));
     return S3TTV_OK;
   }
@@ -731,8 +761,9 @@ int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_pa
   for (int i = 0; i < n; ++i) {
     const size_t region = align_up(plan_bytes_any_tile(&shapes[i]));
     int TA = 0, TB = 0;
-    // the l1 regularisers have no block pass: nothing to tune
-    int32_t r = params[i].regularizer >= S3TTV_REG_SSTV
+    // the l1 regularisers and blocks of more than 16 rows have no anchor tiles to tune
+    int32_t r = params[i].regularizer >= S3TTV_REG_SSTV ||
+                        shapes[i].k1 * shapes[i].k2 > kRows
                     ? S3TTV_OK
                     : tune_tiles(&shapes[i], &params[i], base + off, region, st, TA, TB);
     if (r == S3TTV_OK)
@@ -858,6 +889,7 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
       if (!valid_shape(shape)) return S3TTV_EINVAL;
       const int32_t sup = supported_shape(shape);
       if (sup != S3TTV_OK) return sup;
+      if (op == S3TTV_OP_DUAL_BLOCKS && shape->k1 * shape->k2 > kRows) return S3TTV_EUNSUPPORTED;
       make_plan(pl, shape, nullptr);
       *bytes = pl.bytes;
       return S3TTV_OK;
@@ -973,6 +1005,7 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   if (!(gamma_Y > 0 && isfinite(gamma_Y))) return S3TTV_EINVAL;
   const int32_t sup = supported_shape(shape);
   if (sup != S3TTV_OK) return sup;
+  if (shape->k1 * shape->k2 > kRows) return S3TTV_EUNSUPPORTED;
   Plan pl;
   make_plan(pl, shape, nullptr);
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;

@@ -38,6 +38,8 @@ __device__ inline int xcd_block(int b, int G) {
 constexpr int kTile = 16;
 // Rows of the padded block (K <= 16 rows of the structure tensor, zero padded).
 constexpr int kRows = 16;
+// Blocks of more rows (16 < K <= kBigMax) take the one-workgroup-per-block path.
+constexpr int kBigMax = 100;
 
 // l1-ball threshold selection: radix selection on the IEEE bits of |x| in three levels
 // (bits 30..20, 19..9, 8..0). All values in one level-1 bin share an exponent, so per-bin
@@ -109,6 +111,8 @@ struct Plan {
   int *zslot;          // per pixel: the (up to 4) partial slots holding its overlap-add terms;
                        // absent ones name the extra all-zero slot at the end of zpart
   bool zfold;          // the primal step sums the partials itself (no separate zsum pass)
+  bool big;            // K > kRows: one workgroup per block, overlap-add by gather
+  long long zslots_n;  // overlap-add partial slots carved (tiles x extent + the zero slot)
   int *eflag;          // per block: rotation steps | 256 if the per-lane Jacobi must finish it
   int *estat;          // per k_eig workgroup (64 blocks): step sum, max steps, fallbacks, blocks
   unsigned long long *l1part;  // level-2 l1 partial histograms: 2 x l1_part_blocks(N) x 2048
@@ -164,6 +168,23 @@ hipError_t launch_l1_part_reduce(int nballs, long long n, const unsigned long lo
                                  L1Hist *hist, DevScalars *sc, hipStream_t st);
 hipError_t launch_l1_apply(const float *x, float *out, long long n, int ball, DevScalars *sc,
                            hipStream_t st);
+
+// Blocks of more than 16 rows (Alg. 1 steps 9-10 and the overlap-add).
+struct BigArgs {
+  int n1, n2, k1, k2, K, ncol;
+  long long nblk;
+  const float *gradf;
+  float gY;
+  float *Y;   // [block][K][ncol]
+  float *V;   // [block][K][K] eigenbasis, kept across iterations
+  int first;  // V is still the identity
+  int max_sweeps;
+  DevScalars *sc;
+};
+hipError_t launch_big_block(const BigArgs &a, hipStream_t st);
+hipError_t launch_big_overlap(const BigArgs &a, float *Z, hipStream_t st);
+hipError_t launch_big_identity(float *V, long long nblk, int K, hipStream_t st);
+size_t big_lds_bytes(int K);
 
 // Block kernels (Alg. 1 steps 9-10).
 struct BlockArgs {

@@ -41,7 +41,7 @@ def test_strerror_and_workspace_queries():
 
 @pytest.mark.parametrize("shape,code", [((1, 8, 4, 1, 1), nt.EINVAL), ((8, 8, 1, 1, 1), nt.EINVAL),
                                         ((8, 8, 4, 9, 1), nt.EINVAL), ((8, 8, 4, 0, 2), nt.EINVAL),
-                                        ((8, 8, 4, 5, 4), nt.EUNSUPPORTED)])
+                                        ((12, 12, 4, 11, 10), nt.EUNSUPPORTED)])
 def test_shape_validation(shape, code):
     sz = ctypes.c_size_t()
     sh = nt.Shape(*shape)
