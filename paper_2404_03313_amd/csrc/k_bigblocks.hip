@@ -187,6 +187,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     const int notyet = flag;
     __syncthreads();
     if (!notyet) break;
+    const float skip = 0.1f * tol;
     for (int s = 0; s < m - 1; ++s) {
       if (tid < m / 2) {
         int p, q;
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
         float c = 1.f, sv = 0.f;
         if (q < K) {
           const float apq = G[p * KS + q];
-          if (apq != 0.f) {
+          if (fabsf(apq) > skip) {  // threshold Jacobi: pairs already below skip stay
             const float app = G[p * KS + p], aqq = G[q * KS + q];
             const float zeta = (aqq - app) / (2.f * apq);
             const float t = fabsf(zeta) > 1e15f
