@@ -46,6 +46,53 @@ __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
   q = max(x, y);
 }
 
+// C (K x K) = op(A) B with A and B in LDS (row stride KS); op(A) = A^T when TA. Thread
+// (ti, tj) of a 16 x 16 grid forms the 8 x 8 tile at rows 8 ti, columns 8 tj (K <= 128), so
+// each k costs 16 LDS reads for 64 independent FMAs.
+template <bool TA>
+__device__ inline void mm_tile(const float *A, const float *B, int K, int KS, int ti, int tj,
+                               float acc[8][8]) {
+#pragma unroll
+  for (int x = 0; x < 8; ++x)
+#pragma unroll
+    for (int y = 0; y < 8; ++y) acc[x][y] = 0.f;
+  for (int k = 0; k < K; ++k) {
+    float av[8], bv[8];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+      const int r = 8 * ti + x, c = 8 * tj + x;
+      av[x] = r < K ? (TA ? A[k * KS + r] : A[r * KS + k]) : 0.f;
+      bv[x] = c < K ? B[k * KS + c] : 0.f;
+    }
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+  }
+}
+
+// P (K x 32, row stride cs) = V^T Y (Y: K x 32 chunk, row stride cs); thread (ti, tc) of a
+// 32 x 8 grid forms rows 4 ti .. 4 ti + 3, columns 4 tc .. 4 tc + 3.
+__device__ inline void proj_tile(const float *V, const float *Y, int K, int KS, int cs, int ti,
+                                 int tc, float acc[4][4]) {
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+  for (int r = 0; r < K; ++r) {
+    float av[4], bv[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      av[x] = 4 * ti + x < K ? V[r * KS + 4 * ti + x] : 0.f;
+      bv[x] = Y[r * cs + 4 * tc + x];
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+  }
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
@@ -130,18 +177,21 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   // ---- A = V^T (G V): H = G V into T3, then A into G
-  for (int e = tid; e < K * K; e += kNT) {
-    const int r = e / K, c = e - r * K;
-    float s = 0.f;
-    for (int k = 0; k < K; ++k) s = fmaf(G[r * KS + k], V[k * KS + c], s);
-    T3[r * KS + c] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += kNT) {
-    const int r = e / K, c = e - r * K;
-    float s = 0.f;
-    for (int k = 0; k < K; ++k) s = fmaf(V[k * KS + r], T3[k * KS + c], s);
-    G[r * KS + c] = s;
+  {
+    float acc[8][8];
+    mm_tile<false>(G, V, K, KS, ti, tj, acc);
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (8 * ti + x < K && 8 * tj + y < K) T3[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
+    __syncthreads();
+    mm_tile<true>(V, T3, K, KS, ti, tj, acc);
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (8 * ti + x < K && 8 * tj + y < K) G[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
   }
   __syncthreads();
   // symmetrise exactly
@@ -211,34 +261,68 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
         pq[tid][1] = q;
       }
       __syncthreads();
-      // rows: A <- J^T A. Thread t < nsplit K owns column j = t mod K and every nsplit-th pair
+      // rows: A <- J^T A. Thread t < nsplit K owns column j = t mod K and every nsplit-th pair,
+      // four pairs at a time (their rows are distinct, so the loads overlap)
       if (tid < nsplit * K) {
         const int j = tid - part * K;
-        for (int k = part; k < m / 2; k += nsplit) {
-          const float sv = sn[k];
-          if (sv == 0.f) continue;
-          const int p = pq[k][0], q = pq[k][1];
-          const float c = cs[k];
-          const float ap = G[p * KS + j], aq = G[q * KS + j];
-          G[p * KS + j] = c * ap - sv * aq;
-          G[q * KS + j] = sv * ap + c * aq;
+        for (int k0 = part; k0 < m / 2; k0 += 4 * nsplit) {
+          float c[4], sv[4], ap[4], aq[4];
+          int pp[4], qq[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int k = k0 + b * nsplit;
+            const bool on = k < m / 2;
+            sv[b] = on ? sn[k] : 0.f;
+            c[b] = on ? cs[k] : 1.f;
+            pp[b] = on ? pq[k][0] : 0;
+            qq[b] = on ? pq[k][1] : 0;
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (sv[b] != 0.f) {
+              ap[b] = G[pp[b] * KS + j];
+              aq[b] = G[qq[b] * KS + j];
+            }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (sv[b] != 0.f) {
+              G[pp[b] * KS + j] = c[b] * ap[b] - sv[b] * aq[b];
+              G[qq[b] * KS + j] = sv[b] * ap[b] + c[b] * aq[b];
+            }
         }
       }
       __syncthreads();
       // columns: A <- A J, V <- V J. Thread t owns row i = t mod K and the same pairs
       if (tid < nsplit * K) {
         const int i = tid - part * K;
-        for (int k = part; k < m / 2; k += nsplit) {
-          const float sv = sn[k];
-          if (sv == 0.f) continue;
-          const int p = pq[k][0], q = pq[k][1];
-          const float c = cs[k];
-          const float ap = G[i * KS + p], aq = G[i * KS + q];
-          G[i * KS + p] = c * ap - sv * aq;
-          G[i * KS + q] = sv * ap + c * aq;
-          const float vp = V[i * KS + p], vq = V[i * KS + q];
-          V[i * KS + p] = c * vp - sv * vq;
-          V[i * KS + q] = sv * vp + c * vq;
+        for (int k0 = part; k0 < m / 2; k0 += 4 * nsplit) {
+          float c[4], sv[4], ap[4], aq[4], vp[4], vq[4];
+          int pp[4], qq[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int k = k0 + b * nsplit;
+            const bool on = k < m / 2;
+            sv[b] = on ? sn[k] : 0.f;
+            c[b] = on ? cs[k] : 1.f;
+            pp[b] = on ? pq[k][0] : 0;
+            qq[b] = on ? pq[k][1] : 0;
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (sv[b] != 0.f) {
+              ap[b] = G[i * KS + pp[b]];
+              aq[b] = G[i * KS + qq[b]];
+              vp[b] = V[i * KS + pp[b]];
+              vq[b] = V[i * KS + qq[b]];
+            }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (sv[b] != 0.f) {
+              G[i * KS + pp[b]] = c[b] * ap[b] - sv[b] * aq[b];
+              G[i * KS + qq[b]] = sv[b] * ap[b] + c[b] * aq[b];
+              V[i * KS + pp[b]] = c[b] * vp[b] - sv[b] * vq[b];
+              V[i * KS + qq[b]] = sv[b] * vp[b] + c[b] * vq[b];
+            }
         }
       }
       __syncthreads();
@@ -250,18 +334,23 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   // ---- Newton-Schulz: M = V^T V (T3), V <- 1.5 V - 0.5 V M (via G)
-  for (int e = tid; e < K * K; e += kNT) {
-    const int r = e / K, c = e - r * K;
-    float d = 0.f;
-    for (int k = 0; k < K; ++k) d = fmaf(V[k * KS + r], V[k * KS + c], d);
-    T3[r * KS + c] = d;
-  }
-  __syncthreads();
-  for (int e = tid; e < K * K; e += kNT) {
-    const int r = e / K, c = e - r * K;
-    float d = 0.f;
-    for (int k = 0; k < K; ++k) d = fmaf(V[r * KS + k], T3[k * KS + c], d);
-    G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * d;
+  {
+    float acc[8][8];
+    mm_tile<true>(V, V, K, KS, ti, tj, acc);
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y)
+        if (8 * ti + x < K && 8 * tj + y < K) T3[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
+    __syncthreads();
+    mm_tile<false>(V, T3, K, KS, ti, tj, acc);
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+      for (int y = 0; y < 8; ++y) {
+        const int r = 8 * ti + x, c = 8 * tj + y;
+        if (r < K && c < K) G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * acc[x][y];
+      }
   }
   __syncthreads();
   for (int e = tid; e < K * K; e += kNT) {
@@ -270,7 +359,8 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     Vg[e] = G[r * KS + c];
   }
   // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks (fixed order)
-  float lacc = 0.f;  // thread i < K accumulates lambda_i
+  const int pi = tid >> 3, pc = tid & 7;  // 32 x 8 grid of 4 x 4 tiles over (i, column)
+  float lacc[4] = {0.f, 0.f, 0.f, 0.f};   // kept by the pc == 0 thread of each row group
   for (int c0 = 0; c0 < ncol; c0 += kChunk) {
     __syncthreads();
     for (int e = tid; e < K * kChunk; e += kNT) {
@@ -278,42 +368,97 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       T3[r * CS + cc] = Yb[(long long)r * ncol + c0 + cc];
     }
     __syncthreads();
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int i = e / kChunk, cc = e - i * kChunk;
-      float d = 0.f;
-      for (int r = 0; r < K; ++r) d = fmaf(V[r * KS + i], T3[r * CS + cc], d);
-      G[i * CS + cc] = d;
+    float acc[4][4];
+    proj_tile(V, T3, K, KS, CS, pi, pc, acc);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      float sq = 0.f;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) sq = fmaf(acc[x][y], acc[x][y], sq);
+      // the 8 threads of a row group are consecutive lanes: fixed-order butterfly sum
+      sq += __shfl_xor(sq, 1);
+      sq += __shfl_xor(sq, 2);
+      sq += __shfl_xor(sq, 4);
+      lacc[x] += sq;
     }
-    __syncthreads();
-    if (tid < K)
-      for (int cc = 0; cc < kChunk; ++cc) lacc = fmaf(G[tid * CS + cc], G[tid * CS + cc], lacc);
   }
-  if (tid < K) lam[tid] = lacc > 1.f ? 1.f - 1.f / sqrtf(lacc) : 0.f;   // f_i of the clip
-  // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks (T3: Y' chunk, G: projections)
-  for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+  if (pc == 0) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = 4 * pi + x;
+      if (i < K) lam[i] = lacc[x] > 1.f ? 1.f - 1.f / sqrtf(lacc[x]) : 0.f;  // f_i of the clip
+    }
+  }
+  __syncthreads();
+  // indices of the clipped directions, in order
+  __shared__ int ridx[112];
+  __shared__ int nr;
+  if (tid == 0) {
+    int n = 0;
+    for (int i = 0; i < K; ++i)
+      if (lam[i] > 0.f) ridx[n++] = i;
+    nr = n;
+  }
+  __syncthreads();
+  const int R = nr;
+  // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks (T3: Y' chunk, G: f V_R^T Y')
+  for (int c0 = 0; c0 < ncol && R > 0; c0 += kChunk) {
     __syncthreads();
     for (int e = tid; e < K * kChunk; e += kNT) {
       const int r = e / kChunk, cc = e - r * kChunk;
       T3[r * CS + cc] = Yb[(long long)r * ncol + c0 + cc];
     }
     __syncthreads();
-    // P[i][cc] = f_i * (v_i . y'_cc) for f_i > 0
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int i = e / kChunk, cc = e - i * kChunk;
-      float d = 0.f;
-      if (lam[i] > 0.f) {
-        for (int r = 0; r < K; ++r) d = fmaf(V[r * KS + i], T3[r * CS + cc], d);
-        d *= lam[i];
+    // projections onto the clipped directions: P[n][cc] = f_i v_i^T y'_cc, i = ridx[n]
+    for (int e = tid; e < R * (kChunk / 4); e += kNT) {
+      const int n = e / (kChunk / 4), c4 = (e - n * (kChunk / 4)) * 4;
+      const int i = ridx[n];
+      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
+      for (int r = 0; r < K; ++r) {
+        const float vv = V[r * KS + i];
+        d0 = fmaf(vv, T3[r * CS + c4], d0);
+        d1 = fmaf(vv, T3[r * CS + c4 + 1], d1);
+        d2 = fmaf(vv, T3[r * CS + c4 + 2], d2);
+        d3 = fmaf(vv, T3[r * CS + c4 + 3], d3);
       }
-      G[i * CS + cc] = d;
+      const float f = lam[i];
+      G[n * CS + c4] = f * d0;
+      G[n * CS + c4 + 1] = f * d1;
+      G[n * CS + c4 + 2] = f * d2;
+      G[n * CS + c4 + 3] = f * d3;
     }
     __syncthreads();
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int r = e / kChunk, cc = e - r * kChunk;
-      float y = T3[r * CS + cc];
-      for (int i = 0; i < K; ++i)
-        if (lam[i] > 0.f) y = fmaf(-V[r * KS + i], G[i * CS + cc], y);
-      Yb[(long long)r * ncol + c0 + cc] = y;
+    // Y+[r][cc] = Y'[r][cc] - sum_n V[r][i_n] P[n][cc]; thread tile 4 rows x 4 columns
+    {
+      float acc[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
+      for (int n = 0; n < R; ++n) {
+        const int i = ridx[n];
+        float av[4], bv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          av[x] = 4 * pi + x < K ? V[(4 * pi + x) * KS + i] : 0.f;
+          bv[x] = G[n * CS + 4 * pc + x];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int r = 4 * pi + x;
+        if (r < K) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) {
+            const int cc = 4 * pc + y;
+            Yb[(long long)r * ncol + c0 + cc] = T3[r * CS + cc] - acc[x][y];
+          }
+        }
+      }
     }
   }
 }
