@@ -8,12 +8,15 @@
 //   if every Gershgorin row bound of G is <= 1, no singular value of Y' exceeds 1 and step 10
 //   leaves Y' unchanged; otherwise
 //   A = V^T G V from the stored (orthonormal) eigenbasis V of the previous iteration,
-//   parallel cyclic Jacobi on A (round-robin pair order, all K/2 rotations of a step at once,
-//   accumulated into V) until a certificate holds: every off-diagonal entry in a row or column
+//   parallel cyclic Jacobi on A (round-robin pair order, all K/2 rotations of a step at once:
+//   a row pass and a column pass, accumulated into V) until a certificate holds: every off-diagonal entry in a row or column
 //   whose diagonal exceeds 0.999 is at most 1e-6 ||A||_F (about the FP32 rounding level of
 //   the rotations), and every other row has a Gershgorin bound <= 1, so no eigenvalue above 1
 //   hides among them (the clip factor 1 - lambda^-1/2 is continuous at 1 and uses the
-//   Rayleigh quotients below, so eigenvalues next to 1 need no separation);
+//   Rayleigh quotients below, so eigenvalues next to 1 need no separation). A sweep rotates
+//   only pairs with a row that failed this test when the sweep began (a pair of two certified
+//   rows needs nothing; from the fifth sweep on, every pair), so with the warm basis a step
+//   touches a few rows and columns of A instead of all of them;
 //   one Newton-Schulz step V <- V (3 I - V^T V) / 2 restores orthonormality lost to rounding;
 //   lambda_i = ||v_i^T Y'||^2 (Rayleigh quotients, more accurate than the rotated diagonal);
 //   Y+ = Y' - V_R diag(1 - lambda^-1/2) V_R^T Y'   over R = {i : lambda_i > 1}
@@ -32,16 +35,35 @@ constexpr int kNT = 256;
 constexpr int kChunk = 32;
 // Rows whose diagonal exceeds this take part in the off-diagonal test of the certificate.
 constexpr float kNearOne = 0.999f;
+// Sweeps that rotate only pairs touching a row that failed the certificate; later sweeps
+// rotate every pair above the skip threshold.
+constexpr int kRestricted = 4;
+// Pairs a wave rotates per batch of a rotation pass (a wave has at most
+// ceil((kBigMax / 2) / 2) = 25 pairs, so two batches).
+constexpr int kBatch = 13;
+// Rotation records of a step (K / 2 <= 50 used; reads past the active ones are clamped here
+// and their values ignored).
+constexpr int kRotSlots = 64;
+static_assert(kBigMax <= 128 && kNT == 256, "rotation pass mapping");
+
+// Value of x in lane u of the wave (u a compile-time constant).
+__device__ inline float lane_value(float x, int u) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), u));
+}
 
 __device__ inline int wrapm(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
 
 // Round-robin pairing of m (even) indices, step s (0 <= s < m - 1), pair k (0 <= k < m / 2):
 // index m - 1 stays, the others rotate.
 __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
-  const int n = m - 1;
-  int x = k == 0 ? n : (s + k) % n;
-  int y = (s + n - k) % n;
-  if (k == 0) y = s % n;
+  const int n = m - 1;  // 0 <= s < n, 0 <= k < m / 2
+  int x = n, y = s;
+  if (k != 0) {
+    x = s + k;
+    y = s + n - k;
+    x = x >= n ? x - n : x;
+    y = y >= n ? y - n : y;
+  }
   p = min(x, y);
   q = max(x, y);
 }
@@ -93,6 +115,12 @@ __device__ inline void proj_tile(const float *V, const float *Y, int K, int KS, 
   }
 }
 
+// One rotation of a Jacobi step: J = [[c, s], [-s, c]] on the index pair p < q.
+struct __align__(16) Rot {
+  float c, s;
+  int p, q;
+};
+
 }  // namespace
 
 __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
@@ -102,8 +130,10 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   float *G = lds;                 // K x GS: Gram, then A, then projections of a chunk
   float *V = G + K * GS;          // K x KS: eigenbasis, column c = vector c
   float *T3 = V + K * KS;         // K x GS: H = G V, V^T V, or a Y' column chunk
-  __shared__ float cs[64], sn[64], lam[112];
-  __shared__ int pq[64][2];
+  __shared__ Rot rot[kRotSlots];
+  __shared__ float lam[112];
+  __shared__ bool hot[112];
+  __shared__ int nact;
   __shared__ float red[kNT / 64];
   __shared__ int flag;
   if (a.sc->done) return;
@@ -206,9 +236,14 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   __syncthreads();
 
   // ---- parallel cyclic Jacobi
-  const int m = (K + 1) & ~1;  // even; index K (if m > K) is a dummy
-  const int nsplit = kNT / K;  // threads per column (row) in the rotation phases
-  const int part = tid / K;
+  const int m = (K + 1) & ~1;  // even; index K (if m > K) is a dummy whose rotation is identity
+  const int H = m / 2;         // pairs per step
+  // row / column passes: ceil(K / 64) waves per group of pairs, each wave covering a run of
+  // cpw consecutive indices vi; ngV groups
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int wpg = (K + 63) >> 6, ngV = (kNT / 64) / wpg, cpw = (K + wpg - 1) / wpg;
+  const int vkg = wave / wpg, vi = (wave - vkg * wpg) * cpw + lane, viK = vi * KS;
+  const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
   int sweeps = 0;
   for (; sweeps < a.max_sweeps; ++sweeps) {
     // certificate (see the header): one thread per row
@@ -231,7 +266,9 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
         sum += x;
         if (dr > kNearOne || G[c * KS + c] > kNearOne) mx = fmaxf(mx, x);
       }
-      if (mx > tol || (dr <= kNearOne && dr + sum > 1.f)) atomicOr(&flag, 1);
+      const bool fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
+      if (fail) atomicOr(&flag, 1);
+      hot[tid] = fail || sweeps >= kRestricted;
     }
     __syncthreads();
     const int notyet = flag;
@@ -239,89 +276,95 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     if (!notyet) break;
     const float skip = 0.1f * tol;
     for (int s = 0; s < m - 1; ++s) {
-      if (tid < m / 2) {
-        int p, q;
-        rr_pair(m, s, tid, p, q);
+      // rotation angles; a pair rotates only if a row of it failed the certificate at the
+      // start of the sweep (pairs of two certified rows need nothing) and its entry exceeds
+      // the skip threshold. The active pairs are stored first, in pair order.
+      if (tid < 64) {
+        int p = 0, q = 0;
         float c = 1.f, sv = 0.f;
-        if (q < K) {
-          const float apq = G[p * KS + q];
-          if (fabsf(apq) > skip) {  // threshold Jacobi: pairs already below skip stay
-            const float app = G[p * KS + p], aqq = G[q * KS + q];
-            const float zeta = (aqq - app) / (2.f * apq);
-            const float t = fabsf(zeta) > 1e15f
-                                ? 0.5f / zeta
-                                : copysignf(1.f, zeta) / (fabsf(zeta) + sqrtf(1.f + zeta * zeta));
-            c = 1.f / sqrtf(1.f + t * t);
+        if (tid < H) {
+          rr_pair(m, s, tid, p, q);
+          const int qq = q < K ? q : p;
+          const float apq = G[p * KS + qq], app = G[p * KS + p], aqq = G[qq * KS + qq];
+          if (q < K && (hot[p] || hot[q]) && fabsf(apq) > skip) {
+            // tan of the rotation angle, |t| <= 1 (hardware reciprocal and square roots: the
+            // rotation stays orthogonal to about 1e-7 and the basis is re-orthonormalised)
+            const float zeta = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
+            const float az = fabsf(zeta);
+            const float t = az > 1e15f ? 0.5f * __builtin_amdgcn_rcpf(zeta)
+                                       : copysignf(__builtin_amdgcn_rcpf(az + __builtin_sqrtf(fmaf(zeta, zeta, 1.f))), zeta);
+            c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
             sv = t * c;
           }
         }
-        cs[tid] = c;
-        sn[tid] = sv;
-        pq[tid][0] = p;
-        pq[tid][1] = q;
+        const unsigned long long act = __ballot(sv != 0.f);
+        const int na = __popcll(act);
+        const int before = __popcll(act & ((1ull << tid) - 1ull));
+        if (tid < H) rot[sv != 0.f ? before : na + tid - before] = Rot{c, sv, p, q};
+        if (tid == 0) nact = na;
       }
       __syncthreads();
-      // rows: A <- J^T A. Thread t < nsplit K owns column j = t mod K and every nsplit-th pair,
-      // four pairs at a time (their rows are distinct, so the loads overlap)
-      if (tid < nsplit * K) {
-        const int j = tid - part * K;
-        for (int k0 = part; k0 < m / 2; k0 += 4 * nsplit) {
-          float c[4], sv[4], ap[4], aq[4];
-          int pp[4], qq[4];
+      const int na = __builtin_amdgcn_readfirstlane(nact);
+      // rows: A <- J^T A over the active pairs. Each wave serves one group of pairs (every
+      // ngV-th active pair, kBatch at a time) and its lanes cover a run of columns; the
+      // rotation is wave-uniform and held in scalar registers
+      if (von) {
+        for (int k0 = vkg; k0 < na; k0 += kBatch * ngV) {
+          float c[kBatch], sn[kBatch], ap[kBatch], aq[kBatch];
+          int pK[kBatch], qK[kBatch];
+          // lane u (< kBatch, always active) loads the record of item u; readlane broadcasts
+          const Rot mine = rot[min(k0 + lane * ngV, kRotSlots - 1)];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int k = k0 + b * nsplit;
-            const bool on = k < m / 2;
-            sv[b] = on ? sn[k] : 0.f;
-            c[b] = on ? cs[k] : 1.f;
-            pp[b] = on ? pq[k][0] : 0;
-            qq[b] = on ? pq[k][1] : 0;
+          for (int u = 0; u < kBatch; ++u) {
+            c[u] = lane_value(mine.c, u);
+            sn[u] = lane_value(mine.s, u);
+            pK[u] = __builtin_amdgcn_readlane(mine.p, u) * KS;
+            qK[u] = __builtin_amdgcn_readlane(mine.q, u) * KS;
           }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (sv[b] != 0.f) {
-              ap[b] = G[pp[b] * KS + j];
-              aq[b] = G[qq[b] * KS + j];
+          for (int u = 0; u < kBatch; ++u)
+            if (k0 + u * ngV < na) {
+              ap[u] = G[pK[u] + vi];
+              aq[u] = G[qK[u] + vi];
             }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (sv[b] != 0.f) {
-              G[pp[b] * KS + j] = c[b] * ap[b] - sv[b] * aq[b];
-              G[qq[b] * KS + j] = sv[b] * ap[b] + c[b] * aq[b];
+          for (int u = 0; u < kBatch; ++u)
+            if (k0 + u * ngV < na) {
+              G[pK[u] + vi] = c[u] * ap[u] - sn[u] * aq[u];
+              G[qK[u] + vi] = sn[u] * ap[u] + c[u] * aq[u];
             }
         }
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J. Thread t owns row i = t mod K and the same pairs
-      if (tid < nsplit * K) {
-        const int i = tid - part * K;
-        for (int k0 = part; k0 < m / 2; k0 += 4 * nsplit) {
-          float c[4], sv[4], ap[4], aq[4], vp[4], vq[4];
-          int pp[4], qq[4];
+      // columns: A <- A J, V <- V J, lanes over rows (row stride K + 1 is odd, so they hit
+      // distinct banks); the entry the rotation annihilates is set to 0
+      if (von) {
+        for (int k0 = vkg; k0 < na; k0 += kBatch * ngV) {
+          float c[kBatch], sn[kBatch], ap[kBatch], aq[kBatch], vp[kBatch], vq[kBatch];
+          int pp[kBatch], qq[kBatch];
+          const Rot mine = rot[min(k0 + lane * ngV, kRotSlots - 1)];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int k = k0 + b * nsplit;
-            const bool on = k < m / 2;
-            sv[b] = on ? sn[k] : 0.f;
-            c[b] = on ? cs[k] : 1.f;
-            pp[b] = on ? pq[k][0] : 0;
-            qq[b] = on ? pq[k][1] : 0;
+          for (int u = 0; u < kBatch; ++u) {
+            c[u] = lane_value(mine.c, u);
+            sn[u] = lane_value(mine.s, u);
+            pp[u] = __builtin_amdgcn_readlane(mine.p, u);
+            qq[u] = __builtin_amdgcn_readlane(mine.q, u);
           }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (sv[b] != 0.f) {
-              ap[b] = G[i * KS + pp[b]];
-              aq[b] = G[i * KS + qq[b]];
-              vp[b] = V[i * KS + pp[b]];
-              vq[b] = V[i * KS + qq[b]];
+          for (int u = 0; u < kBatch; ++u)
+            if (k0 + u * ngV < na) {
+              ap[u] = G[viK + pp[u]];
+              aq[u] = G[viK + qq[u]];
+              vp[u] = V[viK + pp[u]];
+              vq[u] = V[viK + qq[u]];
             }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-            if (sv[b] != 0.f) {
-              G[i * KS + pp[b]] = c[b] * ap[b] - sv[b] * aq[b];
-              G[i * KS + qq[b]] = sv[b] * ap[b] + c[b] * aq[b];
-              V[i * KS + pp[b]] = c[b] * vp[b] - sv[b] * vq[b];
-              V[i * KS + qq[b]] = sv[b] * vp[b] + c[b] * vq[b];
+          for (int u = 0; u < kBatch; ++u)
+            if (k0 + u * ngV < na) {
+              G[viK + pp[u]] = vi == qq[u] ? 0.f : c[u] * ap[u] - sn[u] * aq[u];
+              G[viK + qq[u]] = vi == pp[u] ? 0.f : sn[u] * ap[u] + c[u] * aq[u];
+              V[viK + pp[u]] = c[u] * vp[u] - sn[u] * vq[u];
+              V[viK + qq[u]] = sn[u] * vp[u] + c[u] * vq[u];
             }
         }
       }
@@ -330,6 +373,8 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   if (tid == 0) {
     atomicMax(&a.sc->max_sweeps, sweeps);
+    atomicAdd(&a.sc->step_sum, (unsigned long long)sweeps);  // sweeps per clipped block
+    atomicAdd(&a.sc->step_blocks, 1ull);
     if (sweeps == a.max_sweeps) atomicAdd(&a.sc->fallback_blocks, 1ull);  // not certified
   }
   __syncthreads();
