@@ -33,6 +33,17 @@ namespace {
 
 constexpr int kNT = 256;
 constexpr int kChunk = 32;
+// Row stride of a staged Y' chunk in the Gram: 34 makes the MFMA operand reads of a half-wave
+// (rows i = 0..15, columns g = 0..1) hit 32 distinct banks.
+constexpr int kGS = kChunk + 2;
+// 16 x 16 Gram tiles per wave: ceil(28 / 4) for K <= 112 (7 x 7 tiles, upper triangle).
+constexpr int kGramTiles = 7;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Chunk elements a thread stages: ceil(kBigMax * kChunk / kNT).
+constexpr int kStage = (kBigMax * kChunk + kNT - 1) / kNT;
+static_assert(kChunk == 32 && kNT == 256, "chunk staging maps thread t to rows t/32 + 8k");
 // Rows whose diagonal exceeds this take part in the off-diagonal test of the certificate.
 constexpr float kNearOne = 0.999f;
 // Sweeps that rotate only pairs touching a row that failed the certificate; later sweeps
@@ -121,12 +132,25 @@ struct __align__(16) Rot {
   int p, q;
 };
 
+// T[r * ts + c] = Y[r * ncol + c0 + c] for the K x 32 chunk at column c0; thread t moves
+// rows srow + 8 k, column scol, all of its loads issued before the first store.
+__device__ inline void stage_chunk(const float *Y, int ncol, int c0, int K, int srow, int scol,
+                                   float *T, int ts) {
+  float y[kStage];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k)
+    if (srow + 8 * k < K) y[k] = Y[(long long)(srow + 8 * k) * ncol + c0 + scol];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k)
+    if (srow + 8 * k < K) T[(srow + 8 * k) * ts + scol] = y[k];
+}
+
 }  // namespace
 
 __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   extern __shared__ float lds[];
   const int K = a.K, KS = a.K + 1;
-  const int GS = KS > kChunk + 1 ? KS : kChunk + 1;
+  const int GS = KS > kGS ? KS : kGS;
   float *G = lds;                 // K x GS: Gram, then A, then projections of a chunk
   float *V = G + K * GS;          // K x KS: eigenbasis, column c = vector c
   float *T3 = V + K * KS;         // K x GS: H = G V, V^T V, or a Y' column chunk
@@ -144,46 +168,87 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   float *Yb = a.Y + blk * (long long)K * ncol;
   const int CS = kChunk + 1;
 
-  // ---- Gram over column chunks; Y' is written back
-  // thread (ti, tj) of a 16 x 16 grid owns rows 8 ti .. 8 ti + 7 and columns 8 tj .. 8 tj + 7
-  const int ti = tid >> 4, tj = tid & 15;
-  float acc[8][8];
+  // ---- Gram over column chunks on v_mfma_f32_16x16x4_f32; Y' is written back. The K x K
+  // Gram is cut into 16 x 16 tiles; the tiles on and above the diagonal are dealt round-robin
+  // to the four waves. In a 16x16x4 step, lane 16 g + i supplies row i, column g of the
+  // A operand and row g, column i of the B operand, so with both taken from the staged chunk
+  // (rows 16 I + i and 16 J + i, column 4 s + g) a tile accumulates Y'_I Y'_J^T.
+  const int ti = tid >> 4, tj = tid & 15;  // 16 x 16 thread grid of the K x K products
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int srow = tid >> 5, scol = tid & 31;  // chunk staging: rows srow + 8 k, column scol
+  {
+    const int nt = (K + 15) >> 4, ntiles = nt * (nt + 1) / 2;
+    int tI[kGramTiles], tJ[kGramTiles];
 #pragma unroll
-  for (int x = 0; x < 8; ++x)
-#pragma unroll
-    for (int y = 0; y < 8; ++y) acc[x][y] = 0.f;
-  for (int c0 = 0; c0 < ncol; c0 += kChunk) {
-    __syncthreads();
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int r = e / kChunk, cc = e - r * kChunk, col = c0 + cc;
-      const int ra = r / a.k2, rc = r - ra * a.k2;
-      const long long pix = (long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2);
-      const float y = Yb[(long long)r * ncol + col] + a.gY * a.gradf[pix * ncol + col];
-      Yb[(long long)r * ncol + col] = y;
-      T3[r * CS + cc] = y;
-    }
-    __syncthreads();
-    for (int cc = 0; cc < kChunk; ++cc) {
-      float yr[8], yc[8];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) {
-        const int r = 8 * ti + x, c = 8 * tj + x;
-        yr[x] = r < K ? T3[r * CS + cc] : 0.f;
-        yc[x] = c < K ? T3[c * CS + cc] : 0.f;
+    for (int m = 0; m < kGramTiles; ++m) {
+      int rem = wave + 4 * m, I = 0;
+      while (I < nt && rem >= nt - I) {
+        rem -= nt - I;
+        ++I;
       }
+      tI[m] = I;
+      tJ[m] = I + rem;  // valid only if wave + 4 m < ntiles
+    }
+    f4 gacc[kGramTiles];
 #pragma unroll
-      for (int x = 0; x < 8; ++x)
+    for (int m = 0; m < kGramTiles; ++m) gacc[m] = f4{0.f, 0.f, 0.f, 0.f};
+    // staging: thread t moves rows t / 32 + 8 k, column t mod 32 of each chunk; the field
+    // offset of each row's pixel is fixed for the block
+    long long goff[kStage];
 #pragma unroll
-        for (int y = 0; y < 8; ++y) acc[x][y] = fmaf(yr[x], yc[y], acc[x][y]);
+    for (int k = 0; k < kStage; ++k) {
+      const int r = srow + 8 * k;
+      const int ra = r / a.k2, rc = r - ra * a.k2;
+      goff[k] = r < K ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol : 0;
+    }
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      __syncthreads();
+      // all loads of the chunk first, then the stores (the stores could alias later loads)
+      float yv[kStage], gv[kStage];
+#pragma unroll
+      for (int k = 0; k < kStage; ++k)
+        if (srow + 8 * k < K) {
+          yv[k] = Yb[(long long)(srow + 8 * k) * ncol + c0 + scol];
+          gv[k] = a.gradf[goff[k] + c0 + scol];
+        }
+#pragma unroll
+      for (int k = 0; k < kStage; ++k)
+        if (srow + 8 * k < K) {
+          const float y = yv[k] + a.gY * gv[k];
+          Yb[(long long)(srow + 8 * k) * ncol + c0 + scol] = y;
+          T3[(srow + 8 * k) * kGS + scol] = y;
+        }
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < kGramTiles; ++m) {
+        if (wave + 4 * m < ntiles) {
+          const int ra = 16 * tI[m] + i16, rb = 16 * tJ[m] + i16;
+          const float *pa = T3 + ra * kGS + g4, *pb = T3 + rb * kGS + g4;
+#pragma unroll
+          for (int st = 0; st < kChunk / 4; ++st) {
+            const float av = ra < K ? pa[4 * st] : 0.f, bv = rb < K ? pb[4 * st] : 0.f;
+            gacc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, gacc[m], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // result layout: lane i + 16 g, register v holds tile entry (4 g + v, i)
+#pragma unroll
+    for (int m = 0; m < kGramTiles; ++m) {
+      if (wave + 4 * m < ntiles) {
+        const int c = 16 * tJ[m] + i16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * tI[m] + 4 * g4 + v;
+          if (r < K && c < K) {
+            G[r * KS + c] = gacc[m][v];
+            if (tI[m] != tJ[m]) G[c * KS + r] = gacc[m][v];
+          }
+        }
+      }
     }
   }
-#pragma unroll
-  for (int x = 0; x < 8; ++x)
-#pragma unroll
-    for (int y = 0; y < 8; ++y) {
-      const int r = 8 * ti + x, c = 8 * tj + y;
-      if (r < K && c < K) G[r * KS + c] = acc[x][y];
-    }
   if (tid == 0) flag = 0;
   __syncthreads();
   // ---- finiteness and the Gershgorin bound: max_i sum_j |G_ij| <= 1 => nothing to clip
@@ -240,7 +305,6 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   const int H = m / 2;         // pairs per step
   // row / column passes: ceil(K / 64) waves per group of pairs, each wave covering a run of
   // cpw consecutive indices vi; ngV groups
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int wpg = (K + 63) >> 6, ngV = (kNT / 64) / wpg, cpw = (K + wpg - 1) / wpg;
   const int vkg = wave / wpg, vi = (wave - vkg * wpg) * cpw + lane, viK = vi * KS;
   const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
@@ -408,10 +472,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   float lacc[4] = {0.f, 0.f, 0.f, 0.f};   // kept by the pc == 0 thread of each row group
   for (int c0 = 0; c0 < ncol; c0 += kChunk) {
     __syncthreads();
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int r = e / kChunk, cc = e - r * kChunk;
-      T3[r * CS + cc] = Yb[(long long)r * ncol + c0 + cc];
-    }
+    stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
     __syncthreads();
     float acc[4][4];
     proj_tile(V, T3, K, KS, CS, pi, pc, acc);
@@ -449,10 +510,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks (T3: Y' chunk, G: f V_R^T Y')
   for (int c0 = 0; c0 < ncol && R > 0; c0 += kChunk) {
     __syncthreads();
-    for (int e = tid; e < K * kChunk; e += kNT) {
-      const int r = e / kChunk, cc = e - r * kChunk;
-      T3[r * CS + cc] = Yb[(long long)r * ncol + c0 + cc];
-    }
+    stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
     __syncthreads();
     // projections onto the clipped directions: P[n][cc] = f_i v_i^T y'_cc, i = ridx[n]
     for (int e = tid; e < R * (kChunk / 4); e += kNT) {
@@ -539,7 +597,7 @@ __global__ __launch_bounds__(kNT) void k_big_identity(float *V, long long nblk, 
 
 size_t big_lds_bytes(int K) {
   const int KS = K + 1;
-  const int GS = KS > kChunk + 1 ? KS : kChunk + 1;
+  const int GS = KS > kGS ? KS : kGS;
   return (size_t)(2 * K * GS + K * KS) * sizeof(float);
 }
 
