@@ -79,50 +79,54 @@ __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
   q = max(x, y);
 }
 
-// C (K x K) = op(A) B with A and B in LDS (row stride KS); op(A) = A^T when TA. Thread
-// (ti, tj) of a 16 x 16 grid forms the 8 x 8 tile at rows 8 ti, columns 8 tj (K <= 128), so
-// each k costs 16 LDS reads for 64 independent FMAs.
-template <bool TA>
-__device__ inline void mm_tile(const float *A, const float *B, int K, int KS, int ti, int tj,
-                               float acc[8][8]) {
+// A band of NJ 16 x 16 tiles (rows 16 I .., columns 16 (J0 + j) ..) of C = op(A) B over
+// k < kd on v_mfma_f32_16x16x4_f32, with op(A)[r][k] = TA ? A[k * as + r] : A[r * as + k] and
+// B[k][c] = B[k * bs + c]. Lane i + 16 g supplies op(A)[16 I + i][k0 + g] (shared by the
+// band) and B[k0 + g][16 (J0 + j) + i]; result lane i + 16 g, register v of tile j holds
+// C[16 I + 4 g + v][16 (J0 + j) + i]. Row and column indices are clamped to nr - 1, nc - 1
+// (those outputs are not used) and k >= kd contributes zero, so every load is unconditional.
+template <bool TA, int NJ>
+__device__ inline void mfma_band(const float *A, int as, const float *B, int bs, int kd, int nr,
+                                 int nc, int I, int J0, int i16, int g4, f4 acc[NJ]) {
 #pragma unroll
-  for (int x = 0; x < 8; ++x)
+  for (int j = 0; j < NJ; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int r = min(16 * I + i16, nr - 1);
+  int c[NJ];
 #pragma unroll
-    for (int y = 0; y < 8; ++y) acc[x][y] = 0.f;
-  for (int k = 0; k < K; ++k) {
-    float av[8], bv[8];
+  for (int j = 0; j < NJ; ++j) c[j] = min(16 * (J0 + j) + i16, nc - 1);
+#pragma unroll 4
+  for (int k0 = 0; k0 < kd; k0 += 4) {
+    const int k = min(k0 + g4, kd - 1);
+    const bool kok = k0 + g4 < kd;
+    const float a0 = TA ? A[k * as + r] : A[r * as + k];
+    const float av = kok ? a0 : 0.f;
 #pragma unroll
-    for (int x = 0; x < 8; ++x) {
-      const int r = 8 * ti + x, c = 8 * tj + x;
-      av[x] = r < K ? (TA ? A[k * KS + r] : A[r * KS + k]) : 0.f;
-      bv[x] = c < K ? B[k * KS + c] : 0.f;
-    }
-#pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+    for (int j = 0; j < NJ; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, B[k * bs + c[j]], acc[j], 0, 0, 0);
   }
 }
 
-// P (K x 32, row stride cs) = V^T Y (Y: K x 32 chunk, row stride cs); thread (ti, tc) of a
-// 32 x 8 grid forms rows 4 ti .. 4 ti + 3, columns 4 tc .. 4 tc + 3.
-__device__ inline void proj_tile(const float *V, const float *Y, int K, int KS, int cs, int ti,
-                                 int tc, float acc[4][4]) {
+// C = op(A) B for K x K operands (row strides as, bs): bands of four tiles (row tile I,
+// column tiles 4 h .. 4 h + 3) dealt round-robin to the four waves; out(r, c, value) is
+// applied to every entry in range.
+template <bool TA, typename Out>
+__device__ inline void mfma_kk(const float *A, int as, const float *B, int bs, int K, int wave,
+                               int i16, int g4, Out out) {
+  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
+#pragma unroll 1
+  for (int t = wave; t < nt * nh; t += 4) {
+    const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
+    f4 acc[4];
+    mfma_band<TA, 4>(A, as, B, bs, K, K, K, I, J0, i16, g4, acc);
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+    for (int j = 0; j < 4; ++j) {
+      const int cc = 16 * (J0 + j) + i16;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
-  for (int r = 0; r < K; ++r) {
-    float av[4], bv[4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      av[x] = 4 * ti + x < K ? V[r * KS + 4 * ti + x] : 0.f;
-      bv[x] = Y[r * cs + 4 * tc + x];
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * I + 4 * g4 + v;
+        if (r < K && cc < K) out(r, cc, acc[j][v]);
+      }
     }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
   }
 }
 
@@ -173,7 +177,6 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   // to the four waves. In a 16x16x4 step, lane 16 g + i supplies row i, column g of the
   // A operand and row g, column i of the B operand, so with both taken from the staged chunk
   // (rows 16 I + i and 16 J + i, column 4 s + g) a tile accumulates Y'_I Y'_J^T.
-  const int ti = tid >> 4, tj = tid & 15;  // 16 x 16 thread grid of the K x K products
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int srow = tid >> 5, scol = tid & 31;  // chunk staging: rows srow + 8 k, column scol
@@ -272,22 +275,11 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   // ---- A = V^T (G V): H = G V into T3, then A into G
-  {
-    float acc[8][8];
-    mm_tile<false>(G, V, K, KS, ti, tj, acc);
-#pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y)
-        if (8 * ti + x < K && 8 * tj + y < K) T3[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
-    __syncthreads();
-    mm_tile<true>(V, T3, K, KS, ti, tj, acc);
-#pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y)
-        if (8 * ti + x < K && 8 * tj + y < K) G[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
-  }
+  mfma_kk<false>(G, KS, V, KS, K, wave, i16, g4,
+                 [&](int r, int c, float x) { T3[r * KS + c] = x; });
+  __syncthreads();
+  mfma_kk<true>(V, KS, T3, KS, K, wave, i16, g4,
+                [&](int r, int c, float x) { G[r * KS + c] = x; });
   __syncthreads();
   // symmetrise exactly
   for (int e = tid; e < K * K; e += kNT) {
@@ -443,56 +435,59 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   // ---- Newton-Schulz: M = V^T V (T3), V <- 1.5 V - 0.5 V M (via G)
-  {
-    float acc[8][8];
-    mm_tile<true>(V, V, K, KS, ti, tj, acc);
-#pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y)
-        if (8 * ti + x < K && 8 * tj + y < K) T3[(8 * ti + x) * KS + 8 * tj + y] = acc[x][y];
-    __syncthreads();
-    mm_tile<false>(V, T3, K, KS, ti, tj, acc);
-#pragma unroll
-    for (int x = 0; x < 8; ++x)
-#pragma unroll
-      for (int y = 0; y < 8; ++y) {
-        const int r = 8 * ti + x, c = 8 * tj + y;
-        if (r < K && c < K) G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * acc[x][y];
-      }
-  }
+  mfma_kk<true>(V, KS, V, KS, K, wave, i16, g4,
+                [&](int r, int c, float x) { T3[r * KS + c] = x; });
+  __syncthreads();
+  mfma_kk<false>(V, KS, T3, KS, K, wave, i16, g4,
+                 [&](int r, int c, float x) { G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x; });
   __syncthreads();
   for (int e = tid; e < K * K; e += kNT) {
     const int r = e / K, c = e - r * K;
     V[r * KS + c] = G[r * KS + c];
     Vg[e] = G[r * KS + c];
   }
-  // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks (fixed order)
-  const int pi = tid >> 3, pc = tid & 7;  // 32 x 8 grid of 4 x 4 tiles over (i, column)
-  float lacc[4] = {0.f, 0.f, 0.f, 0.f};   // kept by the pc == 0 thread of each row group
-  for (int c0 = 0; c0 < ncol; c0 += kChunk) {
-    __syncthreads();
-    stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
-    __syncthreads();
-    float acc[4][4];
-    proj_tile(V, T3, K, KS, CS, pi, pc, acc);
+  // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks: P = V^T Y' per
+  // chunk on MFMA tiles; wave w owns the row tiles I = w, w + 4 (both column tiles of each),
+  // so every lambda_i is summed by one wave in a fixed order
+  const int pi = tid >> 3, pc = tid & 7;  // 32 x 8 grid of 4 x 4 tiles (clip pass)
+  {
+    const int nt = (K + 15) >> 4;
+    float lacc[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      __syncthreads();
+      stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
+      __syncthreads();
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      float sq = 0.f;
+      for (int m = 0; m < 2; ++m) {
+        const int I = wave + 4 * m;
+        if (I < nt) {
+          f4 acc[kChunk / 16];
+          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
 #pragma unroll
-      for (int y = 0; y < 4; ++y) sq = fmaf(acc[x][y], acc[x][y], sq);
-      // the 8 threads of a row group are consecutive lanes: fixed-order butterfly sum
-      sq += __shfl_xor(sq, 1);
-      sq += __shfl_xor(sq, 2);
-      sq += __shfl_xor(sq, 4);
-      lacc[x] += sq;
+          for (int J = 0; J < kChunk / 16; ++J) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              // sum over the 16 columns of the tile (lanes i16 of one g4 group), fixed order
+              float sq = acc[J][v] * acc[J][v];
+              sq += __shfl_xor(sq, 1);
+              sq += __shfl_xor(sq, 2);
+              sq += __shfl_xor(sq, 4);
+              sq += __shfl_xor(sq, 8);
+              lacc[m][v] += sq;
+            }
+          }
+        }
+      }
     }
-  }
-  if (pc == 0) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      const int i = 4 * pi + x;
-      if (i < K) lam[i] = lacc[x] > 1.f ? 1.f - 1.f / sqrtf(lacc[x]) : 0.f;  // f_i of the clip
+    for (int m = 0; m < 2; ++m) {
+      const int I = wave + 4 * m;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * I + 4 * g4 + v;
+        if (I < nt && i16 == 0 && i < K)
+          lam[i] = lacc[m][v] > 1.f ? 1.f - 1.f / sqrtf(lacc[m][v]) : 0.f;  // f_i of the clip
+      }
     }
   }
   __syncthreads();
