@@ -136,14 +136,18 @@ struct __align__(16) Rot {
   int p, q;
 };
 
-// T[r * ts + c] = Y[r * ncol + c0 + c] for the K x 32 chunk at column c0; thread t moves
-// rows srow + 8 k, column scol, all of its loads issued before the first store.
-__device__ inline void stage_chunk(const float *Y, int ncol, int c0, int K, int srow, int scol,
-                                   float *T, int ts) {
-  float y[kStage];
+// The K x 32 chunk of Y at column c0 (row stride ncol) into registers: thread t holds rows
+// srow + 8 k, column scol. Loading the next chunk before working on the current one hides
+// the memory latency.
+__device__ inline void load_chunk(const float *Y, int ncol, int c0, int K, int srow, int scol,
+                                  float y[kStage]) {
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
     if (srow + 8 * k < K) y[k] = Y[(long long)(srow + 8 * k) * ncol + c0 + scol];
+}
+
+__device__ inline void store_chunk(const float y[kStage], int K, int srow, int scol, float *T,
+                                   int ts) {
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
     if (srow + 8 * k < K) T[(srow + 8 * k) * ts + scol] = y[k];
@@ -205,16 +209,14 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       const int ra = r / a.k2, rc = r - ra * a.k2;
       goff[k] = r < K ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol : 0;
     }
+    // the loads of chunk c0 + 32 are issued before the products of chunk c0
+    float yv[kStage], gv[kStage];
+    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
+#pragma unroll
+    for (int k = 0; k < kStage; ++k)
+      if (srow + 8 * k < K) gv[k] = a.gradf[goff[k] + scol];
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();
-      // all loads of the chunk first, then the stores (the stores could alias later loads)
-      float yv[kStage], gv[kStage];
-#pragma unroll
-      for (int k = 0; k < kStage; ++k)
-        if (srow + 8 * k < K) {
-          yv[k] = Yb[(long long)(srow + 8 * k) * ncol + c0 + scol];
-          gv[k] = a.gradf[goff[k] + c0 + scol];
-        }
 #pragma unroll
       for (int k = 0; k < kStage; ++k)
         if (srow + 8 * k < K) {
@@ -222,6 +224,12 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
           Yb[(long long)(srow + 8 * k) * ncol + c0 + scol] = y;
           T3[(srow + 8 * k) * kGS + scol] = y;
         }
+      if (c0 + kChunk < ncol) {
+        load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
+#pragma unroll
+        for (int k = 0; k < kStage; ++k)
+          if (srow + 8 * k < K) gv[k] = a.gradf[goff[k] + c0 + kChunk + scol];
+      }
       __syncthreads();
 #pragma unroll
       for (int m = 0; m < kGramTiles; ++m) {
@@ -449,13 +457,15 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks: P = V^T Y' per
   // chunk on MFMA tiles; wave w owns the row tiles I = w, w + 4 (both column tiles of each),
   // so every lambda_i is summed by one wave in a fixed order
-  const int pi = tid >> 3, pc = tid & 7;  // 32 x 8 grid of 4 x 4 tiles (clip pass)
   {
     const int nt = (K + 15) >> 4;
     float lacc[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    float yv[kStage];
+    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();
-      stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
+      store_chunk(yv, K, srow, scol, T3, CS);
+      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
@@ -502,58 +512,63 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   const int R = nr;
-  // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks (T3: Y' chunk, G: f V_R^T Y')
-  for (int c0 = 0; c0 < ncol && R > 0; c0 += kChunk) {
-    __syncthreads();
-    stage_chunk(Yb, ncol, c0, K, srow, scol, T3, CS);
-    __syncthreads();
-    // projections onto the clipped directions: P[n][cc] = f_i v_i^T y'_cc, i = ridx[n]
-    for (int e = tid; e < R * (kChunk / 4); e += kNT) {
-      const int n = e / (kChunk / 4), c4 = (e - n * (kChunk / 4)) * 4;
-      const int i = ridx[n];
-      float d0 = 0.f, d1 = 0.f, d2 = 0.f, d3 = 0.f;
-      for (int r = 0; r < K; ++r) {
-        const float vv = V[r * KS + i];
-        d0 = fmaf(vv, T3[r * CS + c4], d0);
-        d1 = fmaf(vv, T3[r * CS + c4 + 1], d1);
-        d2 = fmaf(vv, T3[r * CS + c4 + 2], d2);
-        d3 = fmaf(vv, T3[r * CS + c4 + 3], d3);
-      }
-      const float f = lam[i];
-      G[n * CS + c4] = f * d0;
-      G[n * CS + c4 + 1] = f * d1;
-      G[n * CS + c4 + 2] = f * d2;
-      G[n * CS + c4 + 3] = f * d3;
-    }
-    __syncthreads();
-    // Y+[r][cc] = Y'[r][cc] - sum_n V[r][i_n] P[n][cc]; thread tile 4 rows x 4 columns
-    {
-      float acc[4][4];
+  // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks on MFMA tiles (T3: Y' chunk,
+  // G: P = diag(f) V_R^T Y', R x 32). V_R is read through ridx, so it is never compacted.
+  if (R > 0) {
+    const int nR = (R + 15) >> 4, nt = (K + 15) >> 4;
+    float yv[kStage];
+    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      __syncthreads();
+      store_chunk(yv, K, srow, scol, T3, CS);
+      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
+      __syncthreads();
+      // P: row tile I over the clipped directions n (lane supplies V[k][ridx[n]]), k over K
+      for (int I = wave; I < nR; I += 4) {
+        const int vc = ridx[min(16 * I + i16, R - 1)];
+        f4 acc[kChunk / 16] = {};
+#pragma unroll 4
+        for (int k0 = 0; k0 < K; k0 += 4) {
+          const int k = min(k0 + g4, K - 1);
+          const float av = k0 + g4 < K ? V[k * KS + vc] : 0.f;
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.f;
-      for (int n = 0; n < R; ++n) {
-        const int i = ridx[n];
-        float av[4], bv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          av[x] = 4 * pi + x < K ? V[(4 * pi + x) * KS + i] : 0.f;
-          bv[x] = G[n * CS + 4 * pc + x];
+          for (int J = 0; J < kChunk / 16; ++J)
+            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, T3[k * CS + 16 * J + i16], acc[J],
+                                                          0, 0, 0);
         }
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int v = 0; v < 4; ++v) {
+          const int n = 16 * I + 4 * g4 + v;
+          if (n < R) {
+            const float f = lam[ridx[n]];
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = fmaf(av[x], bv[y], acc[x][y]);
+            for (int J = 0; J < kChunk / 16; ++J) G[n * CS + 16 * J + i16] = f * acc[J][v];
+          }
+        }
       }
+      __syncthreads();
+      // Y+ = Y' - V_R P: row tile I over the block rows, k over the clipped directions
+      for (int I = wave; I < nt; I += 4) {
+        const int r = min(16 * I + i16, K - 1);
+        f4 acc[kChunk / 16] = {};
+#pragma unroll 4
+        for (int k0 = 0; k0 < R; k0 += 4) {
+          const int k = min(k0 + g4, R - 1);
+          const float av = k0 + g4 < R ? V[r * KS + ridx[k]] : 0.f;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int r = 4 * pi + x;
-        if (r < K) {
+          for (int J = 0; J < kChunk / 16; ++J)
+            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, G[k * CS + 16 * J + i16], acc[J],
+                                                          0, 0, 0);
+        }
 #pragma unroll
-          for (int y = 0; y < 4; ++y) {
-            const int cc = 4 * pc + y;
-            Yb[(long long)r * ncol + c0 + cc] = T3[r * CS + cc] - acc[x][y];
+        for (int v = 0; v < 4; ++v) {
+          const int rr = 16 * I + 4 * g4 + v;
+          if (rr < K) {
+#pragma unroll
+            for (int J = 0; J < kChunk / 16; ++J) {
+              const int cc = 16 * J + i16;
+              Yb[(long long)rr * ncol + c0 + cc] = T3[rr * CS + cc] - acc[J][v];
+            }
           }
         }
       }
