@@ -14,7 +14,8 @@ Prints one JSON line. Besides the throughput it reports
     iterations of the same workload).
 Other workloads (--workload): c4, the uneven batch of 24 images in one batched call; c5, the
 learned initial estimate (training on solver-generated pairs, then a 512 x 512 x 191 scene
-solved from zero and from the network's estimate).
+solved from zero and from the network's estimate); paper10, the paper's experimental shape
+(100 x 100 x 198, 10 x 10 windows, stop rule 1e-5) with the paper's running time as context.
 """
 from __future__ import annotations
 
@@ -69,7 +70,7 @@ def iteration_algorithmic_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> 
     return (44 + 16 * k1 * k2) * N
 
 
-def cpu_baseline(d, k1, k2, iters: int) -> dict:
+def cpu_baseline(d, k1, k2, iters: int, label: str = "256x256x128") -> dict:
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     oracle.set_threads(threads)
@@ -77,8 +78,109 @@ def cpu_baseline(d, k1, k2, iters: int) -> dict:
     oracle.solve(d["v64"], k1, k2, max_iter=iters, **d["radii"])
     dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "iters/s", "cores": oracle.get_threads(), "kind": "oracle",
-            "sample": f"{iters} iteration(s) of the same 256x256x128 workload, FP64, "
+            "sample": f"{iters} iteration(s) of the same {label} workload, FP64, "
                       f"{dt:.1f} s wall"}
+
+
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# The paper's running time of its own method on the 100 x 100 x 198 scene (MATLAB on an
+# Intel Core i9-13900 with an RTX 4090, averaged over its noise cases; Sec. IV, running-time
+# table). Context only: another machine, real data, several noise cases.
+PAPER_SECONDS_100x100x198 = 1.37e4
+
+
+def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float) -> float:
+    """FP32 flops of the dense products of one launch of the large-block pass: the symmetric
+    Gram (K (K + 1) / 2 dot products of length 2 n3) of every block and, for the blocks that
+    needed the eigen-solve, V^T G V and the Newton-Schulz step (four K x K x K products) and
+    the Rayleigh quotients (a K x K x 2 n3 product). The Jacobi rotations and the low-rank
+    clip are not counted, so the figure is a lower bound on the work done."""
+    c = 2 * n3
+    return nblk * K * (K + 1) * c + eig_blocks * (8 * K ** 3 + 2 * K * K * c)
+
+
+def bench_paper_shape(nt, synth, torch, args) -> int:
+    """The paper's experimental shape: a 100 x 100 x 198 scene with 10 x 10 windows (K = 100),
+    throughput over a run from zero and the time to the paper's stop rule (1e-5)."""
+    w = synth.WORKLOADS["paper10"]
+    cfg = w["cfg"]
+    k1, k2 = w["k"]
+    n1, n2, n3 = cfg.n1, cfg.n2, cfg.n3
+    print(f"[bench] generating {n1}x{n2}x{n3} workload, block {k1}x{k2}", file=sys.stderr,
+          flush=True)
+    d = synth.make_hsi(cfg)
+    dev = torch.device("cuda:0")
+    v = torch.from_numpy(d["v"]).to(dev)
+    rad = d["radii"]
+    solver = nt.Solver(n1, n2, n3, k1, k2, device=dev)
+    solver.solve(v, nt.make_params(max_iter=max(min(args.warmup, 20), 1), **rad))
+    torch.cuda.synchronize()
+    steps = args.paper_steps
+    print(f"[bench] timed {steps} iterations", file=sys.stderr, flush=True)
+    params = nt.make_params(max_iter=steps, timing_mask=1 << nt.K_BLOCK, **rad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, _, st = solver.solve(v, params)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    name = nt.KERNEL_NAMES[nt.K_BLOCK]
+    calls = st["kernel_calls"][name]
+    if calls < 1:
+        print(f"bench.py: the timed kernel ({name}) did not run", file=sys.stderr)
+        return 3
+    block_ms = st["kernel_ms"][name] / calls
+    K = k1 * k2
+    flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls)
+    achieved = flops / (block_ms * 1e-3) / 1e12
+    out = {
+        "metric": "P-PDS iters/sec + time to the stop rule 1e-5, 100x100x198 HSI, block 10x10",
+        "value": steps / wall,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(min(args.warmup, 20), 1),
+        "ms_per_step": 1e3 * wall / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"S3TTV P-PDS, synthetic HSI {n1}x{n2}x{n3}, block {k1}x{k2} "
+                               f"(K = {K}), sigma {cfg.sigma}, salt-and-pepper {cfg.p_sp}, "
+                               f"stripes {cfg.p_stripe} (offsets in +-{cfg.stripe_amp})",
+                   "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed},
+        "roofline": {"kernel": "k_big_block", "bound": "alu", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_ms": block_ms, "launches_timed": calls,
+                     "dense_flops_per_launch": flops},
+        "eig_blocks_per_launch": st["eig_blocks"] / calls,
+        "eig_avg_sweeps_per_solved_block": st["eig_avg_steps"],
+        "eig_max_sweeps": st["eig_max_sweeps"],
+        "eig_uncertified_blocks": st["eig_fallback_blocks"],
+    }
+    if not args.skip_tol:
+        tol = w["rel_tol"]
+        print(f"[bench] time to the stop rule {tol} (cap {args.tol_cap})", file=sys.stderr,
+              flush=True)
+        p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=tol, check_every=32, **rad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, st2 = solver.solve(v, p2)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out["time_to_rel_tol"] = {"tol": tol, "seconds": secs, "iters": st2["iters"],
+                                  "converged": st2["converged"],
+                                  "uncertified_blocks": st2["eig_fallback_blocks"]}
+        out["paper_context"] = {"seconds": PAPER_SECONDS_100x100x198,
+                                "what": "the paper's own implementation on its 100x100x198 "
+                                        "scene (CPU + RTX 4090), averaged over noise cases",
+                                "ratio_paper_over_this": PAPER_SECONDS_100x100x198 / secs}
+    if not args.skip_cpu:
+        print("[bench] CPU oracle baseline (2 iterations)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(d, k1, k2, 2, label=f"{n1}x{n2}x{n3}, block 10x10")
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_batched(nt, synth, torch, prec) -> int:
@@ -325,10 +427,13 @@ def main() -> int:
     ap.add_argument("--skip-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tol-cap", type=int, default=20000)
     ap.add_argument("--cpu-iters", type=int, default=3)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5", "cnn"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5", "cnn", "paper10"], default="c2",
                     help="c2: the single 256x256x128 image (default); c4: the uneven batch of 24; "
                          "c5: learned initial estimate vs zero start on 512x512x191; cnn: the "
-                         "network kernels alone")
+                         "network kernels alone; paper10: the paper's 100x100x198 shape with "
+                         "10x10 windows")
+    ap.add_argument("--paper-steps", type=int, default=300,
+                    help="paper10: timed iterations (a run from zero)")
     ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv"], default="s3ttv",
                     help="c2: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
@@ -358,6 +463,8 @@ def main() -> int:
         return bench_warm_start(nt, synth, torch, args)
     if args.workload == "cnn":
         return bench_cnn(nt, synth, torch, args)
+    if args.workload == "paper10":
+        return bench_paper_shape(nt, synth, torch, args)
     w = synth.WORKLOADS["c2"]
     cfg = w["cfg"]
     k1, k2 = w["k"]

@@ -152,6 +152,8 @@ typedef struct {
   int32_t kernel_calls[S3TTV_K_COUNT];
   int32_t tile_a, tile_b; /* anchor tile of the block kernels (does not change the result) */
   int32_t status;         /* this problem's return code */
+  int64_t eig_blocks;     /* K > 16: blocks that needed the eigen-solve, summed over the
+                             iterations; K <= 16: blocks counted in eig_avg_steps */
 } s3ttv_stats;
 
 /* Bytes of device workspace s3ttv_solve needs for this shape (host out-pointer bytes). */
@@ -223,9 +225,11 @@ int32_t s3ttv_op_grad(const s3ttv_shape *shape, const float *u, float *gv, float
 int32_t s3ttv_op_grad_adj(const s3ttv_shape *shape, const float *zv, const float *zh, float *w,
                           void *workspace, size_t workspace_bytes, void *stream);
 
-/* Projection of each of nblk matrices (K x ncols, row-major, K <= 16) onto the unit
+/* Projection of each of nblk matrices (K x ncols, row-major, K <= 100) onto the unit
  * spectral-norm ball, U diag(min(sigma, 1)) V^T — the value of Alg. 1 step 10 for any
- * gamma_Y by eq. ProxConjugate. yin, yout device arrays of nblk*K*ncols floats. */
+ * gamma_Y by eq. ProxConjugate. yin, yout device arrays of nblk*K*ncols floats (they may
+ * not overlap). K <= 16 runs the fused block kernels; larger K the one-workgroup-per-block
+ * kernel, whose Jacobi eigen-solve starts from the identity here. K > 100: EUNSUPPORTED. */
 int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const float *yin,
                                float *yout, void *workspace, size_t workspace_bytes, void *stream);
 

@@ -485,6 +485,7 @@ int32_t finish(const Problem &pr, const DevScalars &hs, float ms, Timer *tm, s3t
         hs.step_blocks ? (float)((double)hs.step_sum / (double)hs.step_blocks) : 0.f;
     stats->eig_max_steps = hs.max_steps;
     stats->eig_fallback_blocks = (int64_t)hs.fallback_blocks;
+    stats->eig_blocks = (int64_t)hs.step_blocks;
     stats->ms = ms;
     stats->tile_a = pl.TA;
     stats->tile_b = pl.TB;
@@ -879,6 +880,60 @@ int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_pa
 
 // ---------------------------------------------------------------- operator entry points
 
+// Workspace of the spectral-clip operator: K <= 16 uses the fused block kernels (blocks of 16
+// rows, 16-column tiles, Gram and basis scratch); larger K the large-block kernel (rows
+// padded to 32-column chunks and a K x K basis per block).
+static size_t clip_workspace_bytes(int64_t nblk, int K, int ncols) {
+  if (K > kRows) {
+    const size_t ncolp = (size_t)(ncols + 31) / 32 * 32;
+    return align_up((size_t)nblk * K * ncolp * 4) + align_up((size_t)nblk * K * K * 4) +
+           align_up(sizeof(DevScalars));
+  }
+  const size_t ncol = (size_t)(ncols + 15) / 16 * 16;
+  return align_up((size_t)nblk * kRows * ncol * 4) + 2 * align_up((size_t)nblk * 256 * 4) +
+         align_up(sizeof(DevScalars));
+}
+
+// The clip for K > 16: the blocks are copied into K x ncolp rows (zero columns appended up to
+// a multiple of 32, which leave the singular values and vectors unchanged) and projected by
+// the large-block kernel with no gradient term, its eigen-solve starting from the identity.
+static int32_t spectral_clip_big(int32_t nblk, int32_t K, int32_t ncols, const float *yin, float *yout,
+                          void *workspace, hipStream_t st) {
+  const int ncolp = (ncols + 31) / 32 * 32;
+  Carver cv{(char *)workspace, 0, false};
+  float *Y = cv.take<float>((size_t)nblk * K * ncolp);
+  float *V = cv.take<float>((size_t)nblk * K * K);
+  DevScalars *sc = cv.take<DevScalars>(1);
+  Plan tmp;
+  memset(&tmp, 0, sizeof(tmp));
+  tmp.sc = sc;
+  CK(launch_init_scalars(tmp, 0.0, 0, st));
+  CK(launch_fill(Y, (long long)nblk * K * ncolp, 0.f, st));
+  CK(hipMemcpy2DAsync(Y, (size_t)ncolp * 4, yin, (size_t)ncols * 4, (size_t)ncols * 4,
+                      (size_t)nblk * K, hipMemcpyDeviceToDevice, st));
+  BigArgs ba;
+  memset(&ba, 0, sizeof(ba));
+  ba.n1 = 1;
+  ba.n2 = nblk;
+  ba.k1 = 1;
+  ba.k2 = K;
+  ba.K = K;
+  ba.ncol = ncolp;
+  ba.nblk = nblk;
+  ba.gradf = nullptr;
+  ba.gY = 0.f;
+  ba.Y = Y;
+  ba.V = V;
+  ba.first = 1;
+  ba.max_sweeps = kBigMaxSweeps;
+  ba.sc = sc;
+  CK(launch_big_block(ba, st));
+  CK(hipMemcpy2DAsync(yout, (size_t)ncols * 4, Y, (size_t)ncolp * 4, (size_t)ncols * 4,
+                      (size_t)nblk * K, hipMemcpyDeviceToDevice, st));
+  CK(hipStreamSynchronize(st));
+  return S3TTV_OK;
+}
+
 int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n, size_t *bytes) {
   if (!bytes) return S3TTV_EINVAL;
   Plan pl;
@@ -895,11 +950,9 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
       return S3TTV_OK;
     }
     case S3TTV_OP_CLIP: {
-      if (!shape || n < 1 || shape->k1 < 1 || shape->k1 > kRows || shape->n3 < 1) return S3TTV_EINVAL;
-      const int ncols = shape->n3;
-      const int ncol = (ncols + 15) / 16 * 16;
-      *bytes = align_up((size_t)n * kRows * ncol * 4) + 2 * align_up((size_t)n * 256 * 4) +
-               align_up(sizeof(DevScalars));
+      if (!shape || n < 1 || shape->k1 < 1 || shape->n3 < 1) return S3TTV_EINVAL;
+      if (shape->k1 > kBigMax || n >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
+      *bytes = clip_workspace_bytes(n, shape->k1, shape->n3);
       return S3TTV_OK;
     }
     case S3TTV_OP_L1:
@@ -948,11 +1001,10 @@ int32_t s3ttv_op_grad_adj(const s3ttv_shape *shape, const float *zv, const float
 int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const float *yin,
                                float *yout, void *workspace, size_t workspace_bytes, void *stream) {
   if (nblk < 1 || K < 1 || ncols < 1 || !yin || !yout || !workspace) return S3TTV_EINVAL;
-  if (K > kRows) return S3TTV_EUNSUPPORTED;
+  if (K > kBigMax) return S3TTV_EUNSUPPORTED;
+  if (workspace_bytes < clip_workspace_bytes(nblk, K, ncols)) return S3TTV_EWORKSPACE;
+  if (K > kRows) return spectral_clip_big(nblk, K, ncols, yin, yout, workspace, (hipStream_t)stream);
   const int ncol = (ncols + 15) / 16 * 16;
-  const size_t need = align_up((size_t)nblk * kRows * ncol * 4) + 2 * align_up((size_t)nblk * 256 * 4) +
-                      align_up(sizeof(DevScalars));
-  if (workspace_bytes < need) return S3TTV_EWORKSPACE;
   Carver cv{(char *)workspace, 0, false};
   float *Y = cv.take<float>((size_t)nblk * kRows * ncol);
   float *G = cv.take<float>((size_t)nblk * 256);

@@ -202,19 +202,23 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     for (int m = 0; m < kGramTiles; ++m) gacc[m] = f4{0.f, 0.f, 0.f, 0.f};
     // staging: thread t moves rows t / 32 + 8 k, column t mod 32 of each chunk; the field
     // offset of each row's pixel is fixed for the block
+    // (no gradient field: the blocks are clipped as they are)
+    const bool hasg = a.gradf != nullptr;
     long long goff[kStage];
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
       const int r = srow + 8 * k;
       const int ra = r / a.k2, rc = r - ra * a.k2;
-      goff[k] = r < K ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol : 0;
+      goff[k] = hasg && r < K
+                    ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol
+                    : 0;
     }
     // the loads of chunk c0 + 32 are issued before the products of chunk c0
     float yv[kStage], gv[kStage];
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
 #pragma unroll
     for (int k = 0; k < kStage; ++k)
-      if (srow + 8 * k < K) gv[k] = a.gradf[goff[k] + scol];
+      if (srow + 8 * k < K) gv[k] = hasg ? a.gradf[goff[k] + scol] : 0.f;
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();
 #pragma unroll
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
         load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
 #pragma unroll
         for (int k = 0; k < kStage; ++k)
-          if (srow + 8 * k < K) gv[k] = a.gradf[goff[k] + c0 + kChunk + scol];
+          if (srow + 8 * k < K) gv[k] = hasg ? a.gradf[goff[k] + c0 + kChunk + scol] : 0.f;
       }
       __syncthreads();
 #pragma unroll

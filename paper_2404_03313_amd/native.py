@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                 ("eig_fallback_blocks", ctypes.c_int64),
                 ("ms", ctypes.c_float),
                 ("kernel_ms", ctypes.c_float * 10), ("kernel_calls", ctypes.c_int32 * 10),
-                ("tile_a", ctypes.c_int32), ("tile_b", ctypes.c_int32), ("status", ctypes.c_int32)]
+                ("tile_a", ctypes.c_int32), ("tile_b", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("eig_blocks", ctypes.c_int64)]
 
 
 class CnnShape(ctypes.Structure):
@@ -230,7 +231,7 @@ def _stats_dict(st: Stats, rc: int) -> dict:
                 l1_s=st.l1_s, l1_t=st.l1_t, fid=st.fid, dv_t=st.dv_t,
                 eig_max_sweeps=st.eig_max_sweeps, eig_avg_sweeps=st.eig_avg_sweeps,
                 eig_avg_steps=st.eig_avg_steps, eig_max_steps=st.eig_max_steps,
-                eig_fallback_blocks=st.eig_fallback_blocks, ms=st.ms,
+                eig_fallback_blocks=st.eig_fallback_blocks, eig_blocks=st.eig_blocks, ms=st.ms,
                 kernel_ms={KERNEL_NAMES[i]: st.kernel_ms[i] for i in range(N_KERNEL_CLASSES)},
                 kernel_calls={KERNEL_NAMES[i]: st.kernel_calls[i]
                               for i in range(N_KERNEL_CLASSES)},

@@ -49,6 +49,12 @@ WORKLOADS: Dict[str, dict] = {
                              p_stripe=0.05, seed=1), k=(3, 3), iters=200),
     "c2": dict(cfg=HSIConfig(256, 256, 128, endmembers=12, cells=64, sigma=0.05, p_sp=0.05,
                              p_stripe=0.1, seed=2), k=(4, 4), iters=500),
+    # the paper's experimental shape (a 100 x 100 x 198 scene, 10 x 10 windows, stop rule
+    # 1e-5) with its Case 8 noise: Gaussian 0.1, salt-and-pepper 0.05, stripes on 5 % of the
+    # columns with offsets ~ U[-0.5, 0.5]
+    "paper10": dict(cfg=HSIConfig(100, 100, 198, endmembers=8, cells=32, sigma=0.1, p_sp=0.05,
+                                  p_stripe=0.05, stripe_amp=0.5, seed=10), k=(10, 10),
+                    rel_tol=1e-5),
     # learned initial estimate: applied to one large scene, compared with the zero start
     "c5": dict(cfg=HSIConfig(512, 512, 191, endmembers=12, cells=128, sigma=0.1, p_sp=0.1,
                              p_stripe=0.1, seed=5), k=(4, 4), rel_tol=1e-4),

@@ -39,6 +39,20 @@ def test_strerror_and_workspace_queries():
     assert b1 < b2
 
 
+@pytest.mark.parametrize("K,ncols,code", [(16, 64, 0), (17, 45, 0), (100, 396, 0),
+                                           (101, 396, nt.EUNSUPPORTED), (0, 8, nt.EINVAL)])
+def test_clip_workspace_query(K, ncols, code):
+    """Spectral clip of K x ncols blocks: K <= 100 is served (K > 16 by the large-block
+    kernel, whose workspace holds K x ncols rows padded to 32 columns and a K x K basis per
+    block)."""
+    sz = ctypes.c_size_t()
+    sh = nt.Shape(1, 1, ncols, K, 1)
+    assert nt.lib().s3ttv_op_workspace_bytes(nt.OP_CLIP, ctypes.byref(sh), 7, ctypes.byref(sz)) == code
+    if code == 0 and K > 16:
+        ncolp = (ncols + 31) // 32 * 32
+        assert sz.value >= 7 * K * ncolp * 4 + 7 * K * K * 4
+
+
 @pytest.mark.parametrize("shape,code", [((1, 8, 4, 1, 1), nt.EINVAL), ((8, 8, 1, 1, 1), nt.EINVAL),
                                         ((8, 8, 4, 9, 1), nt.EINVAL), ((8, 8, 4, 0, 2), nt.EINVAL),
                                         ((12, 12, 4, 11, 10), nt.EUNSUPPORTED)])

@@ -63,3 +63,31 @@ def test_big_blocks_reproducible_and_batched(device):
                                dict(v=v, k1=3, k2=3, params=prm)])
     for x, y in zip(a, res[0][:3]):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("nblk,K,ncols", [(24, 100, 396), (9, 17, 45), (13, 55, 33), (5, 64, 70)])
+def test_spectral_clip_large_blocks(device, nblk, K, ncols):
+    """The projection onto the unit spectral-norm ball (Alg. 1 step 10 by eq. ProxConjugate)
+    of K x ncols blocks up to the paper's 10 x 10 windows over 2 x 198 columns, against FP64
+    singular value decompositions. Spectral norms are spread around 1 and some blocks get
+    a cluster of singular values just above and below 1."""
+    print(f"op_spectral_clip nblk={nblk} K={K} ncols={ncols}", flush=True)
+    rng = np.random.default_rng(7)
+    Y = rng.normal(size=(nblk, K, ncols)) / np.sqrt(ncols)
+    Y *= rng.uniform(0.3, 3.0, size=(nblk, 1, 1))
+    for b in range(0, nblk, 3):   # singular values 0.95 .. 1.05 on a quarter of the spectrum
+        U, sv, Wt = np.linalg.svd(Y[b], full_matrices=False)
+        m = max(1, len(sv) // 4)
+        sv[:m] = np.linspace(1.05, 0.95, m)
+        Y[b] = (U * sv) @ Wt
+    Y32 = Y.astype(np.float32)
+    got = nt.op_spectral_clip(torch.from_numpy(Y32).to(device)).cpu().numpy().astype(np.float64)
+    Y64 = Y32.astype(np.float64)
+    worst = 0.0
+    for b in range(nblk):
+        want = oracle.dual_nuclear(Y64[b], 0.25)
+        err = np.linalg.norm(got[b] - want) / max(np.linalg.norm(want), 1e-30)
+        worst = max(worst, err)
+        assert np.linalg.norm(got[b], 2) <= 1 + 1e-4
+    print(f"  worst relative L2 error {worst:.2e}", flush=True)
+    assert worst < 1e-4
