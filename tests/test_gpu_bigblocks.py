@@ -90,4 +90,4 @@ def test_spectral_clip_large_blocks(device, nblk, K, ncols):
         worst = max(worst, err)
         assert np.linalg.norm(got[b], 2) <= 1 + 1e-4
     print(f"  worst relative L2 error {worst:.2e}", flush=True)
-    assert worst < 1e-4
+    assert worst < 2e-5   # the bound of the K <= 16 clip; measured 3e-6 at K = 100
