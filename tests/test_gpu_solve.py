@@ -160,8 +160,8 @@ def test_solve_errors(device):
     with pytest.raises(nt.S3TTVError) as e:
         nt.solve(v, 2, 2, 1.0, 1.0, 1.0, 5)
     assert e.value.code == nt.ENONFINITE
-    with pytest.raises(nt.S3TTVError) as e:
-        nt.solve(torch.zeros((8, 8, 4), device=device), 5, 4, 1.0, 1.0, 1.0, 5)
+    with pytest.raises(nt.S3TTVError) as e:   # blocks of more than 100 rows
+        nt.solve(torch.zeros((12, 12, 4), device=device), 11, 10, 1.0, 1.0, 1.0, 5)
     assert e.value.code == nt.EUNSUPPORTED
 
 
