@@ -97,6 +97,16 @@ __device__ inline float zfold_val(const int *zpart, int4 off, int col) {
   return (float)acc * kZInv;
 }
 
+// The same for the four columns col .. col + 3 (col a multiple of 4: 16-byte loads).
+__device__ inline float4 zfold_val4(const int *zpart, int4 off, int col) {
+  const int4 a = *reinterpret_cast<const int4 *>(zpart + off.x + col);
+  const int4 b = *reinterpret_cast<const int4 *>(zpart + off.y + col);
+  const int4 c = *reinterpret_cast<const int4 *>(zpart + off.z + col);
+  const int4 d = *reinterpret_cast<const int4 *>(zpart + off.w + col);
+  return make_float4((float)((a.x + b.x) + (c.x + d.x)) * kZInv, (float)((a.y + b.y) + (c.y + d.y)) * kZInv,
+                     (float)((a.z + b.z) + (c.z + d.z)) * kZInv, (float)((a.w + b.w) + (c.w + d.w)) * kZInv);
+}
+
 // Alg. 1 steps 2-4 before the l1 projections:
 //   u+ = P_box(u - g_u (D_s^T (D_v^T Zv + D_h^T Zh) + y3))        (eq. prox_box_constraint)
 //   xs = s - g_s y3,   xt = t - g_t (D_v^T y2 + y3),   y3 = kappa * w.
@@ -112,7 +122,97 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
   const float kappa = (float)a.sc->kappa;
   double du2 = 0, u2 = 0, bad = 0;
   const int n2 = a.n2, n3 = a.n3, ncol = a.ncol, Bp = a.Bp;
-  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < a.N;
+  // S3TTV with the partial-slot table and N3 divisible by 4: a thread takes four consecutive
+  // bands of one pixel, so the partials come in 16-byte loads and column b - 1 of band b is
+  // the previous band's column b (one halo column per quad). Same arithmetic per voxel.
+  const uintptr_t align = reinterpret_cast<uintptr_t>(a.u) | reinterpret_cast<uintptr_t>(a.s) |
+                          reinterpret_cast<uintptr_t>(a.t) | reinterpret_cast<uintptr_t>(a.w) |
+                          reinterpret_cast<uintptr_t>(a.y2) | reinterpret_cast<uintptr_t>(a.un) |
+                          reinterpret_cast<uintptr_t>(a.xs) | reinterpret_cast<uintptr_t>(a.xt);
+  const bool quads = MODE == 0 && a.zslot && (n3 & 3) == 0 && (align & 15) == 0;
+  const long long NQ = quads ? a.N >> 2 : 0;
+  // two quads per trip, all of their loads issued before any arithmetic: the slot tables,
+  // then the partials and the voxel values (a trip's stores would otherwise hold back the next
+  // trip's loads)
+  const long long qstride = (long long)gridDim.x * kNT;
+  for (long long q0 = (long long)blockIdx.x * kNT + threadIdx.x; q0 < NQ; q0 += 2 * qstride) {
+    const int nq = n3 >> 2;
+    long long qd[2] = {q0, q0 + qstride};
+    const bool on1 = qd[1] < NQ;
+    if (!on1) qd[1] = q0;  // loads repeat the first quad; the second is then skipped
+    uint32_t pix[2], pim[2], pjm[2];
+    int b0[2], bm[2];
+    int4 sp[2], si[2], sj[2];
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      pix[h2] = (uint32_t)(qd[h2] / nq);
+      b0[h2] = (int)(qd[h2] - (long long)pix[h2] * nq) * 4;
+      const int i = (int)(pix[h2] / (uint32_t)n2), j = (int)(pix[h2] - (uint32_t)i * n2);
+      bm[h2] = wrap_dn(b0[h2] - 1, n3);
+      pim[h2] = (uint32_t)(wrap_dn(i - 1, a.n1) * n2 + j);
+      pjm[h2] = (uint32_t)(i * n2 + wrap_dn(j - 1, n2));
+      sp[h2] = reinterpret_cast<const int4 *>(a.zslot)[pix[h2]];
+      si[h2] = reinterpret_cast<const int4 *>(a.zslot)[pim[h2]];
+      sj[h2] = reinterpret_cast<const int4 *>(a.zslot)[pjm[h2]];
+    }
+    float4 vi[2], vp[2], hj[2], hp[2], w4[2], u4[2], s4[2], t4[2], ye[2], ym[2];
+    float Q0[2];
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      vi[h2] = zfold_val4(a.zpart, si[h2], b0[h2]);
+      vp[h2] = zfold_val4(a.zpart, sp[h2], b0[h2]);
+      hj[h2] = zfold_val4(a.zpart, sj[h2], Bp + b0[h2]);
+      hp[h2] = zfold_val4(a.zpart, sp[h2], Bp + b0[h2]);
+      Q0[h2] = (zfold_val(a.zpart, si[h2], bm[h2]) - zfold_val(a.zpart, sp[h2], bm[h2])) +
+               (zfold_val(a.zpart, sj[h2], Bp + bm[h2]) - zfold_val(a.zpart, sp[h2], Bp + bm[h2]));
+      const long long e0 = qd[h2] * 4;
+      w4[h2] = *reinterpret_cast<const float4 *>(a.w + e0);
+      u4[h2] = *reinterpret_cast<const float4 *>(a.u + e0);
+      s4[h2] = *reinterpret_cast<const float4 *>(a.s + e0);
+      t4[h2] = *reinterpret_cast<const float4 *>(a.t + e0);
+      ye[h2] = *reinterpret_cast<const float4 *>(a.y2 + e0);
+      ym[h2] = *reinterpret_cast<const float4 *>(a.y2 + (size_t)pim[h2] * n3 + b0[h2]);
+    }
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      if (h2 == 1 && !on1) break;
+      // Q(c) = (D_v^T Zv + D_h^T Zh)(c) for c = b0 - 1, b0 .. b0 + 3
+      const float Q[5] = {Q0[h2], (vi[h2].x - vp[h2].x) + (hj[h2].x - hp[h2].x),
+                          (vi[h2].y - vp[h2].y) + (hj[h2].y - hp[h2].y),
+                          (vi[h2].z - vp[h2].z) + (hj[h2].z - hp[h2].z),
+                          (vi[h2].w - vp[h2].w) + (hj[h2].w - hp[h2].w)};
+      const float wv[4] = {w4[h2].x, w4[h2].y, w4[h2].z, w4[h2].w};
+      const float uv[4] = {u4[h2].x, u4[h2].y, u4[h2].z, u4[h2].w};
+      const float sv[4] = {s4[h2].x, s4[h2].y, s4[h2].z, s4[h2].w};
+      const float tv[4] = {t4[h2].x, t4[h2].y, t4[h2].z, t4[h2].w};
+      const float yev[4] = {ye[h2].x, ye[h2].y, ye[h2].z, ye[h2].w};
+      const float ymv[4] = {ym[h2].x, ym[h2].y, ym[h2].z, ym[h2].w};
+      float unv[4], xsv[4], xtv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float adj = Q[k] - Q[k + 1];  // adjoint of D_s: q(b - 1) - q(b)
+        const float y3 = kappa * wv[k];
+        const float uo = uv[k];
+        const float un = box(uo - a.g_u * (adj + y3), a.lo, a.hi);
+        const float xs = sv[k] - a.g_s * y3;
+        const float xt = tv[k] - a.g_t * ((ymv[k] - yev[k]) + y3);
+        unv[k] = un;
+        xsv[k] = xs;
+        xtv[k] = xt;
+        const double d = (double)un - (double)uo;
+        du2 += d * d;
+        u2 += (double)uo * (double)uo;
+        if (!(isfinite(un) && isfinite(xs) && isfinite(xt))) bad = 1;
+        l1_acc(h[0], xs);
+        l1_acc(h[1], xt);
+      }
+      const long long e0 = qd[h2] * 4;
+      *reinterpret_cast<float4 *>(a.un + e0) = make_float4(unv[0], unv[1], unv[2], unv[3]);
+      *reinterpret_cast<float4 *>(a.xs + e0) = make_float4(xsv[0], xsv[1], xsv[2], xsv[3]);
+      *reinterpret_cast<float4 *>(a.xt + e0) = make_float4(xtv[0], xtv[1], xtv[2], xtv[3]);
+    }
+  }
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < (quads ? 0 : a.N);
        e += (long long)gridDim.x * kNT) {
     const uint32_t pix = (uint32_t)(e / n3);
     const int b = (int)(e - (long long)pix * n3);
