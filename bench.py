@@ -83,10 +83,13 @@ def cpu_baseline(d, k1, k2, iters: int, label: str = "256x256x128") -> dict:
 
 
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# The paper's running time of its own method on the 100 x 100 x 198 scene (MATLAB on an
-# Intel Core i9-13900 with an RTX 4090, averaged over its noise cases; Sec. IV, running-time
-# table). Context only: another machine, real data, several noise cases.
+# The paper's running times of its own method on its three scenes (MATLAB on an Intel Core
+# i9-13900 with an RTX 4090, averaged over its noise cases; Sec. IV, running-time table).
+# Context only: another machine, real data, several noise cases.
 PAPER_SECONDS_100x100x198 = 1.37e4
+PAPER_SCENES = {"100x100x198": ("paper10", PAPER_SECONDS_100x100x198),
+                "120x120x98": ("paper10_120x120x98", 2.05e4),
+                "100x100x128": ("paper10_100x100x128", 1.74e4)}
 
 
 def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float) -> float:
@@ -102,7 +105,8 @@ def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float) -> floa
 def bench_paper_shape(nt, synth, torch, args) -> int:
     """The paper's experimental shape: a 100 x 100 x 198 scene with 10 x 10 windows (K = 100),
     throughput over a run from zero and the time to the paper's stop rule (1e-5)."""
-    w = synth.WORKLOADS["paper10"]
+    wname, paper_seconds = PAPER_SCENES[args.scene]
+    w = synth.WORKLOADS[wname]
     cfg = w["cfg"]
     k1, k2 = w["k"]
     n1, n2, n3 = cfg.n1, cfg.n2, cfg.n3
@@ -133,7 +137,7 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
     flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls)
     achieved = flops / (block_ms * 1e-3) / 1e12
     out = {
-        "metric": "P-PDS iters/sec + time to the stop rule 1e-5, 100x100x198 HSI, block 10x10",
+        "metric": f"P-PDS iters/sec + time to the stop rule 1e-5, {n1}x{n2}x{n3} HSI, block 10x10",
         "value": steps / wall,
         "unit": "iters/s",
         "n_gpus": 1,
@@ -172,10 +176,10 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         out["time_to_rel_tol"] = {"tol": tol, "seconds": secs, "iters": st2["iters"],
                                   "converged": st2["converged"],
                                   "uncertified_blocks": st2["eig_fallback_blocks"]}
-        out["paper_context"] = {"seconds": PAPER_SECONDS_100x100x198,
-                                "what": "the paper's own implementation on its 100x100x198 "
+        out["paper_context"] = {"seconds": paper_seconds,
+                                "what": f"the paper's own implementation on its {n1}x{n2}x{n3} "
                                         "scene (CPU + RTX 4090), averaged over noise cases",
-                                "ratio_paper_over_this": PAPER_SECONDS_100x100x198 / secs}
+                                "ratio_paper_over_this": paper_seconds / secs}
     if not args.skip_cpu:
         print("[bench] CPU oracle baseline (2 iterations)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(d, k1, k2, 2, label=f"{n1}x{n2}x{n3}, block 10x10")
@@ -434,6 +438,8 @@ def main() -> int:
                          "10x10 windows")
     ap.add_argument("--paper-steps", type=int, default=300,
                     help="paper10: timed iterations (a run from zero)")
+    ap.add_argument("--scene", choices=sorted(PAPER_SCENES), default="100x100x198",
+                    help="paper10: the shape of one of the paper's scenes")
     ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv"], default="s3ttv",
                     help="c2: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")

@@ -55,6 +55,13 @@ WORKLOADS: Dict[str, dict] = {
     "paper10": dict(cfg=HSIConfig(100, 100, 198, endmembers=8, cells=32, sigma=0.1, p_sp=0.05,
                                   p_stripe=0.05, stripe_amp=0.5, seed=10), k=(10, 10),
                     rel_tol=1e-5),
+    # the shapes of the paper's two other scenes of its running-time table, same noise
+    "paper10_120x120x98": dict(cfg=HSIConfig(120, 120, 98, endmembers=8, cells=32, sigma=0.1,
+                                             p_sp=0.05, p_stripe=0.05, stripe_amp=0.5, seed=11),
+                               k=(10, 10), rel_tol=1e-5),
+    "paper10_100x100x128": dict(cfg=HSIConfig(100, 100, 128, endmembers=8, cells=32, sigma=0.1,
+                                              p_sp=0.05, p_stripe=0.05, stripe_amp=0.5, seed=12),
+                                k=(10, 10), rel_tol=1e-5),
     # learned initial estimate: applied to one large scene, compared with the zero start
     "c5": dict(cfg=HSIConfig(512, 512, 191, endmembers=12, cells=128, sigma=0.1, p_sp=0.1,
                              p_stripe=0.1, seed=5), k=(4, 4), rel_tol=1e-4),

@@ -54,3 +54,9 @@ def test_bench_context_is_the_printed_running_time():
     spec.loader.exec_module(bench)
     t = _golden()["running_time_s3ttv_seconds"]
     assert bench.PAPER_SECONDS_100x100x198 == t["jasper_ridge"]
+    assert bench.PAPER_SCENES["120x120x98"][1] == t["pavia_university"]
+    assert bench.PAPER_SCENES["100x100x128"][1] == t["beltsville"]
+    for name, (wname, _) in bench.PAPER_SCENES.items():
+        cfg = synth.WORKLOADS[wname]["cfg"]
+        assert f"{cfg.n1}x{cfg.n2}x{cfg.n3}" == name
+        assert list(synth.WORKLOADS[wname]["k"]) == _golden()["experiments"]["block"]
