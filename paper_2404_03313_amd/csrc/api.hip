@@ -66,7 +66,6 @@ int32_t supported_shape(const s3ttv_shape *sh) {
 // Anchor-tile candidates (largest first). The arithmetic of a solve does not depend on the
 // tile (the overlap-add is exact fixed point), only its speed does.
 const int kTileCand[][2] = {{8, 8}, {8, 4}, {4, 8}, {4, 4}, {4, 2}, {2, 4}, {2, 2}, {2, 1}, {1, 1}};
-constexpr int kNumTileCand = sizeof(kTileCand) / sizeof(kTileCand[0]);
 
 size_t apply_lds_bytes(const Plan &pl, int TA, int TB) {
   return (size_t)(TA + pl.k1 - 1) * (TB + pl.k2 - 1) * (pl.ncol + 16) * sizeof(float);

@@ -94,15 +94,24 @@ __device__ inline void mfma_band(const float *A, int as, const float *B, int bs,
   int c[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) c[j] = min(16 * (J0 + j) + i16, nc - 1);
-#pragma unroll 4
-  for (int k0 = 0; k0 < kd; k0 += 4) {
-    const int k = min(k0 + g4, kd - 1);
-    const bool kok = k0 + g4 < kd;
-    const float a0 = TA ? A[k * as + r] : A[r * as + k];
-    const float av = kok ? a0 : 0.f;
+  // k in groups of 16 (four MFMA steps unrolled by hand: the compiler does not partially
+  // unroll loops around MFMA), the tail past kd masked to zero
+  for (int k16 = 0; k16 < kd; k16 += 16) {
+    float av[4], bv[4][NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, B[k * bs + c[j]], acc[j], 0, 0, 0);
+    for (int st = 0; st < 4; ++st) {
+      const int kk = k16 + 4 * st + g4;
+      const int k = min(kk, kd - 1);
+      const float a0 = TA ? A[k * as + r] : A[r * as + k];
+      av[st] = kk < kd ? a0 : 0.f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) bv[st][j] = B[k * bs + c[j]];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][j], acc[j], 0, 0, 0);
   }
 }
 
@@ -531,14 +540,20 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       for (int I = wave; I < nR; I += 4) {
         const int vc = ridx[min(16 * I + i16, R - 1)];
         f4 acc[kChunk / 16] = {};
-#pragma unroll 4
-        for (int k0 = 0; k0 < K; k0 += 4) {
-          const int k = min(k0 + g4, K - 1);
-          const float av = k0 + g4 < K ? V[k * KS + vc] : 0.f;
+        for (int k16 = 0; k16 < K; k16 += 16) {  // four MFMA steps per trip, tail masked
+          float av[4], bv[4][kChunk / 16];
 #pragma unroll
-          for (int J = 0; J < kChunk / 16; ++J)
-            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, T3[k * CS + 16 * J + i16], acc[J],
-                                                          0, 0, 0);
+          for (int st = 0; st < 4; ++st) {
+            const int kk = k16 + 4 * st + g4, k = min(kk, K - 1);
+            av[st] = kk < K ? V[k * KS + vc] : 0.f;
+#pragma unroll
+            for (int J = 0; J < kChunk / 16; ++J) bv[st][J] = T3[k * CS + 16 * J + i16];
+          }
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int J = 0; J < kChunk / 16; ++J)
+              acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][J], acc[J], 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -555,14 +570,20 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       for (int I = wave; I < nt; I += 4) {
         const int r = min(16 * I + i16, K - 1);
         f4 acc[kChunk / 16] = {};
-#pragma unroll 4
-        for (int k0 = 0; k0 < R; k0 += 4) {
-          const int k = min(k0 + g4, R - 1);
-          const float av = k0 + g4 < R ? V[r * KS + ridx[k]] : 0.f;
+        for (int k16 = 0; k16 < R; k16 += 16) {  // four MFMA steps per trip, tail masked
+          float av[4], bv[4][kChunk / 16];
 #pragma unroll
-          for (int J = 0; J < kChunk / 16; ++J)
-            acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, G[k * CS + 16 * J + i16], acc[J],
-                                                          0, 0, 0);
+          for (int st = 0; st < 4; ++st) {
+            const int kk = k16 + 4 * st + g4, k = min(kk, R - 1);
+            av[st] = kk < R ? V[r * KS + ridx[k]] : 0.f;
+#pragma unroll
+            for (int J = 0; J < kChunk / 16; ++J) bv[st][J] = G[k * CS + 16 * J + i16];
+          }
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int J = 0; J < kChunk / 16; ++J)
+              acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][J], acc[J], 0, 0, 0);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
