@@ -31,19 +31,24 @@ namespace s3ttv {
 
 namespace {
 
-constexpr int kNT = 256;
+constexpr int kNT = 256;   // overlap-add and fill kernels
+constexpr int kBT = 512;   // the block kernel: eight wavefronts per block
+constexpr int kNW = kBT / 64;
 constexpr int kChunk = 32;
 // Row stride of a staged Y' chunk in the Gram: 34 makes the MFMA operand reads of a half-wave
 // (rows i = 0..15, columns g = 0..1) hit 32 distinct banks.
 constexpr int kGS = kChunk + 2;
-// 16 x 16 Gram tiles per wave: ceil(28 / 4) for K <= 112 (7 x 7 tiles, upper triangle).
-constexpr int kGramTiles = 7;
+// 16 x 16 Gram tiles per wave: ceil(28 / kNW) for K <= 112 (7 x 7 tiles, upper triangle).
+constexpr int kGramTiles = (28 + kNW - 1) / kNW;
+// Row tiles (of 16 rows, at most 7) per wave in the Rayleigh-quotient pass.
+constexpr int kRqTiles = (7 + kNW - 1) / kNW;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Chunk elements a thread stages: ceil(kBigMax * kChunk / kNT).
-constexpr int kStage = (kBigMax * kChunk + kNT - 1) / kNT;
-static_assert(kChunk == 32 && kNT == 256, "chunk staging maps thread t to rows t/32 + 8k");
+// Chunk staging: thread t moves rows t / 32 + kRowStep k, column t mod 32, kStage of them.
+constexpr int kRowStep = kBT / kChunk;
+constexpr int kStage = (kBigMax * kChunk + kBT - 1) / kBT;
+static_assert(kChunk == 32 && kBT % kChunk == 0, "chunk staging");
 // Rows whose diagonal exceeds this take part in the off-diagonal test of the certificate.
 constexpr float kNearOne = 0.999f;
 // Sweeps that rotate only pairs touching a row that failed the certificate; later sweeps
@@ -55,7 +60,8 @@ constexpr int kBatch = 13;
 // Rotation records of a step (K / 2 <= 50 used; reads past the active ones are clamped here
 // and their values ignored).
 constexpr int kRotSlots = 64;
-static_assert(kBigMax <= 128 && kNT == 256, "rotation pass mapping");
+static_assert(kBigMax <= 128 && kBT % 128 == 0 && kBatch * (kNW / 2) >= kBigMax / 2,
+              "rotation pass mapping: one batch covers a wave's pairs");
 
 // Value of x in lane u of the wave (u a compile-time constant).
 __device__ inline float lane_value(float x, int u) {
@@ -116,14 +122,14 @@ __device__ inline void mfma_band(const float *A, int as, const float *B, int bs,
 }
 
 // C = op(A) B for K x K operands (row strides as, bs): bands of four tiles (row tile I,
-// column tiles 4 h .. 4 h + 3) dealt round-robin to the four waves; out(r, c, value) is
+// column tiles 4 h .. 4 h + 3) dealt round-robin to the waves; out(r, c, value) is
 // applied to every entry in range.
 template <bool TA, typename Out>
 __device__ inline void mfma_kk(const float *A, int as, const float *B, int bs, int K, int wave,
                                int i16, int g4, Out out) {
   const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
 #pragma unroll 1
-  for (int t = wave; t < nt * nh; t += 4) {
+  for (int t = wave; t < nt * nh; t += kNW) {
     const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
     f4 acc[4];
     mfma_band<TA, 4>(A, as, B, bs, K, K, K, I, J0, i16, g4, acc);
@@ -146,25 +152,25 @@ struct __align__(16) Rot {
 };
 
 // The K x 32 chunk of Y at column c0 (row stride ncol) into registers: thread t holds rows
-// srow + 8 k, column scol. Loading the next chunk before working on the current one hides
+// srow + kRowStep k, column scol. Loading the next chunk before working on the current one hides
 // the memory latency.
 __device__ inline void load_chunk(const float *Y, int ncol, int c0, int K, int srow, int scol,
                                   float y[kStage]) {
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
-    if (srow + 8 * k < K) y[k] = Y[(long long)(srow + 8 * k) * ncol + c0 + scol];
+    if (srow + kRowStep * k < K) y[k] = Y[(long long)(srow + kRowStep * k) * ncol + c0 + scol];
 }
 
 __device__ inline void store_chunk(const float y[kStage], int K, int srow, int scol, float *T,
                                    int ts) {
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
-    if (srow + 8 * k < K) T[(srow + 8 * k) * ts + scol] = y[k];
+    if (srow + kRowStep * k < K) T[(srow + kRowStep * k) * ts + scol] = y[k];
 }
 
 }  // namespace
 
-__global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
+__global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   extern __shared__ float lds[];
   const int K = a.K, KS = a.K + 1;
   const int GS = KS > kGS ? KS : kGS;
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   __shared__ float lam[112];
   __shared__ bool hot[112];
   __shared__ int nact;
-  __shared__ float red[kNT / 64];
+  __shared__ float red[kNW];
   __shared__ int flag;
   if (a.sc->done) return;
   const int tid = threadIdx.x;
@@ -187,36 +193,36 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
 
   // ---- Gram over column chunks on v_mfma_f32_16x16x4_f32; Y' is written back. The K x K
   // Gram is cut into 16 x 16 tiles; the tiles on and above the diagonal are dealt round-robin
-  // to the four waves. In a 16x16x4 step, lane 16 g + i supplies row i, column g of the
+  // to the waves. In a 16x16x4 step, lane 16 g + i supplies row i, column g of the
   // A operand and row g, column i of the B operand, so with both taken from the staged chunk
   // (rows 16 I + i and 16 J + i, column 4 s + g) a tile accumulates Y'_I Y'_J^T.
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int srow = tid >> 5, scol = tid & 31;  // chunk staging: rows srow + 8 k, column scol
+  const int srow = tid >> 5, scol = tid & 31;  // chunk staging: rows srow + kRowStep k
   {
     const int nt = (K + 15) >> 4, ntiles = nt * (nt + 1) / 2;
     int tI[kGramTiles], tJ[kGramTiles];
 #pragma unroll
     for (int m = 0; m < kGramTiles; ++m) {
-      int rem = wave + 4 * m, I = 0;
+      int rem = wave + kNW * m, I = 0;
       while (I < nt && rem >= nt - I) {
         rem -= nt - I;
         ++I;
       }
       tI[m] = I;
-      tJ[m] = I + rem;  // valid only if wave + 4 m < ntiles
+      tJ[m] = I + rem;  // valid only if wave + kNW m < ntiles
     }
     f4 gacc[kGramTiles];
 #pragma unroll
     for (int m = 0; m < kGramTiles; ++m) gacc[m] = f4{0.f, 0.f, 0.f, 0.f};
-    // staging: thread t moves rows t / 32 + 8 k, column t mod 32 of each chunk; the field
+    // staging: thread t moves rows t / 32 + kRowStep k, column t mod 32 of each chunk; the field
     // offset of each row's pixel is fixed for the block
     // (no gradient field: the blocks are clipped as they are)
     const bool hasg = a.gradf != nullptr;
     long long goff[kStage];
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
-      const int r = srow + 8 * k;
+      const int r = srow + kRowStep * k;
       const int ra = r / a.k2, rc = r - ra * a.k2;
       goff[k] = hasg && r < K
                     ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol
@@ -227,26 +233,26 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
 #pragma unroll
     for (int k = 0; k < kStage; ++k)
-      if (srow + 8 * k < K) gv[k] = hasg ? a.gradf[goff[k] + scol] : 0.f;
+      if (srow + kRowStep * k < K) gv[k] = hasg ? a.gradf[goff[k] + scol] : 0.f;
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kStage; ++k)
-        if (srow + 8 * k < K) {
+        if (srow + kRowStep * k < K) {
           const float y = yv[k] + a.gY * gv[k];
-          Yb[(long long)(srow + 8 * k) * ncol + c0 + scol] = y;
-          T3[(srow + 8 * k) * kGS + scol] = y;
+          Yb[(long long)(srow + kRowStep * k) * ncol + c0 + scol] = y;
+          T3[(srow + kRowStep * k) * kGS + scol] = y;
         }
       if (c0 + kChunk < ncol) {
         load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
 #pragma unroll
         for (int k = 0; k < kStage; ++k)
-          if (srow + 8 * k < K) gv[k] = hasg ? a.gradf[goff[k] + c0 + kChunk + scol] : 0.f;
+          if (srow + kRowStep * k < K) gv[k] = hasg ? a.gradf[goff[k] + c0 + kChunk + scol] : 0.f;
       }
       __syncthreads();
 #pragma unroll
       for (int m = 0; m < kGramTiles; ++m) {
-        if (wave + 4 * m < ntiles) {
+        if (wave + kNW * m < ntiles) {
           const int ra = 16 * tI[m] + i16, rb = 16 * tJ[m] + i16;
           const float *pa = T3 + ra * kGS + g4, *pb = T3 + rb * kGS + g4;
 #pragma unroll
@@ -260,7 +266,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     // result layout: lane i + 16 g, register v holds tile entry (4 g + v, i)
 #pragma unroll
     for (int m = 0; m < kGramTiles; ++m) {
-      if (wave + 4 * m < ntiles) {
+      if (wave + kNW * m < ntiles) {
         const int c = 16 * tJ[m] + i16;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -276,7 +282,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   if (tid == 0) flag = 0;
   __syncthreads();
   // ---- finiteness and the Gershgorin bound: max_i sum_j |G_ij| <= 1 => nothing to clip
-  for (int r = tid; r < K; r += kNT) {
+  for (int r = tid; r < K; r += kBT) {
     float s = 0.f;
     for (int c = 0; c < K; ++c) s += fabsf(G[r * KS + c]);
     if (!(s <= 1.f)) atomicOr(&flag, isfinite(s) ? 1 : 2);
@@ -290,7 +296,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
 
   // ---- basis: identity on the first use, else the stored one (orthonormal to rounding)
   float *Vg = a.V + blk * (long long)K * K;
-  for (int e = tid; e < K * K; e += kNT) {
+  for (int e = tid; e < K * K; e += kBT) {
     const int r = e / K, c = e - r * K;
     V[r * KS + c] = a.first ? (r == c ? 1.f : 0.f) : Vg[e];
   }
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
                 [&](int r, int c, float x) { G[r * KS + c] = x; });
   __syncthreads();
   // symmetrise exactly
-  for (int e = tid; e < K * K; e += kNT) {
+  for (int e = tid; e < K * K; e += kBT) {
     const int r = e / K, c = e - r * K;
     if (r < c) {
       const float m = 0.5f * (G[r * KS + c] + G[c * KS + r]);
@@ -318,14 +324,14 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   const int H = m / 2;         // pairs per step
   // row / column passes: ceil(K / 64) waves per group of pairs, each wave covering a run of
   // cpw consecutive indices vi; ngV groups
-  const int wpg = (K + 63) >> 6, ngV = (kNT / 64) / wpg, cpw = (K + wpg - 1) / wpg;
+  const int wpg = (K + 63) >> 6, ngV = kNW / wpg, cpw = (K + wpg - 1) / wpg;
   const int vkg = wave / wpg, vi = (wave - vkg * wpg) * cpw + lane, viK = vi * KS;
   const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
   int sweeps = 0;
   for (; sweeps < a.max_sweeps; ++sweeps) {
     // certificate (see the header): one thread per row
     float fro = 0.f;
-    for (int e = tid; e < K * K; e += kNT) {
+    for (int e = tid; e < K * K; e += kBT) {
       const int r = e / K, c = e - r * K;
       fro = fmaf(G[r * KS + c], G[r * KS + c], fro);
     }
@@ -333,7 +339,10 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
     if ((tid & 63) == 0) red[tid >> 6] = fro;
     if (tid == 0) flag = 0;
     __syncthreads();
-    const float tol = 1e-6f * sqrtf((red[0] + red[1]) + (red[2] + red[3]));
+    float fsum = 0.f;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
+    const float tol = 1e-6f * sqrtf(fsum);
     if (tid < K) {
       const float dr = G[tid * KS + tid];
       float sum = 0.f, mx = 0.f;
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   mfma_kk<false>(V, KS, T3, KS, K, wave, i16, g4,
                  [&](int r, int c, float x) { G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x; });
   __syncthreads();
-  for (int e = tid; e < K * K; e += kNT) {
+  for (int e = tid; e < K * K; e += kBT) {
     const int r = e / K, c = e - r * K;
     V[r * KS + c] = G[r * KS + c];
     Vg[e] = G[r * KS + c];
@@ -472,7 +481,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
   // so every lambda_i is summed by one wave in a fixed order
   {
     const int nt = (K + 15) >> 4;
-    float lacc[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    float lacc[kRqTiles][4] = {};
     float yv[kStage];
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
@@ -481,8 +490,8 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int I = wave + 4 * m;
+      for (int m = 0; m < kRqTiles; ++m) {
+        const int I = wave + kNW * m;
         if (I < nt) {
           f4 acc[kChunk / 16];
           mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
@@ -503,8 +512,8 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       }
     }
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int I = wave + 4 * m;
+    for (int m = 0; m < kRqTiles; ++m) {
+      const int I = wave + kNW * m;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = 16 * I + 4 * g4 + v;
@@ -537,7 +546,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
       // P: row tile I over the clipped directions n (lane supplies V[k][ridx[n]]), k over K
-      for (int I = wave; I < nR; I += 4) {
+      for (int I = wave; I < nR; I += kNW) {
         const int vc = ridx[min(16 * I + i16, R - 1)];
         f4 acc[kChunk / 16] = {};
         for (int k16 = 0; k16 < K; k16 += 16) {  // four MFMA steps per trip, tail masked
@@ -567,7 +576,7 @@ __global__ __launch_bounds__(kNT) void k_big_block(BigArgs a) {
       }
       __syncthreads();
       // Y+ = Y' - V_R P: row tile I over the block rows, k over the clipped directions
-      for (int I = wave; I < nt; I += 4) {
+      for (int I = wave; I < nt; I += kNW) {
         const int r = min(16 * I + i16, K - 1);
         f4 acc[kChunk / 16] = {};
         for (int k16 = 0; k16 < R; k16 += 16) {  // four MFMA steps per trip, tail masked
@@ -644,7 +653,7 @@ hipError_t launch_big_block(const BigArgs &a, hipStream_t st) {
     if (e != hipSuccess) return e;
     configured = true;
   }
-  hipLaunchKernelGGL(k_big_block, dim3((unsigned)a.nblk), dim3(kNT), big_lds_bytes(a.K), st, a);
+  hipLaunchKernelGGL(k_big_block, dim3((unsigned)a.nblk), dim3(kBT), big_lds_bytes(a.K), st, a);
   return hipGetLastError();
 }
 
