@@ -62,6 +62,7 @@ constexpr int kBatch = 13;
 constexpr int kRotSlots = 64;
 static_assert(kBigMax <= 128 && kBT % 128 == 0 && kBatch * (kNW / 2) >= kBigMax / 2,
               "rotation pass mapping: one batch covers a wave's pairs");
+static_assert(4 * kBigMax <= kBT, "certificate: four threads per row");
 
 // Value of x in lane u of the wave (u a compile-time constant).
 __device__ inline float lane_value(float x, int u) {
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   for (; sweeps < a.max_sweeps; ++sweeps) {
     // certificate (see the header): one thread per row
     float fro = 0.f;
+#pragma unroll 4
     for (int e = tid; e < K * K; e += kBT) {
       const int r = e / K, c = e - r * K;
       fro = fmaf(G[r * KS + c], G[r * KS + c], fro);
@@ -343,18 +345,25 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
 #pragma unroll
     for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
     const float tol = 1e-6f * sqrtf(fsum);
-    if (tid < K) {
-      const float dr = G[tid * KS + tid];
+    if (tid < 4 * K) {  // four consecutive lanes per row, columns interleaved
+      const int r = tid >> 2, part = tid & 3;
+      const float dr = G[r * KS + r];
       float sum = 0.f, mx = 0.f;
-      for (int c = 0; c < K; ++c) {
-        if (c == tid) continue;
-        const float x = fabsf(G[tid * KS + c]);
+#pragma unroll 5
+      for (int c = part; c < K; c += 4) {
+        const float x = c == r ? 0.f : fabsf(G[r * KS + c]);
         sum += x;
         if (dr > kNearOne || G[c * KS + c] > kNearOne) mx = fmaxf(mx, x);
       }
-      const bool fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
-      if (fail) atomicOr(&flag, 1);
-      hot[tid] = fail || sweeps >= kRestricted;
+      sum += __shfl_xor(sum, 1);  // fixed order within the group of four
+      sum += __shfl_xor(sum, 2);
+      mx = fmaxf(mx, __shfl_xor(mx, 1));
+      mx = fmaxf(mx, __shfl_xor(mx, 2));
+      if (part == 0) {
+        const bool fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
+        if (fail) atomicOr(&flag, 1);
+        hot[r] = fail || sweeps >= kRestricted;
+      }
     }
     __syncthreads();
     const int notyet = flag;
