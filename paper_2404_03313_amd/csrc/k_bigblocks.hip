@@ -54,8 +54,8 @@ constexpr float kNearOne = 0.999f;
 // Sweeps that rotate only pairs touching a row that failed the certificate; later sweeps
 // rotate every pair above the skip threshold.
 constexpr int kRestricted = 4;
-// Pairs a wave rotates per batch of a rotation pass (a wave has at most
-// ceil((kBigMax / 2) / 2) = 25 pairs, so two batches).
+// Pairs a wave rotates per batch of a rotation pass: a group of pairs has at most
+// ceil((kBigMax / 2) / (kNW / 2)) = 13 of them, so one batch (the pass loops over batches).
 constexpr int kBatch = 13;
 // Rotation records of a step (K / 2 <= 50 used; reads past the active ones are clamped here
 // and their values ignored).
