@@ -70,12 +70,13 @@ def iteration_algorithmic_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> 
     return (44 + 16 * k1 * k2) * N
 
 
-def cpu_baseline(d, k1, k2, iters: int, label: str = "256x256x128") -> dict:
+def cpu_baseline(d, k1, k2, iters: int, label: str = "256x256x128",
+                 regularizer: str = "s3ttv") -> dict:
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
     oracle.set_threads(threads)
     t0 = time.perf_counter()
-    oracle.solve(d["v64"], k1, k2, max_iter=iters, **d["radii"])
+    oracle.solve(d["v64"], k1, k2, max_iter=iters, regularizer=regularizer, **d["radii"])
     dt = time.perf_counter() - t0
     return {"value": iters / dt, "unit": "iters/s", "cores": oracle.get_threads(), "kind": "oracle",
             "sample": f"{iters} iteration(s) of the same {label} workload, FP64, "
@@ -90,6 +91,13 @@ PAPER_SECONDS_100x100x198 = 1.37e4
 PAPER_SCENES = {"100x100x198": ("paper10", PAPER_SECONDS_100x100x198),
                 "120x120x98": ("paper10_120x120x98", 2.05e4),
                 "100x100x128": ("paper10_100x100x128", 1.74e4)}
+# The same table's rows for the compared regularisers this library runs on the P-PDS
+# skeleton (HSSTV in its l1 form, the paper's HSSTV1; STV with 10 x 10 blocks).
+PAPER_SECONDS_COMPARED = {
+    "sstv": {"100x100x198": 1.92e2, "120x120x98": 2.39e2, "100x100x128": 2.47e2},
+    "hsstv": {"100x100x198": 2.03e2, "120x120x98": 2.05e2, "100x100x128": 1.81e2},
+    "stv": {"100x100x198": 1.82e4, "120x120x98": 1.83e4, "100x100x128": 9.66e3},
+}
 
 
 def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float) -> float:
@@ -106,6 +114,10 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
     """The paper's experimental shape: a 100 x 100 x 198 scene with 10 x 10 windows (K = 100),
     throughput over a run from zero and the time to the paper's stop rule (1e-5)."""
     wname, paper_seconds = PAPER_SCENES[args.scene]
+    reg = args.regularizer
+    if reg != "s3ttv":
+        paper_seconds = PAPER_SECONDS_COMPARED[reg][args.scene]
+    l1_reg = reg in ("sstv", "hsstv")
     w = synth.WORKLOADS[wname]
     cfg = w["cfg"]
     k1, k2 = w["k"]
@@ -117,25 +129,40 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
     v = torch.from_numpy(d["v"]).to(dev)
     rad = d["radii"]
     solver = nt.Solver(n1, n2, n3, k1, k2, device=dev)
-    solver.solve(v, nt.make_params(max_iter=max(min(args.warmup, 20), 1), **rad))
+    solver.solve(v, nt.make_params(max_iter=max(min(args.warmup, 20), 1), regularizer=reg, **rad))
     torch.cuda.synchronize()
     steps = args.paper_steps
-    print(f"[bench] timed {steps} iterations", file=sys.stderr, flush=True)
-    params = nt.make_params(max_iter=steps, timing_mask=1 << nt.K_BLOCK, **rad)
+    print(f"[bench] timed {steps} iterations ({reg})", file=sys.stderr, flush=True)
+    cls = nt.K_DUAL if l1_reg else nt.K_BLOCK
+    params = nt.make_params(max_iter=steps, timing_mask=1 << cls, regularizer=reg, **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, _, _, st = solver.solve(v, params)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    name = nt.KERNEL_NAMES[nt.K_BLOCK]
+    name = nt.KERNEL_NAMES[cls]
     calls = st["kernel_calls"][name]
     if calls < 1:
         print(f"bench.py: the timed kernel ({name}) did not run", file=sys.stderr)
         return 3
     block_ms = st["kernel_ms"][name] / calls
     K = k1 * k2
-    flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls)
-    achieved = flops / (block_ms * 1e-3) / 1e12
+    if l1_reg:
+        # no block pass: the dual sweep is the largest pass (as in the default workload)
+        dbytes = n1 * n2 * n3 * (52 + 16 * (2 if reg == "hsstv" else 1))
+        achieved = dbytes / (block_ms * 1e-3) / 1e9
+        roofline = {"kernel": "k_dual_grad", "bound": "hbm", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": None, "avg_launch_ms": block_ms, "launches_timed": calls,
+                    "algorithmic_bytes_per_launch": dbytes}
+    else:
+        flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls)
+        achieved = flops / (block_ms * 1e-3) / 1e12
+        roofline = {"kernel": "k_big_block", "bound": "alu", "achieved": achieved,
+                    "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "avg_launch_ms": block_ms, "launches_timed": calls,
+                    "dense_flops_per_launch": flops}
     out = {
         "metric": f"P-PDS iters/sec + time to the stop rule 1e-5, {n1}x{n2}x{n3} HSI, block 10x10",
         "value": steps / wall,
@@ -149,15 +176,12 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"S3TTV P-PDS, synthetic HSI {n1}x{n2}x{n3}, block {k1}x{k2} "
-                               f"(K = {K}), sigma {cfg.sigma}, salt-and-pepper {cfg.p_sp}, "
-                               f"stripes {cfg.p_stripe} (offsets in +-{cfg.stripe_amp})",
-                   "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed},
-        "roofline": {"kernel": "k_big_block", "bound": "alu", "achieved": achieved,
-                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "avg_launch_ms": block_ms, "launches_timed": calls,
-                     "dense_flops_per_launch": flops},
+        "config": {"workload": f"{reg.upper()} P-PDS, synthetic HSI {n1}x{n2}x{n3}, block "
+                               f"{k1}x{k2} (K = {K}), sigma {cfg.sigma}, salt-and-pepper "
+                               f"{cfg.p_sp}, stripes {cfg.p_stripe} (offsets in +-{cfg.stripe_amp})",
+                   "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed,
+                   "regularizer": reg},
+        "roofline": roofline,
         "eig_blocks_per_launch": st["eig_blocks"] / calls,
         "eig_avg_sweeps_per_solved_block": st["eig_avg_steps"],
         "eig_max_sweeps": st["eig_max_sweeps"],
@@ -167,7 +191,8 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         tol = w["rel_tol"]
         print(f"[bench] time to the stop rule {tol} (cap {args.tol_cap})", file=sys.stderr,
               flush=True)
-        p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=tol, check_every=32, **rad)
+        p2 = nt.make_params(max_iter=args.tol_cap, rel_tol=tol, check_every=32, regularizer=reg,
+                            **rad)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         _, _, _, st2 = solver.solve(v, p2)
@@ -177,12 +202,14 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
                                   "converged": st2["converged"],
                                   "uncertified_blocks": st2["eig_fallback_blocks"]}
         out["paper_context"] = {"seconds": paper_seconds,
-                                "what": f"the paper's own implementation on its {n1}x{n2}x{n3} "
-                                        "scene (CPU + RTX 4090), averaged over noise cases",
+                                "what": f"the paper's implementation of {reg.upper()} on its "
+                                        f"{n1}x{n2}x{n3} scene (CPU + RTX 4090), averaged over "
+                                        "noise cases",
                                 "ratio_paper_over_this": paper_seconds / secs}
     if not args.skip_cpu:
         print("[bench] CPU oracle baseline (2 iterations)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(d, k1, k2, 2, label=f"{n1}x{n2}x{n3}, block 10x10")
+        out["cpu_baseline"] = cpu_baseline(d, k1, k2, 2, label=f"{n1}x{n2}x{n3}, block 10x10",
+                                           regularizer=reg)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -441,7 +468,7 @@ def main() -> int:
     ap.add_argument("--scene", choices=sorted(PAPER_SCENES), default="100x100x198",
                     help="paper10: the shape of one of the paper's scenes")
     ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv"], default="s3ttv",
-                    help="c2: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
+                    help="c2, paper10: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
     ap.add_argument("--train-steps", type=int, default=2500, help="c5: Adam steps (batch 8)")
     ap.add_argument("--ref-iters", type=int, default=10000,

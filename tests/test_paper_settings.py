@@ -56,6 +56,12 @@ def test_bench_context_is_the_printed_running_time():
     assert bench.PAPER_SECONDS_100x100x198 == t["jasper_ridge"]
     assert bench.PAPER_SCENES["120x120x98"][1] == t["pavia_university"]
     assert bench.PAPER_SCENES["100x100x128"][1] == t["beltsville"]
+    c = _golden()["running_time_compared_seconds"]
+    scene = {"100x100x198": "jasper_ridge", "120x120x98": "pavia_university",
+             "100x100x128": "beltsville"}
+    for reg, key in (("sstv", "sstv"), ("hsstv", "hsstv1"), ("stv", "stv")):
+        for shape, name in scene.items():
+            assert bench.PAPER_SECONDS_COMPARED[reg][shape] == c[key][name], (reg, shape)
     for name, (wname, _) in bench.PAPER_SCENES.items():
         cfg = synth.WORKLOADS[wname]["cfg"]
         assert f"{cfg.n1}x{cfg.n2}x{cfg.n3}" == name
