@@ -71,9 +71,12 @@ typedef struct {
  *  rel_tol: 0 runs exactly max_iter iterations; > 0 stops after the first iteration
  *    k >= 2 with ||u^(k) - u^(k-1)|| / ||u^(k-1)|| < rel_tol (eq. StopCri_simulated).
  *  check_every: iterations between host checks of the stop flag (<= 0 means 16). The
- *    iterate returned is always the one at which the rule fired.
+ *    iterate returned is always the one at which the rule fired. s3ttv_solve replays a
+ *    captured graph of that many iterations (rounded up to even, at most 256) on a stream of
+ *    its own, joined to `stream` before and after; the result does not depend on it.
  *  timing_mask: bit c set => time every launch of kernel class c with HIP events and
- *    report the totals in s3ttv_stats (classes: see S3TTV_K_*). 0 for no timing.
+ *    report the totals in s3ttv_stats (classes: see S3TTV_K_*). 0 for no timing; a solve
+ *    with timing launches every kernel directly on `stream`.
  *  eig_max_steps: from the second iteration on, each block's 16 x 16 eigenproblem is solved
  *    by at most this many simultaneous rotation steps on MFMA, warm started from the previous
  *    iteration's eigenbasis; blocks not certified by then are finished by a per-lane cyclic

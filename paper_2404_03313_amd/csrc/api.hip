@@ -668,6 +668,25 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
                           workspace_bytes, stream, stats);
 }
 
+// A non-blocking stream of the calling thread on which a solve captures and replays its
+// iteration graphs (a capture needs a stream of its own; the caller's stream may be the null
+// stream). Joined to the caller's stream with events before and after.
+struct SolveStream {
+  hipStream_t s = nullptr;
+  hipEvent_t in = nullptr, out = nullptr;
+  hipError_t status;
+  SolveStream() {
+    status = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (status == hipSuccess) status = hipEventCreateWithFlags(&in, hipEventDisableTiming);
+    if (status == hipSuccess) status = hipEventCreateWithFlags(&out, hipEventDisableTiming);
+  }
+};
+
+SolveStream &solve_stream() {
+  thread_local SolveStream s;
+  return s;
+}
+
 int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
                          const float *u0, const float *s0, const float *t0, float *u, float *s,
                          float *t, void *workspace, size_t workspace_bytes, void *stream,
@@ -691,20 +710,80 @@ int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, c
     if (chk != S3TTV_OK) return chk;
   }
   const int check = params->check_every > 0 ? params->check_every : 16;
+  // Iteration 1 directly; then, unless kernel timing is requested, one captured graph of
+  // `span` iterations (even, so the u / t buffer parity of its launches repeats) replayed
+  // until the budget is used or the stop rule has fired on the device (a finished solve's
+  // later launches exit at once), and the remainder directly. The host reads the stop flag
+  // between spans.
+  const int max_iter = params->max_iter;
+  const int span = check < 2 ? 2 : (check > 256 ? 256 : (check + 1) & ~1);
+  bool use_graph = params->timing_mask == 0 && max_iter > 1 + span;
+  const hipStream_t user = st;
+  if (use_graph) {
+    SolveStream &ss = solve_stream();
+    if (ss.status == hipSuccess) {
+      CK(hipEventRecord(ss.in, user));
+      CK(hipStreamWaitEvent(ss.s, ss.in, 0));
+      st = ss.s;
+    } else {
+      use_graph = false;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
   CK(hipEventRecord(e0, st));
-  for (int it = 0; it < params->max_iter; ++it) {
-    const int32_t r = enqueue_iteration(pr, it, tm, st);
-    if (r != S3TTV_OK) return r;
-    if (params->rel_tol > 0 && (it + 1) % check == 0 && it + 1 < params->max_iter) {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t r = S3TTV_OK;
+  int it = 0;
+  while (r == S3TTV_OK && it < max_iter) {
+    if (it >= 1 && use_graph && !exec && it + span <= max_iter) {
+      // capture once; if the stream cannot be captured, keep launching directly
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+      } else {
+        for (int j = it; j < it + span && r == S3TTV_OK; ++j) r = enqueue_iteration(pr, j, tm, st);
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (r != S3TTV_OK) break;
+        if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          graph = nullptr;
+          exec = nullptr;
+          (void)hipGetLastError();
+        }
+      }
+    }
+    int next;
+    if (exec && it + span <= max_iter) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) r = S3TTV_EHIP;
+      next = it + span;
+    } else {
+      // direct launches up to the next check point (or the end)
+      next = it == 0 ? 1 : (params->rel_tol > 0 ? it + check : max_iter);
+      if (next > max_iter) next = max_iter;
+      for (int j = it; j < next && r == S3TTV_OK; ++j) r = enqueue_iteration(pr, j, tm, st);
+    }
+    it = next;
+    if (r == S3TTV_OK && params->rel_tol > 0 && it < max_iter && it > 1) {
       int32_t done = 0;
-      CK(hipMemcpyAsync(&done, &pr.pl.sc->done, sizeof(done), hipMemcpyDeviceToHost, st));
-      CK(hipStreamSynchronize(st));
-      if (done) break;
+      if (hipMemcpyAsync(&done, &pr.pl.sc->done, sizeof(done), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        r = S3TTV_EHIP;
+      else if (done)
+        break;
     }
   }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (st != user) {  // the caller's stream waits for the solve, also after an error
+    if (hipEventRecord(solve_stream().out, st) != hipSuccess ||
+        hipStreamWaitEvent(user, solve_stream().out, 0) != hipSuccess)
+      r = r == S3TTV_OK ? S3TTV_EHIP : r;
+    st = user;
+  }
+  if (r != S3TTV_OK) return r;
   CK(hipEventRecord(e1, st));
   DevScalars hs;
   CK(hipMemcpyAsync(&hs, pr.pl.sc, sizeof(hs), hipMemcpyDeviceToHost, st));

@@ -189,3 +189,31 @@ def test_large_shape_first_iterations_and_invariants(device):
     assert np.isfinite(st["fid"]) and np.isfinite(st["dv_t"])
     _say("stats", {k: st[k] for k in ("iters", "fid", "dv_t", "eig_max_sweeps", "eig_avg_steps",
                                       "eig_max_steps", "eig_fallback_blocks", "ms")})
+
+
+@pytest.mark.parametrize("shape,k,reg", [((32, 32, 16), (3, 3), "s3ttv"), ((12, 12, 8), (10, 10), "s3ttv"),
+                                         ((20, 16, 12), (2, 2), "sstv")])
+def test_graph_replay_matches_direct_launches(device, shape, k, reg):
+    """The solve replays one captured graph of iterations (after the first) unless kernel
+    timing is requested, which launches every kernel directly. Both must give bitwise the same
+    result and iteration count: a fixed budget (first iteration, three replays, a direct
+    remainder) and a stop rule that fires inside a replay; two graph solves in a row with
+    other work between them agree too."""
+    import torch
+    _say("graph replay vs direct launches", shape, k, reg)
+    cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2,
+                          seed=77)
+    d = synth.make_hsi(cfg)
+    v = _t(d["v"], device)
+    sv = nt.Solver(*shape, *k, device=device)
+    for kw in (dict(max_iter=61), dict(max_iter=5000, rel_tol=1e-4)):
+        g = sv.solve(v, nt.make_params(regularizer=reg, **kw, **d["radii"]))
+        g = tuple(x.clone() for x in g[:3]) + (g[3],)
+        torch.ones(1 << 20, device=device).sum().item()   # eager work between the solves
+        g2 = sv.solve(v, nt.make_params(regularizer=reg, **kw, **d["radii"]))
+        dl = sv.solve(v, nt.make_params(regularizer=reg, timing_mask=1 << nt.K_FINAL, **kw,
+                                        **d["radii"]))
+        for a, b, c in zip(g[:3], g2[:3], dl[:3]):
+            assert torch.equal(a, b) and torch.equal(a, c)
+        assert g[3]["iters"] == g2[3]["iters"] == dl[3]["iters"]
+        _say("  ", kw, "iterations", g[3]["iters"])
