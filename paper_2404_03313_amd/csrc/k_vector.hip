@@ -111,7 +111,8 @@ __device__ inline float4 zfold_val4(const int *zpart, int4 off, int col) {
 //   u+ = P_box(u - g_u (D_s^T (D_v^T Zv + D_h^T Zh) + y3))        (eq. prox_box_constraint)
 //   xs = s - g_s y3,   xt = t - g_t (D_v^T y2 + y3),   y3 = kappa * w.
 // MODE 0: the field is adjoined by D_s^T D^T (S3TTV: the overlap-add sum of the blocks; SSTV:
-// the dual field itself); MODE 1: by D^T (STV); MODE 2: D_s^T D^T Z + omega D^T Z2 (HSSTV).
+// the dual field itself); MODE 1: by D^T (STV); MODE 2: D_s^T D^T Z + omega D^T Z2 (HSSTV);
+// MODE 3: as MODE 0 from the partial slots, four bands per thread.
 template <int MODE>
 __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
   __shared__ unsigned long long h[2][kL1Bins1];
@@ -122,14 +123,12 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
   const float kappa = (float)a.sc->kappa;
   double du2 = 0, u2 = 0, bad = 0;
   const int n2 = a.n2, n3 = a.n3, ncol = a.ncol, Bp = a.Bp;
-  // S3TTV with the partial-slot table and N3 divisible by 4: a thread takes four consecutive
-  // bands of one pixel, so the partials come in 16-byte loads and column b - 1 of band b is
-  // the previous band's column b (one halo column per quad). Same arithmetic per voxel.
-  const uintptr_t align = reinterpret_cast<uintptr_t>(a.u) | reinterpret_cast<uintptr_t>(a.s) |
-                          reinterpret_cast<uintptr_t>(a.t) | reinterpret_cast<uintptr_t>(a.w) |
-                          reinterpret_cast<uintptr_t>(a.y2) | reinterpret_cast<uintptr_t>(a.un) |
-                          reinterpret_cast<uintptr_t>(a.xs) | reinterpret_cast<uintptr_t>(a.xt);
-  const bool quads = MODE == 0 && a.zslot && (n3 & 3) == 0 && (align & 15) == 0;
+  // MODE 3 (S3TTV with the partial-slot table, N3 divisible by 4, 16-byte aligned arrays): a
+  // thread takes four consecutive bands of one pixel, so the partials come in 16-byte loads
+  // and column b - 1 of band b is the previous band's column b (one halo column per quad).
+  // Same arithmetic per voxel as MODE 0; a separate instance, so that the other modes keep
+  // their register budget.
+  constexpr bool quads = MODE == 3;
   const long long NQ = quads ? a.N >> 2 : 0;
   // two quads per trip, all of their loads issued before any arithmetic: the slot tables,
   // then the partials and the voxel values (a trip's stores would otherwise hold back the next
@@ -811,10 +810,16 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
   a.zpart = pl.zpart; a.zslot = pl.zfold && pl.reg <= kRegSTV ? pl.zslot : nullptr;
   a.Z2 = pl.gradf; a.omega = pl.omega;
   a.un = u_new; a.xs = pl.xs; a.xt = pl.xt; a.red = pl.red_primal; a.sc = pl.sc; a.hist = pl.hist;
+  const uintptr_t align = reinterpret_cast<uintptr_t>(a.u) | reinterpret_cast<uintptr_t>(a.s) |
+                          reinterpret_cast<uintptr_t>(a.t) | reinterpret_cast<uintptr_t>(a.w) |
+                          reinterpret_cast<uintptr_t>(a.y2) | reinterpret_cast<uintptr_t>(a.un) |
+                          reinterpret_cast<uintptr_t>(a.xs) | reinterpret_cast<uintptr_t>(a.xt);
   if (pl.reg == kRegSTV)
     hipLaunchKernelGGL(k_primal<1>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   else if (pl.reg == kRegHSSTV)
     hipLaunchKernelGGL(k_primal<2>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  else if (a.zslot && (pl.n3 & 3) == 0 && (align & 15) == 0)
+    hipLaunchKernelGGL(k_primal<3>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   else
     hipLaunchKernelGGL(k_primal<0>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   return hipGetLastError();
