@@ -23,8 +23,7 @@
  *    is 1..100: up to 16 rows the blocks are handled in registers and MFMA tiles (fused
  *    pass, warm-started MFMA eigen-solve); 17..100 rows (the paper's experiments use 10 x 10)
  *    take a one-workgroup-per-block path (FP32 Gram, warm-started parallel Jacobi with a
- *    certificate, low-rank clip, gathered overlap-add). The operator entry point
- *    s3ttv_op_dual_blocks supports K <= 16.
+ *    certificate, low-rank clip, gathered overlap-add).
  *  - Array arguments named "device" must be device pointers (hipMalloc / torch CUDA
  *    tensors) on the current HIP device; "host" arguments are host memory. The caller owns
  *    every buffer; the library never allocates device memory and keeps no state between
@@ -240,7 +239,9 @@ int32_t s3ttv_op_spectral_clip(int32_t nblk, int32_t K, int32_t ncols, const flo
  *   Y+_l = Y_l + g P_l D D_s up - g prox_{(1/g) nuclear}((Y_l + g P_l D D_s up)/g),
  *   zv, zh = sum_l P_l^T Y+_l.
  * up (device cube), yin / yout (device, L x K x 2*N3, block column 2b = D_v part, 2b+1 = D_h
- * part, as eq. SSST), zv, zh device cubes. */
+ * part, as eq. SSST), zv, zh device cubes. K = k1 k2 <= 16 runs the MFMA block kernels,
+ * 17..100 the one-workgroup-per-block kernel with its eigen-solve started from the identity.
+ * Returns S3TTV_ENONFINITE when a block holds NaN or Inf. */
 int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const float *up,
                              const float *yin, float *yout, float *zv, float *zh,
                              void *workspace, size_t workspace_bytes, void *stream);

@@ -1022,7 +1022,6 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
       if (!valid_shape(shape)) return S3TTV_EINVAL;
       const int32_t sup = supported_shape(shape);
       if (sup != S3TTV_OK) return sup;
-      if (op == S3TTV_OP_DUAL_BLOCKS && shape->k1 * shape->k2 > kRows) return S3TTV_EUNSUPPORTED;
       make_plan(pl, shape, nullptr);
       *bytes = pl.bytes;
       return S3TTV_OK;
@@ -1135,7 +1134,6 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   if (!(gamma_Y > 0 && isfinite(gamma_Y))) return S3TTV_EINVAL;
   const int32_t sup = supported_shape(shape);
   if (sup != S3TTV_OK) return sup;
-  if (shape->k1 * shape->k2 > kRows) return S3TTV_EUNSUPPORTED;
   Plan pl;
   make_plan(pl, shape, nullptr);
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
@@ -1144,6 +1142,24 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   hipStream_t st = (hipStream_t)stream;
   CK(launch_init_scalars(pl, 0.0, 0, st));
   CK(launch_grad(pl, up, up, 1.f, 0.f, pl.gradf, st));
+  if (pl.big) {
+    // one workgroup per block, its eigen-solve started from the identity; the overlap-add
+    // is a gather in a fixed order
+    CK(launch_big_pack(yin, pl.Y, pl.P, pl.K, pl.n3, pl.Bp, st));
+    BigArgs ba;
+    memset(&ba, 0, sizeof(ba));
+    ba.n1 = pl.n1; ba.n2 = pl.n2; ba.k1 = pl.k1; ba.k2 = pl.k2; ba.K = pl.K; ba.ncol = pl.ncol;
+    ba.nblk = pl.P; ba.gradf = pl.gradf; ba.gY = pl.g_Y; ba.Y = pl.Y; ba.V = pl.V;
+    ba.first = 1; ba.max_sweeps = kBigMaxSweeps; ba.sc = pl.sc;
+    CK(launch_big_block(ba, st));
+    CK(launch_big_overlap(ba, pl.Z, st));
+    CK(launch_big_unpack(pl.Y, yout, pl.P, pl.K, pl.n3, pl.Bp, st));
+    CK(launch_field_to_cubes(pl.Z, zv, zh, pl.P, pl.n3, pl.Bp, st));
+    int32_t bad = 0;
+    CK(hipMemcpyAsync(&bad, &pl.sc->nonfinite, sizeof(bad), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    return bad ? S3TTV_ENONFINITE : S3TTV_OK;
+  }
   CK(launch_pack_blocks(yin, pl.Y, pl.P, pl.K, 2 * pl.n3, pl.ncol, 1, pl.n3, pl.Bp, st));
   BlockArgs ba = block_args(pl);
   ba.V = nullptr;

@@ -648,6 +648,33 @@ __global__ __launch_bounds__(kNT) void k_big_identity(float *V, long long nblk, 
   }
 }
 
+// Blocks in the paper's column order (column 2b + comp of a row: band b of the D_v (comp 0)
+// or D_h (comp 1) part) <-> the block layout [block][K][ncol] with column comp * Bp + b; the
+// columns b >= n3 of each part are zero.
+__global__ __launch_bounds__(kNT) void k_big_pack(const float *src, float *Y, long long nblk, int K,
+                                                  int n3, int Bp) {
+  const int ncol = 2 * Bp;
+  const long long total = nblk * K * ncol;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kNT) {
+    const long long r = e / ncol;  // block * K + row
+    const int c = (int)(e - r * ncol);
+    const int comp = c >= Bp ? 1 : 0, b = c - comp * Bp;
+    Y[e] = b < n3 ? src[r * 2 * n3 + 2 * b + comp] : 0.f;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void k_big_unpack(const float *Y, float *dst, long long nblk,
+                                                    int K, int n3, int Bp) {
+  const long long total = nblk * K * 2 * n3;
+  for (long long e = (long long)blockIdx.x * kNT + threadIdx.x; e < total;
+       e += (long long)gridDim.x * kNT) {
+    const long long r = e / (2 * n3);
+    const int cs = (int)(e - r * 2 * n3);
+    dst[e] = Y[r * 2 * Bp + (cs & 1) * Bp + (cs >> 1)];
+  }
+}
+
 size_t big_lds_bytes(int K) {
   const int KS = K + 1;
   const int GS = KS > kGS ? KS : kGS;
@@ -670,6 +697,22 @@ hipError_t launch_big_overlap(const BigArgs &a, float *Z, hipStream_t st) {
   long long g = ((long long)a.n1 * a.n2 * a.ncol + kNT * 4 - 1) / (kNT * 4);
   if (g > 65535) g = 65535;
   hipLaunchKernelGGL(k_big_overlap, dim3((unsigned)g), dim3(kNT), 0, st, a, Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_pack(const float *src, float *Y, long long nblk, int K, int n3, int Bp,
+                          hipStream_t st) {
+  long long g = (nblk * K * 2 * Bp + kNT * 4 - 1) / (kNT * 4);
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_big_pack, dim3((unsigned)g), dim3(kNT), 0, st, src, Y, nblk, K, n3, Bp);
+  return hipGetLastError();
+}
+
+hipError_t launch_big_unpack(const float *Y, float *dst, long long nblk, int K, int n3, int Bp,
+                            hipStream_t st) {
+  long long g = (nblk * K * 2 * n3 + kNT * 4 - 1) / (kNT * 4);
+  if (g > 65535) g = 65535;
+  hipLaunchKernelGGL(k_big_unpack, dim3((unsigned)g), dim3(kNT), 0, st, Y, dst, nblk, K, n3, Bp);
   return hipGetLastError();
 }
 

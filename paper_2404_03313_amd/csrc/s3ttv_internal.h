@@ -184,6 +184,11 @@ struct BigArgs {
 hipError_t launch_big_block(const BigArgs &a, hipStream_t st);
 hipError_t launch_big_overlap(const BigArgs &a, float *Z, hipStream_t st);
 hipError_t launch_big_identity(float *V, long long nblk, int K, hipStream_t st);
+// Blocks in the paper's column order (L x K x 2 n3) <-> the block layout [L][K][2 Bp].
+hipError_t launch_big_pack(const float *src, float *Y, long long nblk, int K, int n3, int Bp,
+                          hipStream_t st);
+hipError_t launch_big_unpack(const float *Y, float *dst, long long nblk, int K, int n3, int Bp,
+                            hipStream_t st);
 size_t big_lds_bytes(int K);
 
 // Block kernels (Alg. 1 steps 9-10).

@@ -53,6 +53,19 @@ def test_clip_workspace_query(K, ncols, code):
         assert sz.value >= 7 * K * ncolp * 4 + 7 * K * K * 4
 
 
+@pytest.mark.parametrize("k,code", [((4, 4), 0), ((5, 4), 0), ((10, 10), 0), ((11, 10), nt.EUNSUPPORTED)])
+def test_dual_blocks_workspace_query(k, code):
+    # the operator covers the same block sizes as the solver (K = k1 k2 up to 100)
+    sz, sz_solve = ctypes.c_size_t(), ctypes.c_size_t()
+    sh = nt.Shape(12, 12, 20, *k)
+    assert nt.lib().s3ttv_op_workspace_bytes(nt.OP_DUAL_BLOCKS, ctypes.byref(sh), 0,
+                                             ctypes.byref(sz)) == code
+    if code == 0:
+        assert nt.lib().s3ttv_workspace_bytes(ctypes.byref(sh), None, ctypes.byref(sz_solve)) == 0
+        K = k[0] * k[1]
+        assert sz.value >= 144 * max(K, 16) * 2 * 32 * 4
+
+
 @pytest.mark.parametrize("shape,code", [((1, 8, 4, 1, 1), nt.EINVAL), ((8, 8, 1, 1, 1), nt.EINVAL),
                                         ((8, 8, 4, 9, 1), nt.EINVAL), ((8, 8, 4, 0, 2), nt.EINVAL),
                                         ((12, 12, 4, 11, 10), nt.EUNSUPPORTED)])

@@ -96,7 +96,10 @@ def test_spectral_clip_special_cases(device):
 
 
 DUAL_CASES = [((32, 32, 16), (3, 3)), ((13, 11, 7), (2, 3)), ((9, 20, 33), (4, 4)),
-              ((4, 6, 5), (4, 4)), ((2, 3, 2), (2, 3)), ((17, 9, 16), (1, 1)), ((24, 40, 20), (4, 2))]
+              ((4, 6, 5), (4, 4)), ((2, 3, 2), (2, 3)), ((17, 9, 16), (1, 1)), ((24, 40, 20), (4, 2)),
+              # more than 16 rows: the one-workgroup-per-block kernel (K = 20, 21, 100; the last
+              # window covers the whole 10 x 10 image, and K exceeds the 2 N3 = 40 columns)
+              ((12, 11, 9), (5, 4)), ((7, 13, 33), (3, 7)), ((10, 10, 20), (10, 10))]
 
 
 @pytest.mark.parametrize("shape,k", DUAL_CASES)
