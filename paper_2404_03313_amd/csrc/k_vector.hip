@@ -156,14 +156,25 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
     }
     float4 vi[2], vp[2], hj[2], hp[2], w4[2], u4[2], s4[2], t4[2], ye[2], ym[2];
     float Q0[2];
+    const bool halo[2] = {(threadIdx.x & 63) == 0 || b0[0] == 0, (threadIdx.x & 63) == 0 || b0[1] == 0};
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
       vi[h2] = zfold_val4(a.zpart, si[h2], b0[h2]);
       vp[h2] = zfold_val4(a.zpart, sp[h2], b0[h2]);
       hj[h2] = zfold_val4(a.zpart, sj[h2], Bp + b0[h2]);
       hp[h2] = zfold_val4(a.zpart, sp[h2], Bp + b0[h2]);
-      Q0[h2] = (zfold_val(a.zpart, si[h2], bm[h2]) - zfold_val(a.zpart, sp[h2], bm[h2])) +
-               (zfold_val(a.zpart, sj[h2], Bp + bm[h2]) - zfold_val(a.zpart, sp[h2], Bp + bm[h2]));
+      // Column b0 - 1 is the last column of the previous lane's quad (the same pixel's bands
+      // b0 - 4 .. b0 - 1), taken by a shuffle below, except where the quad starts its pixel
+      // (the column wraps to band n3 - 1) or the wavefront; only those lanes gather it here,
+      // the others all read word 0 (one cache line) and discard it.
+      {
+        const int4 z0 = make_int4(0, 0, 0, 0);
+        const int4 hi_ = halo[h2] ? si[h2] : z0, hp_ = halo[h2] ? sp[h2] : z0,
+                   hj_ = halo[h2] ? sj[h2] : z0;
+        const int cv = halo[h2] ? bm[h2] : 0, ch = halo[h2] ? Bp + bm[h2] : 0;
+        Q0[h2] = (zfold_val(a.zpart, hi_, cv) - zfold_val(a.zpart, hp_, cv)) +
+                 (zfold_val(a.zpart, hj_, ch) - zfold_val(a.zpart, hp_, ch));
+      }
       const long long e0 = qd[h2] * 4;
       w4[h2] = *reinterpret_cast<const float4 *>(a.w + e0);
       u4[h2] = *reinterpret_cast<const float4 *>(a.u + e0);
@@ -171,6 +182,14 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
       t4[h2] = *reinterpret_cast<const float4 *>(a.t + e0);
       ye[h2] = *reinterpret_cast<const float4 *>(a.y2 + e0);
       ym[h2] = *reinterpret_cast<const float4 *>(a.y2 + (size_t)pim[h2] * n3 + b0[h2]);
+    }
+    // the last column of every quad, passed one lane up (a lane whose previous quad is in
+    // the loop is itself in the loop, also at the tail, so every read is of an active lane)
+#pragma unroll
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const float last = (vi[h2].w - vp[h2].w) + (hj[h2].w - hp[h2].w);
+      const float prev = __shfl_up(last, 1, 64);
+      if (!halo[h2]) Q0[h2] = prev;
     }
 #pragma unroll
     for (int h2 = 0; h2 < 2; ++h2) {
