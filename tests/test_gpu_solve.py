@@ -66,7 +66,12 @@ def test_solve_parity_small_workload(device):
                                            ((6, 5, 3), (1, 2), 80), ((16, 16, 16), (4, 1), 50),
                                            # ragged wrapping tiles: more than 4 overlap-add
                                            # partials per pixel, summed by the separate pass
-                                           ((10, 10, 8), (4, 4), 40)])
+                                           ((10, 10, 8), (4, 4), 40),
+                                           # four-band primal path: one quad per pixel (every
+                                           # lane gathers the band below), and three per pixel
+                                           # with pixels split across wavefronts and a partial
+                                           # last wavefront
+                                           ((12, 9, 4), (2, 2), 60), ((11, 13, 12), (3, 3), 40)])
 def test_solve_parity_ragged(device, shape, k, iters):
     _say("solve ragged", shape, k, iters)
     cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2, seed=11)
