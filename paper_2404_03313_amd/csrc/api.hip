@@ -1140,6 +1140,7 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
   make_plan(pl, shape, (char *)workspace);
   pl.g_Y = (float)gamma_Y;
   hipStream_t st = (hipStream_t)stream;
+  CK(configure_block_kernels());  // the apply kernel's overlap-add may need more than 64 KB of LDS
   CK(launch_init_scalars(pl, 0.0, 0, st));
   CK(launch_grad(pl, up, up, 1.f, 0.f, pl.gradf, st));
   if (pl.big) {

@@ -25,6 +25,7 @@
 //
 // The overlap-add sum_l P_l^T Y_l is a gather (each pixel reads its K windows in a fixed
 // order), so results are reproducible.
+#include <atomic>
 #include "s3ttv_internal.h"
 
 namespace s3ttv {
@@ -682,12 +683,17 @@ size_t big_lds_bytes(int K) {
 }
 
 hipError_t launch_big_block(const BigArgs &a, hipStream_t st) {
-  static bool configured = false;
-  if (!configured) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_big_block,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsLimit);
+  // the dynamic-LDS limit, raised once per device (a bit per device id)
+  static std::atomic<unsigned long long> done{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const unsigned long long bit = dev < 64 ? 1ull << dev : 0ull;
+  if (!bit || !(done.load(std::memory_order_acquire) & bit)) {
+    e = hipFuncSetAttribute((const void *)k_big_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kLdsLimit);
     if (e != hipSuccess) return e;
-    configured = true;
+    if (bit) done.fetch_or(bit, std::memory_order_release);
   }
   hipLaunchKernelGGL(k_big_block, dim3((unsigned)a.nblk), dim3(kBT), big_lds_bytes(a.K), st, a);
   return hipGetLastError();

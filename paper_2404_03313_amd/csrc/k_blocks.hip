@@ -16,6 +16,7 @@
 // c = comp*Bp + band): column tile t holds columns 16t..16t+15 as 64 lanes x 4 floats,
 // lane L = 16*g + tc, slot s <-> element (row 4g+s, column 16t+tc). This is the B-operand /
 // result layout of v_mfma_f32_16x16x4_f32, so k_apply streams it with 16-byte accesses.
+#include <atomic>
 #include "s3ttv_internal.h"
 
 namespace s3ttv {
@@ -939,21 +940,25 @@ hipError_t allow_lds_nt(int bytes) {
 // Raises the dynamic-LDS limit of the kernels that take it, once per process (a host-side
 // attribute, so it is done before any stream work that might be captured into a graph).
 hipError_t configure_block_kernels() {
-  static hipError_t status = []() {
-    const int bytes = (int)kLdsLimit;
-    hipError_t e = hipFuncSetAttribute((const void *)k_apply,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = allow_lds_nt<2>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<4>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<6>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<8>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<10>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<12>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<14>(bytes);
-    if (e == hipSuccess) e = allow_lds_nt<16>(bytes);
-    return e;
-  }();
-  return status;
+  // once per device (a bit per device id; a repeated call from a racing thread is harmless)
+  static std::atomic<unsigned long long> done{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const unsigned long long bit = dev < 64 ? 1ull << dev : 0ull;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  const int bytes = (int)kLdsLimit;
+  e = hipFuncSetAttribute((const void *)k_apply, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess) e = allow_lds_nt<2>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<4>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<6>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<8>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<10>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<12>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<14>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<16>(bytes);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+  return e;
 }
 
 hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st) {

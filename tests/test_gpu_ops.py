@@ -5,6 +5,8 @@ arithmetic on inputs of magnitude <= ~1 (see the design notes): stencils and blo
 agree to ~1e-6 relative, the l1 threshold to ~1e-12 relative (exact-sum selection in
 FP64 on both sides).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -99,7 +101,9 @@ DUAL_CASES = [((32, 32, 16), (3, 3)), ((13, 11, 7), (2, 3)), ((9, 20, 33), (4, 4
               ((4, 6, 5), (4, 4)), ((2, 3, 2), (2, 3)), ((17, 9, 16), (1, 1)), ((24, 40, 20), (4, 2)),
               # more than 16 rows: the one-workgroup-per-block kernel (K = 20, 21, 100; the last
               # window covers the whole 10 x 10 image, and K exceeds the 2 N3 = 40 columns)
-              ((12, 11, 9), (5, 4)), ((7, 13, 33), (3, 7)), ((10, 10, 20), (10, 10))]
+              ((12, 11, 9), (5, 4)), ((7, 13, 33), (3, 7)), ((10, 10, 20), (10, 10)),
+              # overlap-add accumulators of 11 x 11 pixels x 144 columns: more than 64 KB of LDS
+              ((24, 24, 64), (4, 4))]
 
 
 @pytest.mark.parametrize("shape,k", DUAL_CASES)
@@ -122,6 +126,29 @@ def test_dual_blocks_match_oracle(device, shape, k):
     zs = max(np.abs(wzv).max(), np.abs(wzh).max())
     assert np.abs(_np(zv) - wzv).max() < 1e-4 * zs
     assert np.abs(_np(zh) - wzh).max() < 1e-4 * zs
+
+
+def test_dual_blocks_first_call_in_process(device):
+    """The operator raises the block kernels' LDS limit itself: called first in a fresh
+    process at a shape whose overlap-add needs more than 64 KB of LDS, it still runs."""
+    import subprocess
+    import sys
+    _say("op_dual_blocks first call in a fresh process")
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_2404_03313_amd import native as nt\n"
+        "rng = np.random.default_rng(3)\n"
+        "up = torch.from_numpy(rng.uniform(0, 1, size=(24, 24, 64)).astype(np.float32)).cuda()\n"
+        "Y = torch.zeros(24 * 24, 16, 128, device='cuda')\n"
+        "yout, zv, zh = nt.op_dual_blocks(up, Y, 4, 4, 0.25)\n"
+        "torch.cuda.synchronize()\n"
+        "assert bool(torch.isfinite(yout).all()) and float(yout.abs().max()) > 0\n"
+        "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().endswith("ok")
 
 
 L1_CASES = ["normal_large", "ties", "inside", "single", "zeros_denormals", "spiky", "c2_size",
