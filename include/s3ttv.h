@@ -26,8 +26,11 @@
  *    certificate, low-rank clip, gathered overlap-add).
  *  - Array arguments named "device" must be device pointers (hipMalloc / torch CUDA
  *    tensors) on the current HIP device; "host" arguments are host memory. The caller owns
- *    every buffer; the library never allocates device memory and keeps no state between
- *    calls. Device arrays must be 16-byte aligned and must not alias unless stated.
+ *    every buffer; the library never allocates device memory and keeps no data between
+ *    calls (it keeps HIP streams and events per calling thread and device, the raised LDS
+ *    limit of its kernels per device, and the batched solve's tuned anchor tile per shape).
+ *    Calls from several threads, on distinct workspaces, may run concurrently. Device
+ *    arrays must be 16-byte aligned and must not alias unless stated.
  *  - stream is a hipStream_t passed as void* (NULL = default stream). Every call enqueues
  *    its work on that stream and returns after that work has completed.
  *  - Return codes: 0 success, S3TTV_NOT_CONVERGED (solve ran max_iter iterations without

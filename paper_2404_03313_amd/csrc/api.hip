@@ -240,7 +240,15 @@ bool valid_params(const s3ttv_params *pr) {
   return true;
 }
 
-// Reusable HIP events for per-launch timing (kept for the life of the process).
+// The HIP device current on the calling thread (streams and events belong to one device).
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+// Reusable HIP events for per-launch timing, per thread and device (kept until the thread
+// ends).
 struct EventPool {
   std::vector<hipEvent_t> ev;
   size_t used = 0;
@@ -255,8 +263,8 @@ struct EventPool {
 };
 
 EventPool &event_pool() {
-  static EventPool p;
-  return p;
+  thread_local std::map<int, EventPool> pools;
+  return pools[current_device()];
 }
 
 struct Timer {
@@ -522,7 +530,8 @@ size_t plan_bytes_any_tile(const s3ttv_shape *sh) {
 
 size_t batch_header_bytes(int n) { return align_up((size_t)n * sizeof(DevScalars)); }
 
-// Streams and events of the batched solve, created once (default priority).
+// Streams and events of the batched solve, created once per thread and device (default
+// priority), so that concurrent batched calls from different threads do not share them.
 constexpr int kBatchStreams = 4;
 struct BatchStreams {
   hipStream_t main = nullptr, fork[kBatchStreams] = {};
@@ -541,8 +550,8 @@ struct BatchStreams {
 };
 
 BatchStreams &batch_streams() {
-  static BatchStreams b;
-  return b;
+  thread_local std::map<int, BatchStreams> m;
+  return m[current_device()];
 }
 
 // Anchor tile per problem shape: the fastest candidate for the warm block pass, timed on the
@@ -668,9 +677,9 @@ int32_t s3ttv_solve(const s3ttv_shape *shape, const s3ttv_params *params, const 
                           workspace_bytes, stream, stats);
 }
 
-// A non-blocking stream of the calling thread on which a solve captures and replays its
-// iteration graphs (a capture needs a stream of its own; the caller's stream may be the null
-// stream). Joined to the caller's stream with events before and after.
+// A non-blocking stream of the calling thread and device on which a solve captures and
+// replays its iteration graphs (a capture needs a stream of its own; the caller's stream may
+// be the null stream). Joined to the caller's stream with events before and after.
 struct SolveStream {
   hipStream_t s = nullptr;
   hipEvent_t in = nullptr, out = nullptr;
@@ -683,8 +692,8 @@ struct SolveStream {
 };
 
 SolveStream &solve_stream() {
-  thread_local SolveStream s;
-  return s;
+  thread_local std::map<int, SolveStream> m;
+  return m[current_device()];
 }
 
 int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
