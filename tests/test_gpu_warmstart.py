@@ -1,7 +1,7 @@
 """What the learned initial estimate gains (GPU). The network is trained by the library's
 own kernels on solver-generated pairs; held-out scenes are then solved from u0 = 0 and from
 u0 = v + f(v). Prob. (18) is convex with (measured) a unique solution, so every start ends at
-the same point: the zero-start run is the judge of the warm-started one.
+the same point: the zero-start run is the yardstick for the warm-started one.
 
 What is asserted is what holds scene after scene: the estimate is far closer to the solution
 than the observation; the iterates stay closer to the solution during the first hundred
