@@ -128,6 +128,21 @@ def test_dual_blocks_match_oracle(device, shape, k):
     assert np.abs(_np(zh) - wzh).max() < 1e-4 * zs
 
 
+@pytest.mark.parametrize("k", [(4, 4), (5, 4)])
+def test_dual_blocks_nonfinite_input(device, k):
+    """A NaN in one block is reported as ENONFINITE by both block routes (16 rows or fewer,
+    and more)."""
+    _say("op_dual_blocks NaN", k)
+    rng = np.random.default_rng(8)
+    n1, n2, n3 = 9, 8, 6
+    up = rng.uniform(0, 1, size=(n1, n2, n3)).astype(np.float32)
+    Y = (rng.normal(size=(n1 * n2, k[0] * k[1], 2 * n3)) * 0.05).astype(np.float32)
+    Y[5, 3, 7] = np.nan
+    with pytest.raises(nt.S3TTVError) as ei:
+        nt.op_dual_blocks(_t(up, device), _t(Y, device), k[0], k[1], 0.25)
+    assert ei.value.code == nt.ENONFINITE
+
+
 def test_dual_blocks_first_call_in_process(device):
     """The operator raises the block kernels' LDS limit itself: called first in a fresh
     process at a shape whose overlap-add needs more than 64 KB of LDS, it still runs."""
