@@ -1,0 +1,46 @@
+"""Host logic of bench.py (CPU only): the HBM traffic of the dominant kernel is reported only
+while the kernel source matches the hash recorded with the counters, and more than one GPU
+is refused before anything touches a device."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _layout(tmp_path, source_text, recorded_hash):
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / "k.hip"
+    src.write_text(source_text)
+    (tmp_path / "profiles" / "hbm_bytes_x.md").write_text(
+        "# summary\n\n"
+        f"traffic k_block_fused bytes_per_launch=12345 source=k.hip sha256_16={recorded_hash}\n")
+    return src
+
+
+def test_traffic_reported_while_source_unchanged(tmp_path, monkeypatch):
+    text = "__global__ void k() {}\n"
+    digest = hashlib.sha256(text.encode()).hexdigest()[:16]
+    src = _layout(tmp_path, text, digest)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("k_block_fused") == (12345, os.path.join("profiles", "hbm_bytes_x.md"))
+    assert bench.measured_traffic("k_other") is None
+    src.write_text(text + "// changed\n")
+    assert bench.measured_traffic("k_block_fused") is None
+
+
+def test_committed_traffic_line_matches_the_source():
+    # the committed summary belongs to the committed block kernels
+    got = bench.measured_traffic("k_block_fused")
+    assert got is not None and got[0] > 2_000_000_000
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr
+    assert r.stdout.strip() == ""
