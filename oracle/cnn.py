@@ -20,6 +20,9 @@ Two arithmetic modes:
     where the GPU path stores them in that format: the weights of all layers (biases are kept),
     the four hidden activations, and the four hidden-layer gradients. The remaining
     difference to the GPU path is the FP32 summation order.
+A callable may be given instead of a mode name: it is applied at the same storage points in
+place of the bfloat16 rounding (the tests pass random relative perturbations of the size of a
+bfloat16 rounding error, to measure how such errors propagate to the outputs).
 """
 from __future__ import annotations
 
@@ -109,12 +112,12 @@ def conv_wgrad(x, g):
 
 def forward(params, v, mode: str = "exact"):
     """u0 = v + f(v). v: (nb, n1, n2, n3) (or one (n1, n2, n3) volume). Returns (u0, cache)."""
-    assert mode in ("exact", "bf16")
+    assert callable(mode) or mode in ("exact", "bf16")
     v = np.asarray(v, dtype=np.float64)
     single = v.ndim == 3
     if single:
         v = v[None]
-    rnd = bf16_round if mode == "bf16" else (lambda a: a)
+    rnd = mode if callable(mode) else (bf16_round if mode == "bf16" else (lambda a: a))
     layers = [(rnd(W), b) for W, b in unpack(params)]
     acts = []
     x = v[..., None]

@@ -10,6 +10,11 @@ activations or gradients (one ulp = 2^-8 relative, at a rate of roughly FP32 err
   * Adam:     the update, per block, ||dupdate|| <= 1e-3 ||update||.
 A systematic error (a wrong tap, a lost ReLU mask, truncation instead of rounding to
 nearest) moves every value by a BF16 ulp or more and fails these bounds.
+
+The same kernels are also compared with the exact FP64 network (the oracle's exact mode), under
+a bound that follows from the storage formats alone (tests/cnn_error_bound.py): LAMBDA = 3 times
+the spread of independent relative errors of bfloat16 size at the storage points. That check
+does not depend on the oracle's bf16 mode choosing the same rounding points as the kernels.
 """
 import numpy as np
 import pytest
@@ -160,3 +165,29 @@ def test_forward_full_scene_sampled(device):
         fs.append(abs(r - float(v[i, j, b])))
     print(f"  max err {max(errs):.2e}, max |f| {max(fs):.2e}", flush=True)
     assert max(errs) <= 2e-3 * max(fs) + 1e-6
+
+
+@pytest.mark.parametrize("shape", [(2, 7, 9, 21), (1, 1, 5, 3), (3, 5, 4, 17)])
+def test_forward_and_gradient_within_storage_bound_of_exact_network(device, shape):
+    """u0, the loss and every parameter block of the gradient against the exact FP64 network,
+    within LAMBDA x the spread of bfloat16-sized storage errors (per output block)."""
+    import cnn_error_bound as eb
+    print(f"exact-network bound shape={shape}", flush=True)
+    v, target = _inputs(shape, 81)
+    params = synth.cnn_random_params(seed=82)
+    p64, v64, t64 = params.astype(np.float64), v.astype(np.float64), target.astype(np.float64)
+    tp, tv = torch.from_numpy(params).to(device), torch.from_numpy(v).to(device)
+    u0 = nt.cnn_forward(tp, tv).cpu().numpy().astype(np.float64)
+    ref, spread = eb.forward_spread(p64, v64)
+    r = np.linalg.norm(u0 - ref) / spread
+    print(f"  u0: error / spread {r:.2f}", flush=True)
+    assert r <= eb.LAMBDA
+    loss, grad = nt.cnn_grad(tp, tv, torch.from_numpy(target).to(device))
+    g = grad.cpu().numpy().astype(np.float64)
+    rl, rg, sp, sp_loss = eb.grad_spread(p64, v64, t64)
+    print(f"  loss: error / spread {abs(loss - rl) / sp_loss:.2f}", flush=True)
+    assert abs(loss - rl) <= eb.LAMBDA * sp_loss + 1e-6 * abs(rl)
+    for name, a, b in eb.blocks():
+        r = np.linalg.norm(g[a:b] - rg[a:b]) / sp[name]
+        print(f"  {name}: error / spread {r:.2f}", flush=True)
+        assert r <= eb.LAMBDA, name

@@ -148,3 +148,67 @@ def test_adam_matches_torch_optimizer():
         opt.step()
         p, m, v2 = cnn.adam(p, m, v2, g, k, 1e-3)
     np.testing.assert_allclose(p, pt.detach().numpy(), rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------ the storage-rounding bound of the GPU tests
+
+def _bound_inputs(shape, seed):
+    rng = _rng(seed)
+    v = rng.uniform(0, 1, size=shape).astype(np.float32).astype(np.float64)
+    target = (v + rng.normal(0, 0.05, size=shape)).astype(np.float32).astype(np.float64)
+    return v, target
+
+
+def test_storage_rounding_bound_covers_bf16_rounding():
+    """The bound the GPU tests apply against the exact network (LAMBDA x the spread of random
+    bfloat16-sized relative errors at the storage points) holds for the actual round-to-nearest
+    bfloat16 errors at those points (the oracle's bf16 mode), for the output and every
+    parameter block, with the deterministic error of the size the random model predicts."""
+    import cnn_error_bound as eb
+    v, target = _bound_inputs((2, 7, 9, 21), 71)
+    params = synth.cnn_random_params(seed=72).astype(np.float64)
+    u0, spread = eb.forward_spread(params, v)
+    ub, _ = cnn.forward(params, v, "bf16")
+    r = np.linalg.norm(ub - u0) / spread
+    assert 0.1 < r < eb.LAMBDA, r
+    loss, g, sp, sp_loss = eb.grad_spread(params, v, target)
+    lb, gb = cnn.loss_grad(params, v, target, "bf16")
+    assert abs(lb - loss) <= eb.LAMBDA * sp_loss
+    for name, a, b in eb.blocks():
+        r = np.linalg.norm(gb[a:b] - g[a:b]) / sp[name]
+        assert 0.05 < r < eb.LAMBDA, (name, r)
+        # the bound is a small fraction of the gradient itself
+        assert sp[name] < 0.05 * np.linalg.norm(g[a:b]), name
+
+
+def test_storage_rounding_bound_rejects_planted_mistakes():
+    """Structural mistakes in a network that rounds where the kernels round exceed the bound:
+    one tap of a middle layer read mirrored (forward), and the sign of one hidden layer's data
+    gradient lost in the backward pass (gradient)."""
+    import cnn_error_bound as eb
+    v, target = _bound_inputs((2, 7, 9, 21), 73)
+    params = synth.cnn_random_params(seed=74).astype(np.float64)
+    u0, spread = eb.forward_spread(params, v)
+    layers = cnn.unpack(params)
+    W = layers[2][0].copy()
+    W[[0, 26]] = W[[26, 0]]          # tap (-1,-1,-1) swapped with (+1,+1,+1)
+    layers[2] = (W, layers[2][1])
+    bad, _ = cnn.forward(cnn.pack(layers), v, "bf16")
+    assert np.linalg.norm(bad - u0) > 10 * eb.LAMBDA * spread
+
+    loss, g, sp, _ = eb.grad_spread(params, v, target)
+    orig = cnn.conv_adj
+    calls = {"n": 0}
+
+    def adj_unmasked(gg, Wt):
+        # the second data gradient of the backward pass loses its sign
+        calls["n"] += 1
+        out = orig(gg, Wt)
+        return out if calls["n"] != 2 else np.abs(out)
+    cnn.conv_adj = adj_unmasked
+    try:
+        _, gbad = cnn.loss_grad(params, v, target, "bf16")
+    finally:
+        cnn.conv_adj = orig
+    worst = max(np.linalg.norm(gbad[a:b] - g[a:b]) / sp[n] for n, a, b in eb.blocks())
+    assert worst > 10 * eb.LAMBDA

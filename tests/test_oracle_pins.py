@@ -152,6 +152,9 @@ def test_lemma2_step_sizes():
     np.testing.assert_array_equal(row[mY:mY + n], 2)
     np.testing.assert_array_equal(row[mY + n:], 3)
     g = oracle.default_gammas(k1, k2)
+    # the default steps are the reciprocal column / row sums
+    assert (g["gamma_u"], g["gamma_s"], g["gamma_t"]) == (1 / col[0], 1 / col[n], 1 / col[2 * n])
+    assert (g["gamma_Y"], g["gamma_y2"], g["gamma_y3"]) == (1 / row[0], 1 / row[mY], 1 / row[mY + n])
     G1 = np.concatenate([np.full(n, g["gamma_u"]), np.full(n, g["gamma_s"]), np.full(n, g["gamma_t"])])
     G2 = np.concatenate([np.full(mY, g["gamma_Y"]), np.full(n, g["gamma_y2"]), np.full(n, g["gamma_y3"])])
     M = np.sqrt(G2)[:, None] * A * np.sqrt(G1)[None, :]
@@ -365,3 +368,44 @@ def test_stop_rule():
     n = r["stats"]["iters"]
     assert n >= 2 and tr[n - 1] < 5e-3
     assert np.all(tr[1:n - 1] >= 5e-3)
+
+
+def test_stop_rule_quantity_from_separate_runs():
+    """eq. StopCri_simulated: after iteration k the rule measures
+    ||u^(k) - u^(k-1)|| / ||u^(k-1)||, with the previous iterate's norm below. The value is
+    formed here from two separate oracle runs of k - 1 and k iterations (the iterate map is
+    deterministic) and compared with the oracle's own trace. The other reading, dividing by
+    ||u^(k)||, differs from it by more than 1e-3 relative at k = 3, so a swapped denominator
+    fails."""
+    d = _tiny()
+    kw = dict(k1=2, k2=2, **d["radii"])
+    full = oracle.solve(d["v64"], max_iter=12, trace=True, **kw)
+    # from zero, u^(1) = P_box(0) = 0: the rule is undefined at k = 2 (reported as infinite)
+    assert np.isinf(full["trace"][1])
+    for k in (3, 4, 7, 12):
+        prev = oracle.solve(d["v64"], max_iter=k - 1, **kw)["u"]
+        cur = oracle.solve(d["v64"], max_iter=k, **kw)["u"]
+        diff = np.linalg.norm(cur - prev)
+        want = diff / np.linalg.norm(prev)
+        other = diff / np.linalg.norm(cur)
+        assert full["trace"][k - 1] == pytest.approx(want, rel=1e-12), k
+        if k == 3:
+            assert abs(other - want) > 1e-3 * want
+
+
+@pytest.mark.parametrize("reg", ["s3ttv", "stv", "sstv", "hsstv"])
+def test_oracle_default_steps_equal_lemma2_values(reg):
+    """The C oracle's built-in step sizes (all gammas 0) are the Lemma-2 values that
+    test_lemma2_step_sizes and the variant tests derive from the stacked operator's column and
+    row sums: a solve with the defaults equals, bitwise, a solve given those values."""
+    d = _tiny(shape=(6, 7, 5))
+    kw = dict(max_iter=9, regularizer=reg, **d["radii"])
+    a = oracle.solve(d["v64"], 2, 3, **kw)
+    b = oracle.solve(d["v64"], 2, 3, gammas=oracle.default_gammas(2, 3, reg), **kw)
+    for name in ("u", "s", "t"):
+        assert np.array_equal(a[name], b[name]), name
+    # the defaults are not a no-op: another admissible (smaller) step gives another iterate
+    g = dict(oracle.default_gammas(2, 3, reg))
+    g["gamma_u"] *= 0.5
+    c = oracle.solve(d["v64"], 2, 3, gammas=g, **kw)
+    assert not np.array_equal(a["u"], c["u"])
