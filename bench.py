@@ -2,12 +2,18 @@
 
 A step is one full iteration of Alg. 1 (primal step, both l1-ball projections, gradient
 field, block Gram / eigen-solve / spectral clip / overlap-add, dual steps, scalar
-reductions) on a seeded synthetic 256 x 256 x 128 hyperspectral cube with block 4 x 4.
+reductions) on a seeded synthetic 256 x 256 x 128 hyperspectral cube with block 4 x 4. The
+timed steps continue a solve from zero after a pre-roll (200 iterations by default) and the
+warm-up steps, so they are iterations of the phase in which the blocks clip (from zero no
+block clips during the first ~30 iterations; a solve to rel-tol 1e-4 takes ~625).
 
 Prints one JSON line. Besides the throughput it reports
   - roofline: the dominant kernel (the fused block pass: Gram, eigen-solve, clip and
     overlap-add of every dual block) timed live with HIP events inside the timed solve,
-    against its algorithmic bytes and the 8 TB/s HBM peak;
+    against the algorithmic bytes of steps 9-10 (every dual block read and written once) and
+    the 8 TB/s HBM peak; the bytes the pass moves by design are reported beside them;
+  - gram_mfma: the Gram products' flop rate over the block-pass time against the MFMA peak
+    of their input precision, and the matrix-pipe busy fraction from the counter summary;
   - time_to_rel_tol: wall time and iterations of a solve stopped by the paper's rule with
     tolerance 1e-4;
   - cpu_baseline: the FP64 oracle timed on this host on a bounded sample (the first three
@@ -34,12 +40,55 @@ METRIC = "P-PDS iters/sec + time-to-rel-tol 1e-4, 256×256×128 HSI, vs plain FP
 
 
 def block_pass_algorithmic_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> int:
-    """Bytes the fused block pass must move per launch: read and write every dual block
-    (K x 2*n3 floats), read the gradient field (2 floats per voxel), write the overlap-add
-    field (2 floats per voxel), read and write the stored 16 x 16 eigenbasis of every block."""
+    """Bytes the block pass (Alg. 1 steps 9-10) must move per launch: read and write every dual
+    block Y_l, K x 2 n3 floats, i.e. 16 K n3 bytes per block, L = n1 n2 blocks. The gradient
+    field, the overlap-add field and the kept eigenbases are this implementation's own
+    traffic and are not counted."""
+    L = n1 * n2
+    K = k1 * k2
+    return 16 * K * n3 * L
+
+
+def block_pass_design_bytes(n1: int, n2: int, n3: int, k1: int, k2: int) -> int:
+    """Bytes the fused block pass as designed moves per launch: the dual blocks read and
+    written, the gradient field read (2 floats per voxel), the overlap-add field written
+    (2 floats per voxel) and the stored 16 x 16 eigenbasis of every block read and written."""
     L = n1 * n2
     K = k1 * k2
     return 4 * L * (2 * K * 2 * n3 + 2 * n3 + 2 * n3 + 2 * 256)
+
+
+def gram_flops(n1: int, n2: int, n3: int, k1: int, k2: int) -> int:
+    """Flops of the block Gram products Y' Y'^T of one block pass: K x K outputs of length
+    2 n3, two flops per product term, L = n1 n2 blocks."""
+    K = k1 * k2
+    return 2 * K * K * 2 * n3 * n1 * n2
+
+
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}
+
+
+def measured_counter(name: str, kernel: str):
+    """A per-launch figure of `kernel` from the committed rocprofv3 counter summaries (lines
+    `<name> <kernel> value=... source=... sha256_16=...`), or None when the kernel source has
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) < 4 or parts[0] != name or parts[1] != kernel:
+                    continue
+                kv = dict(p.split("=", 1) for p in parts[2:] if "=" in p)
+                src = os.path.join(ROOT, kv.get("source", ""))
+                if not os.path.isfile(src):
+                    continue
+                with open(src, "rb") as fs:
+                    digest = hashlib.sha256(fs.read()).hexdigest()[:16]
+                if digest == kv.get("sha256_16"):
+                    return float(kv["value"]), os.path.relpath(path, ROOT)
+    return None
 
 
 def measured_traffic(kernel: str):
@@ -475,6 +524,9 @@ def main() -> int:
                     help="c5: iteration cap of the rel-tol 1e-6 reference solve")
     ap.add_argument("--gram-precision", choices=["fp32", "bf16", "fp16"], default="fp32",
                     help="input precision of the block Gram products (accumulation stays FP32)")
+    ap.add_argument("--preroll", type=int, default=200,
+                    help="c2: iterations from zero run before the warm-up and timed ones (the "
+                         "timed iterations continue that solve)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -511,18 +563,23 @@ def main() -> int:
 
     reg = args.regularizer
     l1_reg = reg in ("sstv", "hsstv")
-    print(f"[bench] warmup {args.warmup} iterations", file=sys.stderr, flush=True)
-    solver.solve(v, nt.make_params(max_iter=max(args.warmup, 1), gram_precision=prec,
-                                   regularizer=reg, **rad))
+    # The timed iterations continue a solve from zero after `preroll` iterations (plus the
+    # warm-up ones), so that they are iterations of the clipping phase that makes up almost
+    # all of a solve to tolerance (from zero no block clips for the first ~30 iterations).
+    first = args.preroll + max(args.warmup, 1)
+    print(f"[bench] pre-roll {args.preroll} + warmup {args.warmup} iterations from zero",
+          file=sys.stderr, flush=True)
+    solver.solve(v, nt.make_params(max_iter=first, gram_precision=prec, regularizer=reg, **rad))
     torch.cuda.synchronize()
 
-    print(f"[bench] timed {args.steps} iterations", file=sys.stderr, flush=True)
+    print(f"[bench] timed {args.steps} iterations (iterations {first + 1}-{first + args.steps})",
+          file=sys.stderr, flush=True)
     cls = nt.K_DUAL if l1_reg else nt.K_BLOCK
     params = nt.make_params(max_iter=args.steps, timing_mask=1 << cls, gram_precision=prec,
                             regularizer=reg, **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    u, s, t, st = solver.solve(v, params)
+    u, s, t, st = solver.resume(v, params)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = args.steps / wall
@@ -532,6 +589,7 @@ def main() -> int:
         print(f"bench.py: the timed kernel ({name}) did not run", file=sys.stderr)
         return 3
     block_ms = st["kernel_ms"][name] / block_calls
+    design_bytes = None
     if l1_reg:
         # the dual sweep is the largest pass of the l1 variants: 36 B read and 16 B written per
         # voxel for the vector duals and s, t, plus the l1 dual field(s) read and written
@@ -540,6 +598,7 @@ def main() -> int:
     else:
         kname = "k_block_fused"
         block_bytes = block_pass_algorithmic_bytes(n1, n2, n3, k1, k2)
+        design_bytes = block_pass_design_bytes(n1, n2, n3, k1, k2)
     achieved = block_bytes / (block_ms * 1e-3) / 1e9
 
     traffic = measured_traffic(kname) if reg == "s3ttv" else None
@@ -568,13 +627,28 @@ def main() -> int:
                      "traffic": traffic[0] if traffic else None, "avg_launch_ms": block_ms,
                      "launches_timed": block_calls,
                      "algorithmic_bytes_per_launch": block_bytes,
+                     "design_bytes_per_launch": design_bytes,
                      "traffic_source": traffic[1] if traffic else None},
+        "timed_iterations": [first + 1, first + args.steps],
         "eig_max_sweeps": st["eig_max_sweeps"],
         "eig_avg_sweeps": st["eig_avg_sweeps"],
         "eig_avg_steps": st["eig_avg_steps"],
         "eig_max_steps": st["eig_max_steps"],
         "eig_fallback_blocks": st["eig_fallback_blocks"],
     }
+    if not l1_reg:
+        # MFMA use of the Gram stage: the Gram flops of a launch over the whole block-pass time
+        # (the stage shares the launch with the eigen-solve, the clip and the overlap-add, so
+        # this is a lower bound of the stage's own rate), and the matrix-pipe busy fraction of
+        # the whole launch from the committed counter summary while the source is unchanged
+        gf = gram_flops(n1, n2, n3, k1, k2)
+        busy = measured_counter("mfma_busy_frac", kname) if reg == "s3ttv" else None
+        peak = MFMA_PEAK_TFLOPS[args.gram_precision]
+        out["gram_mfma"] = {"flops_per_launch": gf, "achieved_tflops": gf / (block_ms * 1e-3) / 1e12,
+                            "peak_tflops": peak,
+                            "frac": gf / (block_ms * 1e-3) / 1e12 / peak,
+                            "launch_mfma_busy_frac": busy[0] if busy else None,
+                            "busy_source": busy[1] if busy else None}
 
     if args.copy_probe:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)

@@ -56,7 +56,8 @@ enum {
   S3TTV_ENONFINITE = -5    /* NaN/Inf met in the input or in the iterates */
 };
 
-/* Image and block geometry. n1, n2, n3 >= 2; 1 <= k1 <= n1; 1 <= k2 <= n2; k1*k2 <= 16. */
+/* Image and block geometry. n1, n2, n3 >= 2; 1 <= k1 <= n1; 1 <= k2 <= n2; k1*k2 <= 100
+ * (larger blocks: S3TTV_EUNSUPPORTED); n1*n2*n3 < 2^31. */
 typedef struct {
   int32_t n1, n2, n3, k1, k2;
 } s3ttv_shape;
@@ -180,6 +181,22 @@ int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, c
                          const float *u0, const float *s0, const float *t0, float *u, float *s,
                          float *t, void *workspace, size_t workspace_bytes, void *stream,
                          s3ttv_stats *stats);
+
+/* Continues Alg. 1 from the iterate that an earlier s3ttv_solve, s3ttv_solve_from or
+ * s3ttv_solve_continue call left in `workspace` (same shape, regulariser and workspace; the
+ * same observation v must be passed). Runs at most params->max_iter more iterations with this
+ * call's rel_tol, check_every, timing_mask, eig_max_steps and gram_precision (the step sizes
+ * and radii should be those of the first call: P-PDS does not change them between iterations).
+ * Iteration k of the continued run is iteration k of one uninterrupted solve: a solve of n1
+ * iterations continued by n2 gives bitwise the result of a solve of n1 + n2 iterations. The
+ * stop rule (eq. StopCri_simulated) is checked from the first continued iteration; stats
+ * count the iterations and eigen-solves of this call only. Returns S3TTV_EINVAL when the
+ * workspace holds no state of this problem (never solved, another shape or regulariser, a
+ * batched solve's workspace) and S3TTV_ENONFINITE when the held state met a non-finite value.
+ * v (device, input), u, s, t (device, outputs), workspace (device), stats (host, nullable). */
+int32_t s3ttv_solve_continue(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                             float *u, float *s, float *t, void *workspace,
+                             size_t workspace_bytes, void *stream, s3ttv_stats *stats);
 
 /* ---------------- Batched solve ---------------- */
 

@@ -60,6 +60,13 @@ int32_t supported_shape(const s3ttv_shape *sh) {
   if (sh->k1 * sh->k2 > kBigMax) return S3TTV_EUNSUPPORTED;
   const long long N = (long long)sh->n1 * sh->n2 * sh->n3;
   if (N >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
+  if (sh->k1 * sh->k2 <= kRows) {
+    // the smallest anchor tile (1 x 1) must hold its overlap-add accumulators in LDS:
+    // k1 k2 pixels of 2 Bp + 16 floats (N3 up to 1200 for 4 x 4 blocks)
+    const size_t Bp = (size_t)(sh->n3 + 15) / 16 * 16;
+    if ((size_t)sh->k1 * sh->k2 * (2 * Bp + 16) * sizeof(float) > kMaxLds)
+      return S3TTV_EUNSUPPORTED;
+  }
   return S3TTV_OK;
 }
 
@@ -458,7 +465,7 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
 
 // Result copies and statistics from the final scalars hs (tm: timed launches, nullable).
 int32_t finish(const Problem &pr, const DevScalars &hs, float ms, Timer *tm, s3ttv_stats *stats,
-               hipStream_t st) {
+               hipStream_t st, int iters_before = 0) {
   const Plan &pl = pr.pl;
   int32_t code = S3TTV_OK;
   if (hs.nonfinite) code = S3TTV_ENONFINITE;
@@ -482,7 +489,7 @@ int32_t finish(const Problem &pr, const DevScalars &hs, float ms, Timer *tm, s3t
       stats->fid = sqrt(diag[2]);
       stats->dv_t = sqrt(diag[3]);
     }
-    stats->iters = hs.iters;
+    stats->iters = hs.iters - iters_before;
     stats->converged = hs.converged && !hs.nonfinite;
     stats->rel_change = hs.rel_change;
     stats->eig_max_sweeps = hs.max_sweeps;
@@ -651,7 +658,9 @@ const char *s3ttv_strerror(int32_t code) {
     case S3TTV_OK: return "ok";
     case S3TTV_NOT_CONVERGED: return "max_iter reached before rel_tol";
     case S3TTV_EINVAL: return "invalid argument";
-    case S3TTV_EUNSUPPORTED: return "unsupported configuration (block rows k1*k2 > 16 or too large)";
+    case S3TTV_EUNSUPPORTED:
+      return "unsupported configuration (block rows k1*k2 > 100, 2^31 or more voxels, or a block "
+             "pass that does not fit the LDS)";
     case S3TTV_EWORKSPACE: return "workspace too small";
     case S3TTV_EHIP: return "HIP runtime error";
     case S3TTV_ENONFINITE: return "non-finite value in input or iterates";
@@ -691,43 +700,29 @@ struct SolveStream {
   }
 };
 
-SolveStream &solve_stream() {
+static SolveStream &solve_stream() {
   thread_local std::map<int, SolveStream> m;
   return m[current_device()];
 }
 
-int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
-                         const float *u0, const float *s0, const float *t0, float *u, float *s,
-                         float *t, void *workspace, size_t workspace_bytes, void *stream,
-                         s3ttv_stats *stats) {
-  Problem pr;
-  const int32_t prep = prepare(pr, shape, params, v, u0, u, s, t, workspace, workspace_bytes, 0, 0);
-  if (prep != S3TTV_OK) return prep;
-  pr.s0 = s0;
-  pr.t0 = t0;
-  CK(configure_block_kernels());
-  hipStream_t st = (hipStream_t)stream;
-  Timer tm{params->timing_mask, st, {}};
-  event_pool().used = 0;
-  const int32_t ini = enqueue_init(pr, st);
-  if (ini != S3TTV_OK) return ini;
-  {
-    DevScalars hs0;
-    CK(hipMemcpyAsync(&hs0, pr.pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    const int32_t chk = check_init(pr, hs0);
-    if (chk != S3TTV_OK) return chk;
-  }
+// The state signature a single solve records in its workspace (checked by a continuation).
+static StateSig state_sig(const Problem &pr) {
+  const Plan &pl = pr.pl;
+  return StateSig{{kStateMagic, pl.n1, pl.n2, pl.n3, pl.k1, pl.k2, pl.reg, pl.TA * 256 + pl.TB}};
+}
+
+// Iterations it0 .. it_end - 1 of one problem whose state is in its workspace (stopping early
+// when the rule fires), then the result copies and statistics. Iteration it0 == 0 runs
+// directly; then, unless kernel timing is requested, one captured graph of `span` iterations
+// (even, so the u / t buffer parity of its launches repeats) is replayed until the budget is
+// used or the stop rule has fired on the device (a finished solve's later launches exit at
+// once), and the remainder runs directly. The host reads the stop flag between spans.
+static int32_t run_iterations(Problem &pr, const s3ttv_params *params, int it0, int it_end,
+                              hipStream_t user, Timer &tm, s3ttv_stats *stats) {
+  hipStream_t st = user;
   const int check = params->check_every > 0 ? params->check_every : 16;
-  // Iteration 1 directly; then, unless kernel timing is requested, one captured graph of
-  // `span` iterations (even, so the u / t buffer parity of its launches repeats) replayed
-  // until the budget is used or the stop rule has fired on the device (a finished solve's
-  // later launches exit at once), and the remainder directly. The host reads the stop flag
-  // between spans.
-  const int max_iter = params->max_iter;
   const int span = check < 2 ? 2 : (check > 256 ? 256 : (check + 1) & ~1);
-  bool use_graph = params->timing_mask == 0 && max_iter > 1 + span;
-  const hipStream_t user = st;
+  bool use_graph = params->timing_mask == 0 && it_end - it0 > 1 + span;
   if (use_graph) {
     SolveStream &ss = solve_stream();
     if (ss.status == hipSuccess) {
@@ -745,9 +740,9 @@ int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, c
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int32_t r = S3TTV_OK;
-  int it = 0;
-  while (r == S3TTV_OK && it < max_iter) {
-    if (it >= 1 && use_graph && !exec && it + span <= max_iter) {
+  int it = it0;
+  while (r == S3TTV_OK && it < it_end) {
+    if (it >= 1 && use_graph && !exec && it + span <= it_end) {
       // capture once; if the stream cannot be captured, keep launching directly
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipGetLastError();
@@ -764,17 +759,17 @@ int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, c
       }
     }
     int next;
-    if (exec && it + span <= max_iter) {
+    if (exec && it + span <= it_end) {
       if (hipGraphLaunch(exec, st) != hipSuccess) r = S3TTV_EHIP;
       next = it + span;
     } else {
       // direct launches up to the next check point (or the end)
-      next = it == 0 ? 1 : (params->rel_tol > 0 ? it + check : max_iter);
-      if (next > max_iter) next = max_iter;
+      next = it == 0 ? 1 : (params->rel_tol > 0 ? it + check : it_end);
+      if (next > it_end) next = it_end;
       for (int j = it; j < next && r == S3TTV_OK; ++j) r = enqueue_iteration(pr, j, tm, st);
     }
     it = next;
-    if (r == S3TTV_OK && params->rel_tol > 0 && it < max_iter && it > 1) {
+    if (r == S3TTV_OK && params->rel_tol > 0 && it < it_end && it > 1) {
       int32_t done = 0;
       if (hipMemcpyAsync(&done, &pr.pl.sc->done, sizeof(done), hipMemcpyDeviceToHost, st) !=
               hipSuccess ||
@@ -801,7 +796,58 @@ int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, c
   CK(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return finish(pr, hs, ms, &tm, stats, st);
+  return finish(pr, hs, ms, &tm, stats, st, it0);
+}
+
+int32_t s3ttv_solve_from(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                         const float *u0, const float *s0, const float *t0, float *u, float *s,
+                         float *t, void *workspace, size_t workspace_bytes, void *stream,
+                         s3ttv_stats *stats) {
+  Problem pr;
+  const int32_t prep = prepare(pr, shape, params, v, u0, u, s, t, workspace, workspace_bytes, 0, 0);
+  if (prep != S3TTV_OK) return prep;
+  pr.s0 = s0;
+  pr.t0 = t0;
+  CK(configure_block_kernels());
+  hipStream_t st = (hipStream_t)stream;
+  Timer tm{params->timing_mask, st, {}};
+  event_pool().used = 0;
+  const int32_t ini = enqueue_init(pr, st);
+  if (ini != S3TTV_OK) return ini;
+  CK(launch_mark_state(pr.pl, state_sig(pr), st));
+  {
+    DevScalars hs0;
+    CK(hipMemcpyAsync(&hs0, pr.pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const int32_t chk = check_init(pr, hs0);
+    if (chk != S3TTV_OK) return chk;
+  }
+  return run_iterations(pr, params, 0, params->max_iter, st, tm, stats);
+}
+
+int32_t s3ttv_solve_continue(const s3ttv_shape *shape, const s3ttv_params *params, const float *v,
+                             float *u, float *s, float *t, void *workspace,
+                             size_t workspace_bytes, void *stream, s3ttv_stats *stats) {
+  Problem pr;
+  const int32_t prep =
+      prepare(pr, shape, params, v, nullptr, u, s, t, workspace, workspace_bytes, 0, 0);
+  if (prep != S3TTV_OK) return prep;
+  CK(configure_block_kernels());
+  hipStream_t st = (hipStream_t)stream;
+  Timer tm{params->timing_mask, st, {}};
+  event_pool().used = 0;
+  DevScalars hs0;
+  CK(hipMemcpyAsync(&hs0, pr.pl.sc, sizeof(hs0), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const StateSig want = state_sig(pr);
+  for (int k = 0; k < 8; ++k)
+    if (hs0.sig[k] != want.v[k]) return S3TTV_EINVAL;
+  if (hs0.nonfinite) return S3TTV_ENONFINITE;
+  if (hs0.iters < 1 || hs0.iters > INT32_MAX - params->max_iter) return S3TTV_EINVAL;
+  const int32_t chk = check_init(pr, hs0);
+  if (chk != S3TTV_OK) return chk;
+  CK(launch_resume_scalars(pr.pl, params->rel_tol, params->max_iter, st));
+  return run_iterations(pr, params, hs0.iters, hs0.iters + params->max_iter, st, tm, stats);
 }
 
 // ---------------------------------------------------------------- batched solve

@@ -701,6 +701,26 @@ __global__ void k_init_scalars(DevScalars *sc, double rel_tol, int max_iter) {
   }
 }
 
+__global__ void k_mark_state(DevScalars *sc, StateSig sig) {
+  if (threadIdx.x < 8 && blockIdx.x == 0) sc->sig[threadIdx.x] = sig.v[threadIdx.x];
+}
+
+__global__ void k_resume_scalars(DevScalars *sc, double rel_tol, int budget) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->done = 0;
+    sc->converged = 0;
+    sc->rel_tol = rel_tol;
+    sc->max_iter = sc->iters + budget;
+    sc->max_sweeps = 0;
+    sc->sweep_sum = 0;
+    sc->sweep_waves = 0;
+    sc->step_sum = 0;
+    sc->step_blocks = 0;
+    sc->fallback_blocks = 0;
+    sc->max_steps = 0;
+  }
+}
+
 __global__ void k_check_finite(const float *x, long long n, DevScalars *sc) {
   bool bad = false;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -812,6 +832,16 @@ hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_init_scalars(const Plan &pl, double rel_tol, int max_iter, hipStream_t st) {
   hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, pl.sc, rel_tol, max_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_state(const Plan &pl, const StateSig &sig, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_state, dim3(1), dim3(64), 0, st, pl.sc, sig);
+  return hipGetLastError();
+}
+
+hipError_t launch_resume_scalars(const Plan &pl, double rel_tol, int budget, hipStream_t st) {
+  hipLaunchKernelGGL(k_resume_scalars, dim3(1), dim3(64), 0, st, pl.sc, rel_tol, budget);
   return hipGetLastError();
 }
 

@@ -79,6 +79,15 @@ struct DevScalars {
   unsigned long long fallback_blocks;  // warm-iteration blocks handed to the per-lane Jacobi
   int32_t max_steps;              // largest rotation step count of one block
   int32_t zslot_overflow;         // some pixel has more than 4 overlap-add partial slots
+  // Signature of the iterate the workspace holds (a solve may be continued from it):
+  // sig[0] = kStateMagic once a single solve has initialised its state, then the shape
+  // (n1, n2, n3, k1, k2), the regulariser and the anchor tile (TA * 256 + TB).
+  int32_t sig[8];
+};
+
+constexpr int32_t kStateMagic = 0x53335456;
+struct StateSig {
+  int32_t v[8];
 };
 
 // l1 histograms: per ball, per level: counts (u32) and significand sums (u64).
@@ -132,6 +141,11 @@ hipError_t launch_identity16(float *V, long long nblk, hipStream_t st);
 hipError_t launch_fill_hash(float *p, long long n, float scale, uint32_t seed, hipStream_t st);
 hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st);
 hipError_t launch_init_scalars(const Plan &pl, double rel_tol, int max_iter, hipStream_t st);
+// Records the state signature (after the state has been initialised).
+hipError_t launch_mark_state(const Plan &pl, const StateSig &sig, hipStream_t st);
+// Continues from the iterate held in the workspace: clears the stop flags and the eigen-solve
+// statistics, sets the stop tolerance and a budget of `budget` more iterations.
+hipError_t launch_resume_scalars(const Plan &pl, double rel_tol, int budget, hipStream_t st);
 hipError_t launch_zero_bytes(void *p, size_t bytes, hipStream_t st);
 hipError_t launch_check_finite(const float *x, long long n, DevScalars *sc, hipStream_t st);
 // Primal step (Alg. 1 steps 2-4) from (u_cur, s, t_cur, y2, w, Z) into (u_new, xs, xt),

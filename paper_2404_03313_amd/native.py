@@ -22,7 +22,8 @@ KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", 
 N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 
-EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_solve_from", "s3ttv_strerror", "s3ttv_op_workspace_bytes",
+EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_solve_from", "s3ttv_solve_continue",
+           "s3ttv_strerror", "s3ttv_op_workspace_bytes",
            "s3ttv_op_grad", "s3ttv_op_grad_adj", "s3ttv_op_spectral_clip",
            "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_batch_workspace_bytes",
            "s3ttv_solve_batched", "s3ttv_cnn_param_count", "s3ttv_cnn_workspace_bytes",
@@ -88,6 +89,8 @@ def lib():
                                   vp, sz, vp, ctypes.POINTER(Stats)]
         L.s3ttv_solve_from.argtypes = [ctypes.POINTER(Shape), ctypes.POINTER(Params), vp, vp, vp,
                                        vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(Stats)]
+        L.s3ttv_solve_continue.argtypes = [ctypes.POINTER(Shape), ctypes.POINTER(Params), vp, vp,
+                                           vp, vp, vp, sz, vp, ctypes.POINTER(Stats)]
         L.s3ttv_strerror.argtypes = [ctypes.c_int32]
         L.s3ttv_strerror.restype = ctypes.c_char_p
         L.s3ttv_op_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
@@ -223,6 +226,24 @@ class Solver:
                                         _dev_ptr(t0, "t0"), _dev_ptr(u, "u"), _dev_ptr(s, "s"),
                                         _dev_ptr(t, "t"), *ws)
         _check(rc, name, allow=(OK, NOT_CONVERGED))
+        return u, s, t, _stats_dict(st, rc)
+
+    def resume(self, v, params: Params, out=None):
+        """s3ttv_solve_continue: params.max_iter more iterations from the iterate an earlier
+        solve (or resume) of this Solver left in its workspace (same v)."""
+        torch = _torch()
+        if tuple(v.shape) != self.dims:
+            raise ValueError(f"v has shape {tuple(v.shape)}, expected {self.dims}")
+        if out is None:
+            out = tuple(torch.empty_like(v) for _ in range(3))
+        u, s, t = out
+        st = Stats()
+        rc = lib().s3ttv_solve_continue(ctypes.byref(self.shape), ctypes.byref(params),
+                                        _dev_ptr(v, "v"), _dev_ptr(u, "u"), _dev_ptr(s, "s"),
+                                        _dev_ptr(t, "t"), ctypes.c_void_p(self.ws.data_ptr()),
+                                        ctypes.c_size_t(self.ws.numel()), _stream(),
+                                        ctypes.byref(st))
+        _check(rc, "s3ttv_solve_continue", allow=(OK, NOT_CONVERGED))
         return u, s, t, _stats_dict(st, rc)
 
 

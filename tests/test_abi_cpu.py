@@ -68,7 +68,15 @@ def test_dual_blocks_workspace_query(k, code):
 
 @pytest.mark.parametrize("shape,code", [((1, 8, 4, 1, 1), nt.EINVAL), ((8, 8, 1, 1, 1), nt.EINVAL),
                                         ((8, 8, 4, 9, 1), nt.EINVAL), ((8, 8, 4, 0, 2), nt.EINVAL),
-                                        ((12, 12, 4, 11, 10), nt.EUNSUPPORTED)])
+                                        ((12, 12, 4, 11, 10), nt.EUNSUPPORTED),
+                                        # 4 x 4 blocks: the 1 x 1 anchor tile's overlap-add
+                                        # accumulators hold 16 (2 Bp + 16) floats <= 152 KiB
+                                        # (Bp = N3 rounded up to 16): N3 <= 1200
+                                        ((8, 8, 1200, 4, 4), 0),
+                                        ((8, 8, 1201, 4, 4), nt.EUNSUPPORTED),
+                                        ((8, 8, 3000, 2, 2), 0),
+                                        # more rows: one workgroup per block, any band count
+                                        ((12, 12, 3000, 5, 4), 0)])
 def test_shape_validation(shape, code):
     sz = ctypes.c_size_t()
     sh = nt.Shape(*shape)
@@ -88,6 +96,27 @@ def test_param_validation_before_any_gpu_call(bad):
     rc = nt.lib().s3ttv_solve(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), dummy, None,
                               dummy, dummy, dummy, dummy, 1 << 30, None, None)
     assert rc == nt.EINVAL
+
+
+def test_continue_rejects_invalid_arguments_before_any_gpu_call():
+    """s3ttv_solve_continue validates shape, parameters and pointers like s3ttv_solve before it
+    reads the workspace's state."""
+    p = nt.make_params(1.0, 1.0, 1.0, 10)
+    dummy = ctypes.c_void_p(16)
+    L = nt.lib()
+    rc = L.s3ttv_solve_continue(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), None,
+                                None, None, None, None, 0, None, None)
+    assert rc == nt.EINVAL
+    bad = nt.make_params(1.0, 1.0, 1.0, 0)
+    rc = L.s3ttv_solve_continue(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(bad), dummy,
+                                dummy, dummy, dummy, dummy, 1 << 30, None, None)
+    assert rc == nt.EINVAL
+    rc = L.s3ttv_solve_continue(ctypes.byref(nt.Shape(12, 12, 4, 11, 10)), ctypes.byref(p), dummy,
+                                dummy, dummy, dummy, dummy, 1 << 30, None, None)
+    assert rc == nt.EUNSUPPORTED
+    rc = L.s3ttv_solve_continue(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), dummy,
+                                dummy, dummy, dummy, dummy, 16, None, None)
+    assert rc == nt.EWORKSPACE
 
 
 def test_null_pointers_rejected():

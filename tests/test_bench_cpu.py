@@ -44,3 +44,27 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_counter_figure_reported_while_source_unchanged(tmp_path, monkeypatch):
+    text = "__global__ void k() {}\n"
+    digest = hashlib.sha256(text.encode()).hexdigest()[:16]
+    (tmp_path / "profiles").mkdir()
+    src = tmp_path / "k.hip"
+    src.write_text(text)
+    (tmp_path / "profiles" / "sq_x.md").write_text(
+        f"mfma_busy_frac k_block_fused value=0.25 source=k.hip sha256_16={digest}\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_counter("mfma_busy_frac", "k_block_fused") == (
+        0.25, os.path.join("profiles", "sq_x.md"))
+    assert bench.measured_counter("mfma_busy_frac", "k_other") is None
+    src.write_text(text + "// changed\n")
+    assert bench.measured_counter("mfma_busy_frac", "k_block_fused") is None
+
+
+def test_block_pass_byte_counts():
+    # steps 9-10 read and write every dual block once: 16 K N3 bytes per block
+    assert bench.block_pass_algorithmic_bytes(256, 256, 128, 4, 4) == 16 * 16 * 128 * 65536
+    assert bench.block_pass_design_bytes(256, 256, 128, 4, 4) > bench.block_pass_algorithmic_bytes(
+        256, 256, 128, 4, 4)
+    assert bench.gram_flops(256, 256, 128, 4, 4) == 131072 * 65536

@@ -148,6 +148,23 @@ def test_solve_stop_rule_matches_oracle(device):
     assert abs(st["iters"] - r["stats"]["iters"]) <= 1
 
 
+def test_stop_rule_value_matches_separate_oracle_runs(device):
+    """The relative change the GPU reports after k iterations (the quantity of eq.
+    StopCri_simulated) equals ||u^(k) - u^(k-1)|| / ||u^(k-1)|| formed from two oracle runs of
+    k - 1 and k iterations."""
+    _say("solve stop-rule value")
+    cfg = synth.HSIConfig(12, 12, 8, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=13)
+    d = synth.make_hsi(cfg)
+    v = _t(d["v"], device)
+    for k in (3, 5, 9, 40):
+        st = nt.solve(v, 2, 2, max_iter=k, **d["radii"])[3]
+        prev = oracle.solve(d["v64"], 2, 2, max_iter=k - 1, **d["radii"])["u"]
+        cur = oracle.solve(d["v64"], 2, 2, max_iter=k, **d["radii"])["u"]
+        want = np.linalg.norm(cur - prev) / np.linalg.norm(prev)
+        _say("  k", k, "gpu", st["rel_change"], "from oracle runs", want)
+        assert st["rel_change"] == pytest.approx(want, rel=1e-4)
+
+
 def test_solve_deterministic(device):
     _say("solve determinism")
     d = synth.make_hsi(synth.WORKLOADS["c1"]["cfg"])
@@ -222,3 +239,69 @@ def test_graph_replay_matches_direct_launches(device, shape, k, reg):
             assert torch.equal(a, b) and torch.equal(a, c)
         assert g[3]["iters"] == g2[3]["iters"] == dl[3]["iters"]
         _say("  ", kw, "iterations", g[3]["iters"])
+
+
+@pytest.mark.parametrize("shape,k,reg", [((32, 32, 16), (3, 3), "s3ttv"), ((12, 10, 150), (2, 2), "s3ttv"),
+                                         ((12, 12, 8), (10, 10), "s3ttv"), ((20, 16, 12), (2, 2), "sstv"),
+                                         ((14, 13, 9), (3, 2), "stv")])
+def test_continue_equals_one_uninterrupted_solve(device, shape, k, reg):
+    """s3ttv_solve_continue: a solve of n1 iterations continued by n2 gives bitwise the solve of
+    n1 + n2 iterations (graph replays and direct launches, every block-pass route, an l1
+    variant); a continued stop rule fires at the iteration of the uninterrupted solve."""
+    import torch
+    _say("continue", shape, k, reg)
+    cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2,
+                          seed=91)
+    d = synth.make_hsi(cfg)
+    v = _t(d["v"], device)
+    sv = nt.Solver(*shape, *k, device=device)
+    ref = sv.solve(v, nt.make_params(max_iter=57, regularizer=reg, **d["radii"]))
+    ref = tuple(x.clone() for x in ref[:3])
+    for n1, timing in ((20, 0), (1, 0), (36, 1 << nt.K_FINAL)):
+        sv.solve(v, nt.make_params(max_iter=n1, regularizer=reg, **d["radii"]))
+        got = sv.resume(v, nt.make_params(max_iter=57 - n1, regularizer=reg, timing_mask=timing,
+                                          **d["radii"]))
+        assert got[3]["iters"] == 57 - n1
+        for a, b in zip(got[:3], ref):
+            assert torch.equal(a, b), (n1, timing)
+    # continued in three pieces
+    sv.solve(v, nt.make_params(max_iter=10, regularizer=reg, **d["radii"]))
+    sv.resume(v, nt.make_params(max_iter=30, regularizer=reg, **d["radii"]))
+    got = sv.resume(v, nt.make_params(max_iter=17, regularizer=reg, **d["radii"]))
+    for a, b in zip(got[:3], ref):
+        assert torch.equal(a, b)
+    # the stop rule in a continuation
+    one = sv.solve(v, nt.make_params(max_iter=5000, rel_tol=1e-3, regularizer=reg, **d["radii"]))
+    n_one = one[3]["iters"]
+    one = tuple(x.clone() for x in one[:3])
+    sv.solve(v, nt.make_params(max_iter=7, regularizer=reg, **d["radii"]))
+    got = sv.resume(v, nt.make_params(max_iter=5000, rel_tol=1e-3, regularizer=reg, **d["radii"]))
+    _say("  stop rule after", n_one, "iterations; continued", 7, "+", got[3]["iters"])
+    assert got[3]["converged"] and got[3]["iters"] == n_one - 7
+    for a, b in zip(got[:3], one):
+        assert torch.equal(a, b)
+
+
+def test_continue_rejects_a_workspace_without_that_state(device):
+    import torch
+    _say("continue errors")
+    d = synth.make_hsi(synth.HSIConfig(12, 12, 8, endmembers=3, cells=4, sigma=0.05, p_sp=0.05,
+                                       p_stripe=0.2, seed=13))
+    v = _t(d["v"], device)
+    sv = nt.Solver(12, 12, 8, 2, 2, device=device)
+    sv.ws.zero_()
+    with pytest.raises(nt.S3TTVError) as e:      # never solved
+        sv.resume(v, nt.make_params(max_iter=5, **d["radii"]))
+    assert e.value.code == nt.EINVAL
+    sv.solve(v, nt.make_params(max_iter=5, regularizer="sstv", **d["radii"]))
+    with pytest.raises(nt.S3TTVError) as e:      # another regulariser
+        sv.resume(v, nt.make_params(max_iter=5, **d["radii"]))
+    assert e.value.code == nt.EINVAL
+    sv.solve(v, nt.make_params(max_iter=5, **d["radii"]))
+    other = nt.Solver(12, 12, 8, 2, 2, device=device)
+    other.ws.copy_(sv.ws)
+    other.shape = nt.Shape(12, 12, 8, 1, 2)       # another block size on the same bytes
+    with pytest.raises(nt.S3TTVError) as e:
+        other.resume(v, nt.make_params(max_iter=5, **d["radii"]))
+    assert e.value.code == nt.EINVAL
+    torch.cuda.synchronize()
