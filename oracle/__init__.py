@@ -46,6 +46,8 @@ def lib():
             f.restype = None
         L.ora_blocks_extract.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, _dp]
         L.ora_blocks_scatter.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, _dp]
+        L.ora_blocks_extract3.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, _dp, _dp]
+        L.ora_blocks_scatter3.argtypes = [ctypes.c_int] * 5 + [_dp, _dp, _dp, _dp]
         L.ora_struct_tensor.argtypes = [ctypes.c_int] * 5 + [_dp, _dp]
         L.ora_struct_tensor_adj.argtypes = [ctypes.c_int] * 5 + [_dp, _dp]
         L.ora_svd_rows.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp]
@@ -138,6 +140,25 @@ def blocks_scatter(Y, shape, k1: int, k2: int):
     return zv, zh
 
 
+def blocks_extract3(gv, gh, gs, k1: int, k2: int) -> np.ndarray:
+    """P applied to a three-component field (gv, gh, gs), column 3b + comp: returns
+    (N1*N2, k1*k2, 3*N3)."""
+    gv, gh, gs = _f64(gv), _f64(gh), _f64(gs)
+    n1, n2, n3 = gv.shape
+    T = np.empty((n1 * n2, k1 * k2, 3 * n3))
+    lib().ora_blocks_extract3(n1, n2, n3, k1, k2, _p(gv), _p(gh), _p(gs), _p(T))
+    return T
+
+
+def blocks_scatter3(Y, shape, k1: int, k2: int):
+    """Adjoint of blocks_extract3; returns (zv, zh, zs)."""
+    Y = _f64(Y)
+    n1, n2, n3 = shape
+    z = [np.empty(shape) for _ in range(3)]
+    lib().ora_blocks_scatter3(n1, n2, n3, k1, k2, _p(Y), *(_p(x) for x in z))
+    return tuple(z)
+
+
 def struct_tensor(u, k1: int, k2: int) -> np.ndarray:
     """T_l = P_l D D_s u for all l (eq. rewrite_Lu): (N1*N2, k1*k2, 2*N3)."""
     u = _f64(u)
@@ -213,18 +234,21 @@ def s3ttv(u, k1: int, k2: int) -> float:
     return float(lib().ora_s3ttv(*u.shape, k1, k2, _p(u)))
 
 
-REGULARIZERS = {"s3ttv": 0, "stv": 1, "sstv": 2, "hsstv": 3}
+REGULARIZERS = {"s3ttv": 0, "stv": 1, "sstv": 2, "hsstv": 3, "ssst": 4}
+BLOCK_COMPONENTS = {"s3ttv": 2, "stv": 2, "ssst": 3}
 
 
 def default_gammas(k1: int, k2: int, regularizer: str = "s3ttv", omega: float = 0.05) -> dict:
     """Lemma-2 step sizes for the stacked operator. S3TTV: column sums 8K+1, 1, 3; row sums 4,
     2, 3. STV (blocks of D u): 4K+1 and block rows 2. SSTV (||D D_s u||_1): 9 and rows 4.
-    HSSTV (+ omega ||D u||_1): 9 + 4 omega; its second field steps with 1/(2 omega)."""
+    HSSTV (+ omega ||D u||_1): 9 + 4 omega; its second field steps with 1/(2 omega).
+    SSST (blocks of (D_v u, D_h u, D_s u)): 6K+1 and block rows 2."""
     K = k1 * k2
     g_u = {"s3ttv": 1.0 / (8 * K + 1), "stv": 1.0 / (4 * K + 1), "sstv": 1.0 / 9,
-           "hsstv": 1.0 / (9 + 4 * omega)}[regularizer]
+           "hsstv": 1.0 / (9 + 4 * omega), "ssst": 1.0 / (6 * K + 1)}[regularizer]
     return dict(gamma_u=g_u, gamma_s=1.0, gamma_t=1.0 / 3,
-                gamma_Y=0.5 if regularizer == "stv" else 0.25, gamma_y2=0.5, gamma_y3=1.0 / 3)
+                gamma_Y=0.5 if regularizer in ("stv", "ssst") else 0.25, gamma_y2=0.5,
+                gamma_y3=1.0 / 3)
 
 
 def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: int,
@@ -234,8 +258,9 @@ def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: 
     """Alg. 1 in float64. Returns dict(u, s, t, stats[, trace][, Y or Z, y2, y3]).
     u0, s0, t0: optional initial values (zero when None); the duals start at zero.
     regularizer: "s3ttv" (Prob. (18)), or the compared P-PDS-applicable terms "stv",
-    "sstv", "hsstv" (weight omega) in its place (Sec. IV-A). Z (SSTV, HSSTV): the dual
-    fields (z1v, z1h, z2v, z2h) stacked, shape (4, N1, N2, N3)."""
+    "sstv", "hsstv" (weight omega), "ssst" in its place (Sec. IV-A). Y (S3TTV, STV, SSST): the
+    block duals (N1*N2, K, c*N3), c = 2 (3 for SSST, column 3b + comp). Z (SSTV, HSSTV): the
+    dual fields (z1v, z1h, z2v, z2h) stacked, shape (4, N1, N2, N3)."""
     reg = REGULARIZERS[regularizer]
     v = _f64(v)
     n1, n2, n3 = v.shape
@@ -250,8 +275,10 @@ def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: 
     t = np.empty_like(v)
     st = np.zeros(8)
     tr = np.zeros(max_iter) if trace else None
-    Y = np.empty((n1 * n2, k1 * k2, 2 * n3)) if duals and reg <= 1 else None
-    Z = np.empty((4,) + v.shape) if duals and reg >= 2 else None
+    blk = regularizer in BLOCK_COMPONENTS
+    Y = (np.empty((n1 * n2, k1 * k2, BLOCK_COMPONENTS[regularizer] * n3)) if duals and blk
+         else None)
+    Z = np.empty((4,) + v.shape) if duals and not blk else None
     y2 = np.empty_like(v) if duals else None
     y3 = np.empty_like(v) if duals else None
     u0a = _f64(u0) if u0 is not None else None
@@ -269,5 +296,5 @@ def solve(v, k1: int, k2: int, eps: float, alpha: float, beta: float, max_iter: 
         out["trace"] = tr[:out["stats"]["iters"]]
     if duals:
         out.update(y2=y2, y3=y3)
-        out.update(Y=Y) if reg <= 1 else out.update(Z=Z)
+        out.update(Y=Y) if blk else out.update(Z=Z)
     return out

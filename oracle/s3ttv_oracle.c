@@ -152,6 +152,52 @@ void ora_blocks_scatter(int n1, int n2, int n3, int k1, int k2, const double *Y,
       }
 }
 
+/* Three-component blocks (the compared SSST regulariser): T[l][r][3b+comp] =
+   g_comp((p+a)%N1, (q+c)%N2, b) with g_0 = gv, g_1 = gh, g_2 = gs; T has L*K*3*N3 entries. */
+void ora_blocks_extract3(int n1, int n2, int n3, int k1, int k2, const double *gv,
+                         const double *gh, const double *gs, double *T) {
+  const int K = k1 * k2;
+  const size_t C = 3 * (size_t)n3;
+#pragma omp parallel for schedule(static)
+  for (int p = 0; p < n1; ++p)
+    for (int q = 0; q < n2; ++q) {
+      double *Tl = T + ((size_t)p * n2 + q) * K * C;
+      for (int a = 0; a < k1; ++a)
+        for (int c = 0; c < k2; ++c) {
+          const int i = (p + a) % n1, j = (q + c) % n2, r = a * k2 + c;
+          for (int b = 0; b < n3; ++b) {
+            Tl[r * C + 3 * b] = gv[X3(i, j, b)];
+            Tl[r * C + 3 * b + 1] = gh[X3(i, j, b)];
+            Tl[r * C + 3 * b + 2] = gs[X3(i, j, b)];
+          }
+        }
+    }
+}
+
+/* Its adjoint: zv, zh, zs = sum_l P_l^T Y_l for three-component blocks. */
+void ora_blocks_scatter3(int n1, int n2, int n3, int k1, int k2, const double *Y, double *zv,
+                         double *zh, double *zs) {
+  const int K = k1 * k2;
+  const size_t C = 3 * (size_t)n3;
+  const size_t N = (size_t)n1 * n2 * n3;
+  memset(zv, 0, N * sizeof(double));
+  memset(zh, 0, N * sizeof(double));
+  memset(zs, 0, N * sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int b = 0; b < n3; ++b)
+    for (int p = 0; p < n1; ++p)
+      for (int q = 0; q < n2; ++q) {
+        const double *Yl = Y + ((size_t)p * n2 + q) * K * C;
+        for (int a = 0; a < k1; ++a)
+          for (int c = 0; c < k2; ++c) {
+            const int i = (p + a) % n1, j = (q + c) % n2, r = a * k2 + c;
+            zv[X3(i, j, b)] += Yl[r * C + 3 * b];
+            zh[X3(i, j, b)] += Yl[r * C + 3 * b + 1];
+            zs[X3(i, j, b)] += Yl[r * C + 3 * b + 2];
+          }
+      }
+}
+
 /* Composite forward operator of eq. rewrite_Lu: T_l = P_l D D_s u for every l. */
 void ora_struct_tensor(int n1, int n2, int n3, int k1, int k2, const double *u, double *T) {
   const size_t N = (size_t)n1 * n2 * n3;
@@ -394,8 +440,10 @@ double ora_s3ttv(int n1, int n2, int n3, int k1, int k2, const double *u) {
      0 S3TTV: sum_l ||P_l D D_s u||_*          (dual: blocks Y_l, step 10 = spectral clip)
      1 STV:   sum_l ||P_l D u||_*              (blocks of first-order spatial differences)
      2 SSTV:  ||D D_s u||_1                    (dual: field Z, step = clip to [-1, 1])
-     3 HSSTV: ||D D_s u||_1 + omega ||D u||_1  (two fields, the second with step 1/(2 omega)) */
-enum { REG_S3TTV = 0, REG_STV = 1, REG_SSTV = 2, REG_HSSTV = 3 };
+     3 HSSTV: ||D D_s u||_1 + omega ||D u||_1  (two fields, the second with step 1/(2 omega))
+     4 SSST:  sum_l ||P_l [D_v u, D_h u, D_s u]||_*  (blocks of first-order spatial and
+              spectral differences, three columns per band) */
+enum { REG_S3TTV = 0, REG_STV = 1, REG_SSTV = 2, REG_HSSTV = 3, REG_SSST = 4 };
 
 /* gv, gh = D_v x, D_h x, after D_s when spectral != 0. tmp: N scratch doubles. */
 static void grad_pair(int n1, int n2, int n3, int spectral, const double *x, double *gv,
@@ -424,8 +472,9 @@ static void grad_pair_adj(int n1, int n2, int n3, int spectral, const double *zv
         [5] gamma_u [6] gamma_s [7] gamma_t [8] gamma_Y [9] gamma_y2 [10] gamma_y3 [11] rel_tol
         [12] regulariser (REG_*) [13] omega (HSSTV weight, > 0 for REG_HSSTV)
    Step sizes that are all zero select the Lemma-2 defaults of the regulariser's stacked
-   operator: gamma_u = 1/(8K+1) (S3TTV), 1/(4K+1) (STV), 1/9 (SSTV), 1/(9 + 4 omega) (HSSTV);
-   gamma_Y (the step of the regulariser's dual) = 1/4, except 1/2 for STV; gamma_s = 1,
+   operator: gamma_u = 1/(8K+1) (S3TTV), 1/(4K+1) (STV), 1/9 (SSTV), 1/(9 + 4 omega) (HSSTV),
+   1/(6K+1) (SSST); gamma_Y (the step of the regulariser's dual) = 1/4, except 1/2 for STV and
+   SSST; gamma_s = 1,
    gamma_t = 1/3, gamma_y2 = 1/2, gamma_y3 = 1/3. The HSSTV second field always steps with
    1/(2 omega).
    Initial values (Alg. 1 leaves them free): u0, s0, t0 (nullable: zero); all duals start at
@@ -435,7 +484,7 @@ static void grad_pair_adj(int n1, int n2, int n3, int spectral, const double *zv
         [3] ||D_v t|| [4] ||u+s+t-v|| - eps [5] ||s||_1 - alpha [6] ||t||_1 - beta
         [7] worst SVD sweep count (-1 if some block did not converge).
    trace (nullable, max_iter doubles): relative change after each iteration.
-   Y_out (S3TTV, STV), z_out (SSTV, HSSTV: 4N doubles z1v, z1h, z2v, z2h), y2_out, y3_out
+   Y_out (S3TTV, STV, SSST), z_out (SSTV, HSSTV: 4N doubles z1v, z1h, z2v, z2h), y2_out, y3_out
    (nullable): final dual variables (Y in the T layout).
    Returns 0, or -1 for invalid arguments. */
 int ora_solve(const int *dims, const double *prm, int max_iter, const double *v, const double *u0,
@@ -450,19 +499,20 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   const double tol = prm[11];
   const int reg = (int)prm[12];
   const double omega = prm[13];
-  if (reg < REG_S3TTV || reg > REG_HSSTV) return -1;
+  if (reg < REG_S3TTV || reg > REG_SSST) return -1;
   if (reg == REG_HSSTV && !(omega > 0)) return -1;
-  const int blocks = reg == REG_S3TTV || reg == REG_STV;
-  const int spectral = reg != REG_STV;
-  const int K = k1 * k2, C = 2 * n3;
+  const int blocks = reg == REG_S3TTV || reg == REG_STV || reg == REG_SSST;
+  const int spectral = reg != REG_STV && reg != REG_SSST;
+  const int K = k1 * k2, C = (reg == REG_SSST ? 3 : 2) * n3;
   if (g_u == 0 && g_s == 0 && g_t == 0 && g_Y == 0 && g_y2 == 0 && g_y3 == 0) {
     g_u = reg == REG_S3TTV ? 1.0 / (8.0 * K + 1.0)
           : reg == REG_STV ? 1.0 / (4.0 * K + 1.0)
+          : reg == REG_SSST ? 1.0 / (6.0 * K + 1.0)
           : reg == REG_SSTV ? 1.0 / 9.0
                             : 1.0 / (9.0 + 4.0 * omega);
     g_s = 1.0;
     g_t = 1.0 / 3.0;
-    g_Y = reg == REG_STV ? 0.5 : 0.25;
+    g_Y = (reg == REG_STV || reg == REG_SSST) ? 0.5 : 0.25;
     g_y2 = 0.5;
     g_y3 = 1.0 / 3.0;
   }
@@ -487,6 +537,7 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   double *gh = (double *)malloc(N * sizeof(double));
   double *s1 = (double *)malloc(N * sizeof(double));
   double *s2 = (double *)malloc(N * sizeof(double));
+  double *gs = reg == REG_SSST ? (double *)malloc(N * sizeof(double)) : NULL;
 
   for (size_t e = 0; e < N; ++e) {
     u[e] = u0 ? u0[e] : 0.0;
@@ -503,6 +554,12 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
     } else if (reg == REG_STV) {
       ora_blocks_scatter(n1, n2, n3, k1, k2, Y, gv, gh);
       grad_pair_adj(n1, n2, n3, 0, gv, gh, w, s1, s2);
+    } else if (reg == REG_SSST) {
+      /* w = D_v^T zv + D_h^T zh + D_s^T zs */
+      ora_blocks_scatter3(n1, n2, n3, k1, k2, Y, gv, gh, gs);
+      grad_pair_adj(n1, n2, n3, 0, gv, gh, w, s1, s2);
+      ora_ds_t(n1, n2, n3, gs, s1);
+      for (size_t e = 0; e < N; ++e) w[e] += s1[e];
     } else {
       grad_pair_adj(n1, n2, n3, 1, Z, Z + N, w, s1, s2);
       if (reg == REG_HSSTV) {
@@ -526,7 +583,12 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
        nuclear norms, a clip of each entry to [-1, 1] for the l1 norms. */
     if (blocks) {
       grad_pair(n1, n2, n3, spectral, up, gv, gh, s1);
-      ora_blocks_extract(n1, n2, n3, k1, k2, gv, gh, T);
+      if (reg == REG_SSST) {
+        ora_ds(n1, n2, n3, up, gs);
+        ora_blocks_extract3(n1, n2, n3, k1, k2, gv, gh, gs, T);
+      } else {
+        ora_blocks_extract(n1, n2, n3, k1, k2, gv, gh, T);
+      }
       int sweeps_max = 0, failed = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(max : sweeps_max) reduction(| : failed)
       for (size_t l = 0; l < L; ++l) {
@@ -619,5 +681,6 @@ int ora_solve(const int *dims, const double *prm, int max_iter, const double *v,
   free(gh);
   free(s1);
   free(s2);
+  free(gs);
   return 0;
 }

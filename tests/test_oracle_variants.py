@@ -3,6 +3,8 @@ the terms of the compared P-PDS-applicable methods in place of S3TTV in Prob. (1
   STV   sum_l ||P_l D u||_*          (blocks of first-order spatial differences)
   SSTV  ||D D_s u||_1
   HSSTV ||D D_s u||_1 + omega ||D u||_1
+  SSST  sum_l ||P_l [D_v u, D_h u, D_s u]||_*   (blocks of first-order spatial and spectral
+        differences, three columns per band)
 Each is pinned by Lemma 2 on the dense stacked operator (the default steps are its reciprocal
 column / row sums and satisfy the condition of Thm. 1), by convex duality (the primal-dual
 gap closes at the P-PDS limit, with LAPACK singular values for the nuclear norms), by shift
@@ -28,12 +30,15 @@ def _reg_ops(reg, shape, k1, k2):
     dd = lambda u: np.concatenate([oracle.dv(u).ravel(), oracle.dh(u).ravel()])
     if reg == "stv":
         return [lambda u: oracle.blocks_extract(oracle.dv(u), oracle.dh(u), k1, k2).ravel()]
+    if reg == "ssst":
+        return [lambda u: oracle.blocks_extract3(oracle.dv(u), oracle.dh(u), oracle.ds(u), k1,
+                                                 k2).ravel()]
     if reg == "sstv":
         return [dvds]
     return [dvds, lambda u: OMEGA * dd(u)]
 
 
-@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv"])
+@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv", "ssst"])
 def test_lemma2_steps_of_each_variant(reg):
     shape, (k1, k2) = (3, 4, 3), (2, 2)
     n = int(np.prod(shape))
@@ -67,6 +72,13 @@ def test_lemma2_steps_of_each_variant(reg):
 
 def _primal_and_adjoint(reg, r, shape, k1, k2):
     u = r["u"]
+    if reg == "ssst":
+        T = oracle.blocks_extract3(oracle.dv(u), oracle.dh(u), oracle.ds(u), k1, k2)
+        primal = np.linalg.svd(T, compute_uv=False).sum()
+        Y = r["Y"]
+        assert np.linalg.norm(Y, 2, axis=(1, 2)).max() <= 1 + 1e-12
+        zv, zh, zs = oracle.blocks_scatter3(Y, shape, k1, k2)
+        return primal, oracle.dv_t(zv) + oracle.dh_t(zh) + oracle.ds_t(zs)
     if reg == "stv":
         T = oracle.blocks_extract(oracle.dv(u), oracle.dh(u), k1, k2)
         primal = np.linalg.svd(T, compute_uv=False).sum()
@@ -85,7 +97,7 @@ def _primal_and_adjoint(reg, r, shape, k1, k2):
     return primal, adj
 
 
-@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv"])
+@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv", "ssst"])
 def test_variant_duality_gap_closes(reg):
     """Weak duality for the variant of Prob. (19): the regulariser value at u is at least the
     dual value at any dual-feasible point, and both meet at the P-PDS limit (Thm. 1)."""
@@ -111,7 +123,7 @@ def test_variant_duality_gap_closes(reg):
     assert res_dv < 1e-4 and abs(res_fid) < 1e-4
 
 
-@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv"])
+@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv", "ssst"])
 def test_variant_shift_equivariance(reg):
     d = _tiny(seed=3, shape=(8, 8, 6))
     kw = dict(k1=2, k2=3, max_iter=15, regularizer=reg, omega=OMEGA, **d["radii"])
@@ -121,6 +133,36 @@ def test_variant_shift_equivariance(reg):
         r = oracle.solve(np.ascontiguousarray(tr(d["v64"])), **kw)
         for key in ("u", "s", "t"):
             np.testing.assert_allclose(r[key], tr(base[key]), atol=1e-11)
+
+
+def test_three_component_blocks_geometry():
+    """P for three components: a unit impulse of component c at pixel (i, j), band b appears in
+    exactly the K windows anchored at (i - a, j - c'), in row a k2 + c' and column 3b + c; the
+    scatter is its adjoint; a field (0, 0, g(b)) constant over the image gives blocks of K equal
+    rows, each of spectral norm sqrt(K) ||g||."""
+    shape, (k1, k2) = (5, 4, 3), (2, 3)
+    n1, n2, n3 = shape
+    K = k1 * k2
+    for comp in range(3):
+        f = [np.zeros(shape) for _ in range(3)]
+        f[comp][3, 1, 2] = 1.0
+        T = oracle.blocks_extract3(*f, k1, k2)
+        hits = np.argwhere(T != 0)
+        assert len(hits) == K
+        for l, r, c in hits:
+            p, q = divmod(l, n2)
+            a, cc = divmod(r, k2)
+            assert ((p + a) % n1, (q + cc) % n2) == (3, 1) and c == 3 * 2 + comp
+    rng = np.random.default_rng(7)
+    f = [rng.normal(size=shape) for _ in range(3)]
+    Y = rng.normal(size=(n1 * n2, K, 3 * n3))
+    lhs = np.vdot(oracle.blocks_extract3(*f, k1, k2), Y)
+    rhs = sum(np.vdot(a, b) for a, b in zip(f, oracle.blocks_scatter3(Y, shape, k1, k2)))
+    assert abs(lhs - rhs) < 1e-10
+    g = rng.normal(size=n3)
+    T = oracle.blocks_extract3(np.zeros(shape), np.zeros(shape), np.broadcast_to(g, shape), k1, k2)
+    np.testing.assert_allclose(np.linalg.norm(T, 2, axis=(1, 2)), np.sqrt(K) * np.linalg.norm(g),
+                               rtol=1e-13)
 
 
 def test_hsstv_tends_to_sstv():
