@@ -94,11 +94,14 @@ typedef struct {
  *  regularizer: the term minimised in place of S3TTV on the same P-PDS skeleton (Sec. IV-A
  *    compares methods this way): S3TTV_REG_S3TTV (default, Prob. (18)),
  *    S3TTV_REG_STV (sum_l ||P_l D u||_*, blocks of first-order differences),
- *    S3TTV_REG_SSTV (||D D_s u||_1) or S3TTV_REG_HSSTV (||D D_s u||_1 + omega ||D u||_1).
- *    For the l1 terms the dual of the regulariser is a field clipped to [-1, 1] each
- *    iteration (gamma_Y is its step; the HSSTV second field steps with 1/(2 omega)) and no
- *    block pass runs. Default steps (all gammas 0), by Lemma 2: gamma_u = 1/(8K+1), 1/(4K+1),
- *    1/9, 1/(9 + 4 omega); gamma_Y = 1/4, 1/2 (STV), 1/4, 1/4; the other four as above.
+ *    S3TTV_REG_SSTV (||D D_s u||_1), S3TTV_REG_HSSTV (||D D_s u||_1 + omega ||D u||_1) or
+ *    S3TTV_REG_SSST (sum_l ||P_l [D_v u, D_h u, D_s u]||_*, blocks of first-order spatial and
+ *    spectral differences: 3 N3 columns). For the l1 terms the dual of the regulariser is a
+ *    field clipped to [-1, 1] each iteration (gamma_Y is its step; the HSSTV second field
+ *    steps with 1/(2 omega)) and no block pass runs. Default steps (all gammas 0), by Lemma 2:
+ *    gamma_u = 1/(8K+1), 1/(4K+1), 1/9, 1/(9 + 4 omega), 1/(6K+1); gamma_Y = 1/4, 1/2 (STV),
+ *    1/4, 1/4, 1/2 (SSST); the other four as above. The workspace depends on the regulariser
+ *    (s3ttv_workspace_bytes takes it from params; null params mean S3TTV).
  *  omega: HSSTV weight; 0 selects 0.05 (the value of the paper's comparison); finite, >= 0. */
 typedef struct {
   double eps, alpha, beta;
@@ -115,7 +118,13 @@ typedef struct {
 } s3ttv_params;
 
 enum { S3TTV_GRAM_FP32 = 0, S3TTV_GRAM_BF16 = 1, S3TTV_GRAM_FP16 = 2 };
-enum { S3TTV_REG_S3TTV = 0, S3TTV_REG_STV = 1, S3TTV_REG_SSTV = 2, S3TTV_REG_HSSTV = 3 };
+enum {
+  S3TTV_REG_S3TTV = 0,
+  S3TTV_REG_STV = 1,
+  S3TTV_REG_SSTV = 2,
+  S3TTV_REG_HSSTV = 3,
+  S3TTV_REG_SSST = 4
+};
 
 /* Kernel classes for timing_mask / s3ttv_stats.kernel_ms. */
 enum {

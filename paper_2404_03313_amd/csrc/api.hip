@@ -56,19 +56,30 @@ bool valid_shape(const s3ttv_shape *sh) {
   return true;
 }
 
-int32_t supported_shape(const s3ttv_shape *sh) {
+// Bands padded to whole column tiles: 16 per component, and for three components a multiple
+// of 32, so that every block has an even number of 16-column tiles (pairs of tiles per LDS
+// round trip in the fused pass) and a multiple of 32 columns (the large-block chunks).
+int padded_bands(int n3, int reg) {
+  const int q = block_comps(reg) == 3 ? 32 : 16;
+  return (n3 + q - 1) / q * q;
+}
+
+int32_t supported_shape(const s3ttv_shape *sh, int reg) {
   if (sh->k1 * sh->k2 > kBigMax) return S3TTV_EUNSUPPORTED;
   const long long N = (long long)sh->n1 * sh->n2 * sh->n3;
   if (N >= (1ll << 31)) return S3TTV_EUNSUPPORTED;
   if (sh->k1 * sh->k2 <= kRows) {
     // the smallest anchor tile (1 x 1) must hold its overlap-add accumulators in LDS:
-    // k1 k2 pixels of 2 Bp + 16 floats (N3 up to 1200 for 4 x 4 blocks)
-    const size_t Bp = (size_t)(sh->n3 + 15) / 16 * 16;
-    if ((size_t)sh->k1 * sh->k2 * (2 * Bp + 16) * sizeof(float) > kMaxLds)
+    // k1 k2 pixels of comps * Bp + 16 floats (N3 up to 1200 for 4 x 4 blocks of S3TTV)
+    const size_t ncol = (size_t)block_comps(reg) * padded_bands(sh->n3, reg);
+    if ((size_t)sh->k1 * sh->k2 * (ncol + 16) * sizeof(float) > kMaxLds)
       return S3TTV_EUNSUPPORTED;
   }
   return S3TTV_OK;
 }
+
+// Regulariser of a call's parameters (null parameters: S3TTV).
+int reg_of(const s3ttv_params *pr) { return pr ? pr->regularizer : S3TTV_REG_S3TTV; }
 
 // Anchor-tile candidates (largest first). The arithmetic of a solve does not depend on the
 // tile (the overlap-add is exact fixed point), only its speed does.
@@ -102,7 +113,8 @@ void choose_tiles(Plan &pl, int forceTA, int forceTB) {
 }
 
 // Geometry + carve. base == nullptr -> size only. forceTA/TB > 0 fix the anchor tile.
-void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int forceTA = 0, int forceTB = 0) {
+void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int reg, int forceTA = 0,
+               int forceTB = 0) {
   memset(&pl, 0, sizeof(pl));
   pl.n1 = sh->n1;
   pl.n2 = sh->n2;
@@ -110,8 +122,9 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int forceTA = 0, int
   pl.k1 = sh->k1;
   pl.k2 = sh->k2;
   pl.K = sh->k1 * sh->k2;
-  pl.Bp = (sh->n3 + 15) / 16 * 16;
-  pl.ncol = 2 * pl.Bp;
+  pl.reg = reg;
+  pl.Bp = padded_bands(sh->n3, reg);
+  pl.ncol = block_comps(reg) * pl.Bp;
   pl.ntile = pl.ncol / 16;
   pl.P = (long long)sh->n1 * sh->n2;
   pl.N = pl.P * sh->n3;
@@ -216,11 +229,12 @@ bool resolve_gammas(const s3ttv_shape *sh, const s3ttv_params *pr, Gammas &g) {
       case S3TTV_REG_STV: g.u = 1.0 / (4.0 * K + 1.0); break;
       case S3TTV_REG_SSTV: g.u = 1.0 / 9.0; break;
       case S3TTV_REG_HSSTV: g.u = 1.0 / (9.0 + 4.0 * om); break;
+      case S3TTV_REG_SSST: g.u = 1.0 / (6.0 * K + 1.0); break;
       default: g.u = 1.0 / (8.0 * K + 1.0); break;
     }
     g.s = 1.0;
     g.t = 1.0 / 3.0;
-    g.Y = pr->regularizer == S3TTV_REG_STV ? 0.5 : 0.25;
+    g.Y = (pr->regularizer == S3TTV_REG_STV || pr->regularizer == S3TTV_REG_SSST) ? 0.5 : 0.25;
     g.y2 = 0.5;
     g.y3 = 1.0 / 3.0;
   } else {
@@ -242,7 +256,7 @@ bool valid_params(const s3ttv_params *pr) {
   if (!(pr->rel_tol >= 0 && isfinite(pr->rel_tol))) return false;
   if (pr->eig_max_steps > 255) return false;
   if (pr->gram_precision < S3TTV_GRAM_FP32 || pr->gram_precision > S3TTV_GRAM_FP16) return false;
-  if (pr->regularizer < S3TTV_REG_S3TTV || pr->regularizer > S3TTV_REG_HSSTV) return false;
+  if (pr->regularizer < S3TTV_REG_S3TTV || pr->regularizer > S3TTV_REG_SSST) return false;
   if (!(pr->omega >= 0 && isfinite(pr->omega))) return false;
   return true;
 }
@@ -322,14 +336,14 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
                 size_t ws_bytes, int forceTA, int forceTB) {
   if (!valid_shape(shape) || !valid_params(params) || !v || !u || !s || !t || !ws)
     return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
+  const int32_t sup = supported_shape(shape, params->regularizer);
   if (sup != S3TTV_OK) return sup;
   Gammas gm;
   if (!resolve_gammas(shape, params, gm)) return S3TTV_EINVAL;
   Plan &pl = pr.pl;
-  make_plan(pl, shape, nullptr, forceTA, forceTB);
+  make_plan(pl, shape, nullptr, params->regularizer, forceTA, forceTB);
   if (ws_bytes < pl.bytes) return S3TTV_EWORKSPACE;
-  make_plan(pl, shape, (char *)ws, forceTA, forceTB);
+  make_plan(pl, shape, (char *)ws, params->regularizer, forceTA, forceTB);
   pl.g_u = (float)gm.u;
   pl.g_s = (float)gm.s;
   pl.g_t = (float)gm.t;
@@ -433,7 +447,7 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
   // dual steps (3-7 thresholds, 12, 13) together with the gradient field of u' (steps 5, 9):
   // neither depends on the block pass
   TIMED(S3TTV_K_DUAL, launch_dual_grad(pl, pl.u[c], pl.u[n], pl.t[c], pl.t[n], pr.v, st));
-  if (pl.reg >= kRegSSTV) {
+  if (l1_reg(pl.reg)) {
     // l1 regulariser: its dual step ran inside the dual sweep; there are no blocks
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));
     return S3TTV_OK;
@@ -525,11 +539,11 @@ int32_t finish(const Problem &pr, const DevScalars &hs, float ms, Timer *tm, s3t
 namespace {
 
 // Workspace bytes of one problem for any anchor tile the tuner may choose.
-size_t plan_bytes_any_tile(const s3ttv_shape *sh) {
+size_t plan_bytes_any_tile(const s3ttv_shape *sh, int reg) {
   size_t m = 0;
   for (auto &c : kTileCand) {
     Plan pl;
-    make_plan(pl, sh, nullptr, c[0], c[1]);
+    make_plan(pl, sh, nullptr, reg, c[0], c[1]);
     if (pl.bytes > m) m = pl.bytes;
   }
   return m;
@@ -565,10 +579,11 @@ BatchStreams &batch_streams() {
 // problem's own workspace with synthetic blocks (the arithmetic does not depend on the tile,
 // so the choice only changes speed). Results are cached per shape for the process.
 struct TileKey {
-  int n1, n2, n3, k1, k2, prec;
+  int n1, n2, n3, k1, k2, prec, reg;
   bool operator<(const TileKey &o) const {
-    const int a[6] = {n1, n2, n3, k1, k2, prec}, b[6] = {o.n1, o.n2, o.n3, o.k1, o.k2, o.prec};
-    for (int i = 0; i < 6; ++i)
+    const int a[7] = {n1, n2, n3, k1, k2, prec, reg};
+    const int b[7] = {o.n1, o.n2, o.n3, o.k1, o.k2, o.prec, o.reg};
+    for (int i = 0; i < 7; ++i)
       if (a[i] != b[i]) return a[i] < b[i];
     return false;
   }
@@ -586,7 +601,8 @@ std::mutex &tile_mutex() {
 
 int32_t tune_tiles(const s3ttv_shape *shape, const s3ttv_params *params, void *ws, size_t ws_bytes,
                    hipStream_t st, int &TA, int &TB) {
-  const TileKey key{shape->n1, shape->n2, shape->n3, shape->k1, shape->k2, params->gram_precision};
+  const TileKey key{shape->n1, shape->n2, shape->n3, shape->k1, shape->k2, params->gram_precision,
+                     params->regularizer};
   {
     std::lock_guard<std::mutex> lk(tile_mutex());
     auto it = tile_cache().find(key);
@@ -669,12 +685,13 @@ const char *s3ttv_strerror(int32_t code) {
 }
 
 int32_t s3ttv_workspace_bytes(const s3ttv_shape *shape, const s3ttv_params *params, size_t *bytes) {
-  (void)params;
   if (!bytes || !valid_shape(shape)) return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
+  const int reg = reg_of(params);
+  if (reg < S3TTV_REG_S3TTV || reg > S3TTV_REG_SSST) return S3TTV_EINVAL;
+  const int32_t sup = supported_shape(shape, reg);
   if (sup != S3TTV_OK) return sup;
   Plan pl;
-  make_plan(pl, shape, nullptr);
+  make_plan(pl, shape, nullptr, reg);
   *bytes = pl.bytes;
   return S3TTV_OK;
 }
@@ -854,14 +871,15 @@ int32_t s3ttv_solve_continue(const s3ttv_shape *shape, const s3ttv_params *param
 
 int32_t s3ttv_batch_workspace_bytes(int32_t n, const s3ttv_shape *shapes,
                                     const s3ttv_params *params, size_t *bytes) {
-  (void)params;
   if (n < 1 || !shapes || !bytes) return S3TTV_EINVAL;
   size_t total = batch_header_bytes(n);
   for (int i = 0; i < n; ++i) {
     if (!valid_shape(&shapes[i])) return S3TTV_EINVAL;
-    const int32_t sup = supported_shape(&shapes[i]);
+    const int reg = reg_of(params ? &params[i] : nullptr);
+    if (reg < S3TTV_REG_S3TTV || reg > S3TTV_REG_SSST) return S3TTV_EINVAL;
+    const int32_t sup = supported_shape(&shapes[i], reg);
     if (sup != S3TTV_OK) return sup;
-    total += align_up(plan_bytes_any_tile(&shapes[i]));
+    total += align_up(plan_bytes_any_tile(&shapes[i], reg));
   }
   *bytes = total;
   return S3TTV_OK;
@@ -893,10 +911,10 @@ int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_pa
   std::vector<Problem> prs(n);
   std::vector<int32_t> code(n, S3TTV_OK);
   for (int i = 0; i < n; ++i) {
-    const size_t region = align_up(plan_bytes_any_tile(&shapes[i]));
+    const size_t region = align_up(plan_bytes_any_tile(&shapes[i], params[i].regularizer));
     int TA = 0, TB = 0;
     // the l1 regularisers and blocks of more than 16 rows have no anchor tiles to tune
-    int32_t r = params[i].regularizer >= S3TTV_REG_SSTV ||
+    int32_t r = l1_reg(params[i].regularizer) ||
                         shapes[i].k1 * shapes[i].k2 > kRows
                     ? S3TTV_OK
                     : tune_tiles(&shapes[i], &params[i], base + off, region, st, TA, TB);
@@ -1075,9 +1093,9 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
     case S3TTV_OP_GRAD_ADJ:
     case S3TTV_OP_DUAL_BLOCKS: {
       if (!valid_shape(shape)) return S3TTV_EINVAL;
-      const int32_t sup = supported_shape(shape);
+      const int32_t sup = supported_shape(shape, kRegS3TTV);
       if (sup != S3TTV_OK) return sup;
-      make_plan(pl, shape, nullptr);
+      make_plan(pl, shape, nullptr, kRegS3TTV);
       *bytes = pl.bytes;
       return S3TTV_OK;
     }
@@ -1100,12 +1118,12 @@ int32_t s3ttv_op_workspace_bytes(int32_t op, const s3ttv_shape *shape, int64_t n
 int32_t s3ttv_op_grad(const s3ttv_shape *shape, const float *u, float *gv, float *gh,
                       void *workspace, size_t workspace_bytes, void *stream) {
   if (!valid_shape(shape) || !u || !gv || !gh || !workspace) return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
+  const int32_t sup = supported_shape(shape, kRegS3TTV);
   if (sup != S3TTV_OK) return sup;
   Plan pl;
-  make_plan(pl, shape, nullptr);
+  make_plan(pl, shape, nullptr, kRegS3TTV);
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
-  make_plan(pl, shape, (char *)workspace);
+  make_plan(pl, shape, (char *)workspace, kRegS3TTV);
   hipStream_t st = (hipStream_t)stream;
   CK(launch_init_scalars(pl, 0.0, 0, st));
   CK(launch_grad(pl, u, u, 1.f, 0.f, pl.gradf, st));
@@ -1117,12 +1135,12 @@ int32_t s3ttv_op_grad(const s3ttv_shape *shape, const float *u, float *gv, float
 int32_t s3ttv_op_grad_adj(const s3ttv_shape *shape, const float *zv, const float *zh, float *w,
                           void *workspace, size_t workspace_bytes, void *stream) {
   if (!valid_shape(shape) || !zv || !zh || !w || !workspace) return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
+  const int32_t sup = supported_shape(shape, kRegS3TTV);
   if (sup != S3TTV_OK) return sup;
   Plan pl;
-  make_plan(pl, shape, nullptr);
+  make_plan(pl, shape, nullptr, kRegS3TTV);
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
-  make_plan(pl, shape, (char *)workspace);
+  make_plan(pl, shape, (char *)workspace, kRegS3TTV);
   hipStream_t st = (hipStream_t)stream;
   CK(launch_cubes_to_field(zv, zh, pl.Z, pl.P, pl.n3, pl.Bp, st));
   CK(launch_grad_adj(pl, pl.Z, w, st));
@@ -1187,12 +1205,12 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
                              void *workspace, size_t workspace_bytes, void *stream) {
   if (!valid_shape(shape) || !up || !yin || !yout || !zv || !zh || !workspace) return S3TTV_EINVAL;
   if (!(gamma_Y > 0 && isfinite(gamma_Y))) return S3TTV_EINVAL;
-  const int32_t sup = supported_shape(shape);
+  const int32_t sup = supported_shape(shape, kRegS3TTV);
   if (sup != S3TTV_OK) return sup;
   Plan pl;
-  make_plan(pl, shape, nullptr);
+  make_plan(pl, shape, nullptr, kRegS3TTV);
   if (workspace_bytes < pl.bytes) return S3TTV_EWORKSPACE;
-  make_plan(pl, shape, (char *)workspace);
+  make_plan(pl, shape, (char *)workspace, kRegS3TTV);
   pl.g_Y = (float)gamma_Y;
   hipStream_t st = (hipStream_t)stream;
   CK(configure_block_kernels());  // the apply kernel's overlap-add may need more than 64 KB of LDS

@@ -134,7 +134,8 @@ __device__ inline void load_basis(const BlockArgs &a, long long l, f4 &vd, f4 &v
 }
 
 __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G, f4 vd, f4 Vt,
-                                           float *tb, f4 &Wout) {
+                                           float *tb, f4 &Wout, bool refine = false,
+                                           f4 Xres = f4{0.f, 0.f, 0.f, 0.f}) {
   const int lane = threadIdx.x & 63;
   const int j = lane & 15, g = lane >> 4;
   float *Vl = a.V + (size_t)l * 256;
@@ -157,10 +158,8 @@ __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G
 
   f4 dI;
   float dJ = 0.f;
-  bool ok = false, rough = false;
-  int steps = 0;
-  for (;;) {
-    // symmetrise (exactly) and fetch the diagonal for rows 4g+v and column j
+  // symmetrise A (exactly) and fetch the diagonal for rows 4g+v and column j
+  auto symmetrise = [&]() {
 #pragma unroll
     for (int v = 0; v < 4; ++v) tb[(4 * g + v) * 20 + j] = A[v];
     wave_lds_sync();
@@ -171,6 +170,55 @@ __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G
     wave_lds_sync();
 #pragma unroll
     for (int v = 0; v < 4; ++v) A[v] = 0.5f * (A[v] + At[v]);
+  };
+  // one damped simultaneous rotation step on the symmetrised A; returns ||K||_F^2
+  auto rotate = [&]() -> float {
+    f4 K;
+    float kf2 = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = 4 * g + v;
+      const float den = dJ - dI[v];
+      const float sg = (den > 0.f || (den == 0.f && i < j)) ? 1.f : -1.f;
+      const float q = fabsf(den) + sqrtf(fmaf(den, den, 4.f * A[v] * A[v]));
+      const float t = (i != j && q > 0.f) ? __fdividef(2.f * A[v] * sg, q) : 0.f;
+      K[v] = t;
+      kf2 = fmaf(t, t, kf2);
+    }
+    kf2 = wave_sum(kf2);
+    if (kf2 > kStepCap * kStepCap) {
+      const float sc = kStepCap * rsqrtf(kf2);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) K[v] *= sc;
+      kf2 = kStepCap * kStepCap;
+    }
+    const f4 KK = mtn(K, K);  // K^T K = -K^2
+    f4 J, Jt;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float id = (4 * g + v) == j ? 1.f : 0.f;
+      const float h = -0.5f * KK[v];
+      J[v] = id + K[v] + h;
+      Jt[v] = id - K[v] + h;
+    }
+    if (kf2 > kQuarticNorm2) {
+      f4 K2;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) K2[v] = -KK[v];
+      const f4 K4 = mtn(K2, K2);   // (K^2)^T K^2 = K^4
+      const f4 JK4 = mtn(Jt, K4);  // J K^4
+#pragma unroll
+      for (int v = 0; v < 4; ++v) J[v] = fmaf(-0.125f, JK4[v], J[v]);
+    }
+    A = mtn(J, mtn(A, J));  // J^T (A J), A symmetric
+    Vt = mtn(J, Vt);        // (V J)^T
+    return kf2;
+  };
+
+  bool ok = false, rough = false;
+  int steps = 0;
+  for (;;) {
+    symmetrise();
     // certificate
     bool bad = false;
     float gr[4];
@@ -201,54 +249,45 @@ __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G
       }
     }
     if (steps >= a.eig_steps) break;
-    // one damped simultaneous rotation step
-    f4 K;
-    float kf2 = 0.f;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = 4 * g + v;
-      const float den = dJ - dI[v];
-      const float sg = (den > 0.f || (den == 0.f && i < j)) ? 1.f : -1.f;
-      const float q = fabsf(den) + sqrtf(fmaf(den, den, 4.f * A[v] * A[v]));
-      const float t = (i != j && q > 0.f) ? __fdividef(2.f * A[v] * sg, q) : 0.f;
-      K[v] = t;
-      kf2 = fmaf(t, t, kf2);
-    }
-    kf2 = wave_sum(kf2);
-    if (kf2 > kStepCap * kStepCap) {
-      const float sc = kStepCap * rsqrtf(kf2);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) K[v] *= sc;
-      kf2 = kStepCap * kStepCap;
-    }
-    rough |= kf2 > kRoughNorm2;
-    const f4 KK = mtn(K, K);  // K^T K = -K^2
-    f4 J, Jt;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float id = (4 * g + v) == j ? 1.f : 0.f;
-      const float h = -0.5f * KK[v];
-      J[v] = id + K[v] + h;
-      Jt[v] = id - K[v] + h;
-    }
-    if (kf2 > kQuarticNorm2) {
-      f4 K2;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) K2[v] = -KK[v];
-      const f4 K4 = mtn(K2, K2);   // (K^2)^T K^2 = K^4
-      const f4 JK4 = mtn(Jt, K4);  // J K^4
-#pragma unroll
-      for (int v = 0; v < 4; ++v) J[v] = fmaf(-0.125f, JK4[v], J[v]);
-    }
-    A = mtn(J, mtn(A, J));  // J^T (A J), A symmetric
-    Vt = mtn(J, Vt);        // (V J)^T
+    rough |= rotate() > kRoughNorm2;
     ++steps;
   }
 
+  // Reduced-precision Gram (refine): G is the Gram matrix of the rounded block Yh, and Xres
+  // holds Yh Dh^T with Dh the rounded residual Y' - Yh, so Gc = G + X + X^T is the Gram matrix
+  // of Y' up to the residual's own rounding and Dh Dh^T (relative 2^-16 of G for bfloat16
+  // inputs, 2^-22 for binary16).
+  // The refinement cannot change W when every eigenvalue of G lies below 1 by more than the
+  // spectral norm of X + X^T (Weyl), bounded here by 2 ||X||_F (the omitted Dh Dh^T is far
+  // smaller): then W = I either way.
+  if (refine && ok) {
+    float dmax = fmaxf(fmaxf(dI[0], dI[1]), fmaxf(dI[2], dI[3]));
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, m));
+    const float xf = sqrtf(wave_sum(Xres[0] * Xres[0] + Xres[1] * Xres[1] + Xres[2] * Xres[2] +
+                                    Xres[3] * Xres[3]));
+    if (dmax + 2.001f * xf < 1.f) refine = false;
+  }
+  f4 Gc = G;
+  if (refine) {
+    const f4 Xt = dform_transpose(Xres, tb, j, g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Gc[v] = G[v] + (Xres[v] + Xt[v]);
+  }
   float *Gl = a.G + (size_t)l * 256 + (4 * g) * 16 + j;
   if (ok) {
     f4 Vc;
     orthonormalise(Vc);
+    if (refine) {
+      // One FP32 refinement step of the eigenvectors against Gc: A = V^T Gc V and one
+      // simultaneous rotation (its off-diagonal entries are of the size of the Gram's
+      // rounding, so one step leaves a residual of second order), then the clip factors from
+      // the refined diagonal. A block whose refined spectrum stays below 1 gets W = I.
+      A = mtn(Vc, mtn(Gc, Vc));
+      symmetrise();
+      if (rotate() > kRoughNorm2) orthonormalise(Vc);
+      symmetrise();
+    }
     f4 H;
 #pragma unroll
     for (int v = 0; v < 4; ++v) H[v] = (dI[v] > 1.f ? 1.f - rsqrtf(dI[v]) : 0.f) * Vt[v];
@@ -256,9 +295,10 @@ __device__ __forceinline__ bool eigen_mfma(const BlockArgs &a, long long l, f4 G
 #pragma unroll
     for (int v = 0; v < 4; ++v) Wout[v] = ((4 * g + v) == j ? 1.f : 0.f) - S[v];
   } else {
+    // left to the per-lane Jacobi, which solves the rotated (corrected) Gram matrix
     f4 Vc;
     orthonormalise(Vc);
-    A = mtn(Vc, mtn(G, Vc));
+    A = mtn(Vc, mtn(Gc, Vc));
 #pragma unroll
     for (int v = 0; v < 4; ++v) Gl[16 * v] = A[v];
   }
@@ -713,7 +753,9 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
     load_basis(a, lb, vd, vt);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      y[t] = *(const f4 *)(Yl + t * 256);
+      // Y is streamed (read and written once per pass): non-temporal, so that the L2 keeps
+      // the gradient-field rows that the neighbouring windows of the tile read again
+      y[t] = __builtin_nontemporal_load((const f4 *)(Yl + t * 256));
 #pragma unroll
       for (int s = 0; s < 4; ++s) T[t][s] = gp[s][16 * t];
     }
@@ -727,6 +769,7 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
     // (A and B are the same registers, so any fixed column-to-slot assignment is a valid
     // order of the sum).
     f4 G = {0.f, 0.f, 0.f, 0.f};
+    f4 X = {0.f, 0.f, 0.f, 0.f};  // reduced precision: Yh Dh^T (rounded block x its residual)
     const int prec = a.gram_prec;
 #pragma unroll
     for (int t = 0; t < NT; t += 2) {
@@ -749,21 +792,27 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
         G = mfma4(y1[2], y1[2], G);
         G = mfma4(y1[3], y1[3], G);
       } else if (prec == 1) {
-        bf8 v;
+        bf8 v, r;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           v[s] = (__bf16)y0[s];
           v[4 + s] = (__bf16)y1[s];
+          r[s] = (__bf16)(y0[s] - (float)v[s]);
+          r[4 + s] = (__bf16)(y1[s] - (float)v[4 + s]);
         }
         G = __builtin_amdgcn_mfma_f32_16x16x32_bf16(v, v, G, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_16x16x32_bf16(v, r, X, 0, 0, 0);
       } else {
-        h8 v;
+        h8 v, r;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           v[s] = (_Float16)y0[s];
           v[4 + s] = (_Float16)y1[s];
+          r[s] = (_Float16)(y0[s] - (float)v[s]);
+          r[4 + s] = (_Float16)(y1[s] - (float)v[4 + s]);
         }
         G = __builtin_amdgcn_mfma_f32_16x16x32_f16(v, v, G, 0, 0, 0);
+        X = __builtin_amdgcn_mfma_f32_16x16x32_f16(v, r, X, 0, 0, 0);
       }
     }
     // Y+ below is a spectral-norm projection (entries in [-1, 1]) of Y'; a non-finite Y'
@@ -771,7 +820,7 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
     const bool fin = isfinite(G[0] + G[1] + G[2] + G[3]);
     bad |= !fin;
     f4 W;
-    if (eigen_mfma(a, lb, G, vd, vt, tbw, W) && fin) {
+    if (eigen_mfma(a, lb, G, vd, vt, tbw, W, prec != 0, X) && fin) {
       // Y+ = W Y' (W symmetric: its D-form register s of lane (r, g) is W[r][4g+s]),
       // stored in place and added to the tile's overlap-add accumulators
 #pragma unroll
@@ -781,7 +830,7 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
         acc = mfma4(W[1], y[t][1], acc);
         acc = mfma4(W[2], y[t][2], acc);
         acc = mfma4(W[3], y[t][3], acc);
-        *(f4 *)(Yl + t * 256) = acc;
+        __builtin_nontemporal_store(acc, (f4 *)(Yl + t * 256));
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed_bounded(acc[s]));

@@ -112,7 +112,8 @@ __device__ inline float4 zfold_val4(const int *zpart, int4 off, int col) {
 //   xs = s - g_s y3,   xt = t - g_t (D_v^T y2 + y3),   y3 = kappa * w.
 // MODE 0: the field is adjoined by D_s^T D^T (S3TTV: the overlap-add sum of the blocks; SSTV:
 // the dual field itself); MODE 1: by D^T (STV); MODE 2: D_s^T D^T Z + omega D^T Z2 (HSSTV);
-// MODE 3: as MODE 0 from the partial slots, four bands per thread.
+// MODE 3: as MODE 0 from the partial slots, four bands per thread; MODE 4: the three-component
+// field by D_v^T Zv + D_h^T Zh + D_s^T Zs (SSST).
 template <int MODE>
 __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
   __shared__ unsigned long long h[2][kL1Bins1];
@@ -239,23 +240,34 @@ __global__ __launch_bounds__(kNT) void k_primal(PrimalArgs a) {
     const uint32_t pim = (uint32_t)(wrap_dn(i - 1, a.n1) * n2 + j);
     const uint32_t pjm = (uint32_t)(i * n2 + wrap_dn(j - 1, n2));
     // q(b) = (D_v^T Zv + D_h^T Zh)(b); adjoint of D_s: q(b-1) - q(b)
-    float q0, q1;
+    float q0, q1, zs = 0.f;
     if (a.zslot) {
       const int4 sp = reinterpret_cast<const int4 *>(a.zslot)[pix];
       const int4 si = reinterpret_cast<const int4 *>(a.zslot)[pim];
       const int4 sj = reinterpret_cast<const int4 *>(a.zslot)[pjm];
       q0 = (zfold_val(a.zpart, si, b) - zfold_val(a.zpart, sp, b)) +
            (zfold_val(a.zpart, sj, Bp + b) - zfold_val(a.zpart, sp, Bp + b));
-      q1 = (zfold_val(a.zpart, si, bm) - zfold_val(a.zpart, sp, bm)) +
-           (zfold_val(a.zpart, sj, Bp + bm) - zfold_val(a.zpart, sp, Bp + bm));
+      if (MODE == 4) {
+        // (D_s^T Zs)(b) = Zs(b - 1) - Zs(b)
+        zs = zfold_val(a.zpart, sp, 2 * Bp + bm) - zfold_val(a.zpart, sp, 2 * Bp + b);
+        q1 = 0.f;
+      } else {
+        q1 = (zfold_val(a.zpart, si, bm) - zfold_val(a.zpart, sp, bm)) +
+             (zfold_val(a.zpart, sj, Bp + bm) - zfold_val(a.zpart, sp, Bp + bm));
+      }
     } else {
       const float *Zp = a.Z + (size_t)pix * ncol;
       const float *Zi = a.Z + (size_t)pim * ncol;
       const float *Zj = a.Z + (size_t)pjm * ncol;
       q0 = (Zi[b] - Zp[b]) + (Zj[Bp + b] - Zp[Bp + b]);
-      q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+      if (MODE == 4) {
+        zs = Zp[2 * Bp + bm] - Zp[2 * Bp + b];
+        q1 = 0.f;
+      } else {
+        q1 = (Zi[bm] - Zp[bm]) + (Zj[Bp + bm] - Zp[Bp + bm]);
+      }
     }
-    float adj = MODE == 1 ? q0 : q1 - q0;
+    float adj = MODE == 1 ? q0 : (MODE == 4 ? q0 + zs : q1 - q0);
     if (MODE == 2) {
       const float *Zp = a.Z2 + (size_t)pix * ncol;
       const float *Zi = a.Z2 + (size_t)pim * ncol;
@@ -510,7 +522,7 @@ __device__ inline float clip1(float x) { return fminf(1.f, fmaxf(-1.f, x)); }
 // REG 0 (S3TTV): g = (D_v D_s u', D_h D_s u') for the block pass. REG 1 (STV): g = (D_v u',
 // D_h u'). REG 2 (SSTV): the l1 dual step Z = clip(Z + gZ D D_s u') to [-1, 1] (the Moreau
 // form of the prox of ||.||_1), in place. REG 3 (HSSTV): as REG 2 plus
-// Z2 = clip(Z2 + gZ2 omega D u').
+// Z2 = clip(Z2 + gZ2 omega D u'). REG 4 (SSST): g = (D_v u', D_h u', D_s u').
 template <int REG>
 __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
   __shared__ double sh[4];
@@ -526,7 +538,7 @@ __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
        idx += (long long)gridDim.x * kNT) {
     const uint32_t pix = (uint32_t)(idx / Bp);
     const int b = (int)(idx - (long long)pix * Bp);
-    float gv = 0.f, gh = 0.f;
+    float gv = 0.f, gh = 0.f, gs = 0.f;
     if (b < n3) {
       const int i = (int)(pix / (uint32_t)n2), j = (int)(pix - (uint32_t)i * n2);
       const size_t e = (size_t)pix * n3 + b;
@@ -554,9 +566,10 @@ __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
       const size_t o00 = (size_t)pix * n3;
 #define UP(o, bb) (2.f * a.un[(o) + (bb)] + -1.f * a.uo[(o) + (bb)])
       const float u10 = UP(o10, b), u01 = UP(o01, b);
-      if (REG == 1) {
+      if (REG == 1 || REG == 4) {
         gv = u10 - up;
         gh = u01 - up;
+        if (REG == 4) gs = UP(o00, b1) - up;
       } else {
         const float d00 = UP(o00, b1) - up;
         const float d10 = UP(o10, b1) - u10;
@@ -565,7 +578,7 @@ __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
         gh = d01 - d00;
       }
 #undef UP
-      if (REG >= 2) {
+      if (REG == 2 || REG == 3) {
         const size_t o = (size_t)pix * ag.ncol + b;
         gv = clip1(ag.g[o] + ag.gZ * gv);
         gh = clip1(ag.g[o + Bp] + ag.gZ * gh);
@@ -578,6 +591,7 @@ __global__ __launch_bounds__(kNT) void k_dual_grad(DualGradArgs ag) {
     }
     ag.g[(size_t)pix * ag.ncol + b] = gv;
     ag.g[(size_t)pix * ag.ncol + Bp + b] = gh;
+    if (REG == 4) ag.g[(size_t)pix * ag.ncol + 2 * Bp + b] = gs;
   }
   w2 = block_sum(w2, sh);
   if (threadIdx.x == 0) a.red[blockIdx.x] = w2;
@@ -856,7 +870,7 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
   a.n1 = pl.n1; a.n2 = pl.n2; a.n3 = pl.n3; a.Bp = pl.Bp; a.ncol = pl.ncol; a.N = pl.N;
   a.g_u = pl.g_u; a.g_s = pl.g_s; a.g_t = pl.g_t; a.lo = pl.mu_min; a.hi = pl.mu_max;
   a.u = u_cur; a.s = pl.s; a.t = t_cur; a.y2 = pl.y2; a.w = pl.w; a.Z = pl.Z;
-  a.zpart = pl.zpart; a.zslot = pl.zfold && pl.reg <= kRegSTV ? pl.zslot : nullptr;
+  a.zpart = pl.zpart; a.zslot = pl.zfold && !l1_reg(pl.reg) ? pl.zslot : nullptr;
   a.Z2 = pl.gradf; a.omega = pl.omega;
   a.un = u_new; a.xs = pl.xs; a.xt = pl.xt; a.red = pl.red_primal; a.sc = pl.sc; a.hist = pl.hist;
   const uintptr_t align = reinterpret_cast<uintptr_t>(a.u) | reinterpret_cast<uintptr_t>(a.s) |
@@ -865,6 +879,8 @@ hipError_t launch_primal(const Plan &pl, const float *u_cur, float *u_new, const
                           reinterpret_cast<uintptr_t>(a.xs) | reinterpret_cast<uintptr_t>(a.xt);
   if (pl.reg == kRegSTV)
     hipLaunchKernelGGL(k_primal<1>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
+  else if (pl.reg == kRegSSST)
+    hipLaunchKernelGGL(k_primal<4>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   else if (pl.reg == kRegHSSTV)
     hipLaunchKernelGGL(k_primal<2>, dim3(pl.red_blocks), dim3(kNT), 0, st, a);
   else if (a.zslot && (pl.n3 & 3) == 0 && (align & 15) == 0)
@@ -931,13 +947,14 @@ hipError_t launch_dual_grad(const Plan &pl, const float *u_cur, const float *u_n
   a.un = u_new; a.uo = u_cur; a.xs = pl.xs; a.xt = pl.xt; a.to = t_cur; a.v = v;
   a.s = pl.s; a.tn = t_new; a.y2 = pl.y2; a.w = pl.w; a.red = pl.red_dual; a.sc = pl.sc;
   g.Bp = pl.Bp; g.ncol = pl.ncol;
-  g.g = pl.reg >= kRegSSTV ? pl.Z : pl.gradf;
+  g.g = l1_reg(pl.reg) ? pl.Z : pl.gradf;
   g.g2 = pl.gradf;
   g.gZ = pl.g_Y; g.gZ2 = pl.g_Z2; g.omega = pl.omega;
   switch (pl.reg) {
     case kRegSTV: hipLaunchKernelGGL(k_dual_grad<1>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
     case kRegSSTV: hipLaunchKernelGGL(k_dual_grad<2>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
     case kRegHSSTV: hipLaunchKernelGGL(k_dual_grad<3>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
+    case kRegSSST: hipLaunchKernelGGL(k_dual_grad<4>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
     default: hipLaunchKernelGGL(k_dual_grad<0>, dim3(pl.red_blocks), dim3(kNT), 0, st, g); break;
   }
   return hipGetLastError();

@@ -8,7 +8,11 @@ namespace s3ttv {
 
 // Regularisers on the P-PDS skeleton (values of s3ttv_params.regularizer): the S3TTV term of
 // Prob. (18), or the terms of the compared P-PDS-applicable methods in its place.
-constexpr int kRegS3TTV = 0, kRegSTV = 1, kRegSSTV = 2, kRegHSSTV = 3;
+constexpr int kRegS3TTV = 0, kRegSTV = 1, kRegSSTV = 2, kRegHSSTV = 3, kRegSSST = 4;
+// Regularisers whose dual is a field clipped entrywise (no block pass).
+__host__ __device__ inline bool l1_reg(int reg) { return reg == kRegSSTV || reg == kRegHSSTV; }
+// Components of the block columns per band: 3 for SSST (D_v u, D_h u, D_s u), else 2.
+__host__ __device__ inline int block_comps(int reg) { return reg == kRegSSST ? 3 : 2; }
 
 // Overlap-add partials (P_l^T of step 2) are accumulated in 32-bit fixed point with this
 // scale: every entry of Y+_l lies in [-1, 1] (its spectral norm is at most 1), so a pixel's
@@ -98,8 +102,8 @@ struct L1Hist {
 
 struct Plan {
   int n1, n2, n3, k1, k2, K;
-  int Bp;        // bands padded to a multiple of 16
-  int ncol;      // 2 * Bp columns per block (comp-major: c = comp*Bp + band)
+  int Bp;        // bands padded to a multiple of 16 (of 32 for three components)
+  int ncol;      // comps * Bp columns per block (comp-major: c = comp*Bp + band)
   int ntile;     // ncol / 16
   long long N;   // n1*n2*n3
   long long P;   // n1*n2 pixels (= L blocks)

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(HERE, "libs3ttv.so")
 OK, NOT_CONVERGED, EINVAL, EUNSUPPORTED, EWORKSPACE, EHIP, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
 K_PRIMAL, K_L1, K_GRAD, K_GRAM, K_EIG, K_APPLY, K_ZSUM, K_DUAL, K_FINAL, K_BLOCK = range(10)
 GRAM_FP32, GRAM_BF16, GRAM_FP16 = 0, 1, 2
-REG_S3TTV, REG_STV, REG_SSTV, REG_HSSTV = 0, 1, 2, 3
-REGULARIZERS = {"s3ttv": REG_S3TTV, "stv": REG_STV, "sstv": REG_SSTV, "hsstv": REG_HSSTV}
+REG_S3TTV, REG_STV, REG_SSTV, REG_HSSTV, REG_SSST = 0, 1, 2, 3, 4
+REGULARIZERS = {"s3ttv": REG_S3TTV, "stv": REG_STV, "sstv": REG_SSTV, "hsstv": REG_HSSTV,
+                "ssst": REG_SSST}
 KERNEL_NAMES = ["primal", "l1", "grad", "gram", "eig", "apply", "zsum", "dual", "final", "block"]
 N_KERNEL_CLASSES = len(KERNEL_NAMES)
 OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
@@ -186,10 +187,20 @@ def make_params(eps, alpha, beta, max_iter, mu_min=0.0, mu_max=1.0, gammas: Opti
                   float(omega))
 
 
-def workspace_bytes(n1, n2, n3, k1, k2) -> int:
+def _reg_params(regularizer) -> Params:
+    """Parameters carrying only a regulariser (what the workspace queries read)."""
+    if isinstance(regularizer, str):
+        regularizer = REGULARIZERS[regularizer]
+    p = Params()
+    p.regularizer = int(regularizer)
+    return p
+
+
+def workspace_bytes(n1, n2, n3, k1, k2, regularizer=REG_S3TTV) -> int:
     sz = ctypes.c_size_t()
     sh = Shape(n1, n2, n3, k1, k2)
-    _check(lib().s3ttv_workspace_bytes(ctypes.byref(sh), None, ctypes.byref(sz)),
+    prm = _reg_params(regularizer)
+    _check(lib().s3ttv_workspace_bytes(ctypes.byref(sh), ctypes.byref(prm), ctypes.byref(sz)),
            "s3ttv_workspace_bytes")
     return sz.value
 
@@ -197,11 +208,19 @@ def workspace_bytes(n1, n2, n3, k1, k2) -> int:
 class Solver:
     """Holds a workspace for one shape and runs s3ttv_solve on torch tensors."""
 
-    def __init__(self, n1, n2, n3, k1, k2, device="cuda"):
+    def __init__(self, n1, n2, n3, k1, k2, device="cuda", regularizer=REG_S3TTV):
         self.shape = Shape(n1, n2, n3, k1, k2)
         self.dims = (n1, n2, n3)
         self.device = device
-        self.ws = _workspace(workspace_bytes(n1, n2, n3, k1, k2), device)
+        self.ws = _workspace(workspace_bytes(n1, n2, n3, k1, k2, regularizer), device)
+
+    def _fit(self, params: Params):
+        """Grows the workspace when params' regulariser needs more (SSST's blocks have three
+        columns per band); a larger workspace holds no state, so it suits a new solve only."""
+        sh = self.shape
+        need = workspace_bytes(sh.n1, sh.n2, sh.n3, sh.k1, sh.k2, params.regularizer)
+        if self.ws.numel() < need:
+            self.ws = _workspace(need, self.device)
 
     def solve(self, v, params: Params, u0=None, out=None, s0=None, t0=None):
         """s3ttv_solve, or s3ttv_solve_from when s0 or t0 is given."""
@@ -211,6 +230,7 @@ class Solver:
         if out is None:
             out = tuple(torch.empty_like(v) for _ in range(3))
         u, s, t = out
+        self._fit(params)
         st = Stats()
         ws = (ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()), _stream(),
               ctypes.byref(st))
@@ -259,11 +279,13 @@ def _stats_dict(st: Stats, rc: int) -> dict:
                 tile=(st.tile_a, st.tile_b), status=st.status, code=rc)
 
 
-def batch_workspace_bytes(shapes) -> int:
-    """shapes: list of (n1, n2, n3, k1, k2)."""
+def batch_workspace_bytes(shapes, params=None) -> int:
+    """shapes: list of (n1, n2, n3, k1, k2); params: list of Params (their regularisers size
+    the regions) or None (S3TTV)."""
     arr = (Shape * len(shapes))(*[Shape(*sh) for sh in shapes])
+    prm = (Params * len(shapes))(*params) if params is not None else None
     sz = ctypes.c_size_t()
-    _check(lib().s3ttv_batch_workspace_bytes(len(shapes), arr, None, ctypes.byref(sz)),
+    _check(lib().s3ttv_batch_workspace_bytes(len(shapes), arr, prm, ctypes.byref(sz)),
            "s3ttv_batch_workspace_bytes")
     return sz.value
 
@@ -278,7 +300,7 @@ def solve_batched(problems, workspace=None):
     shapes = [(*p["v"].shape, p["k1"], p["k2"]) for p in problems]
     sh = (Shape * n)(*[Shape(*x) for x in shapes])
     prm = (Params * n)(*[p["params"] for p in problems])
-    need = batch_workspace_bytes(shapes)
+    need = batch_workspace_bytes(shapes, [p["params"] for p in problems])
     dev = problems[0]["v"].device
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
@@ -300,8 +322,9 @@ def solve_batched(problems, workspace=None):
 def solve(v, k1, k2, eps, alpha, beta, max_iter, u0=None, s0=None, t0=None, **kw):
     """One-shot solve of Prob. (18) by Alg. 1 on the GPU; returns (u, s, t, stats)."""
     n1, n2, n3 = v.shape
-    sv = Solver(n1, n2, n3, k1, k2, device=v.device)
-    return sv.solve(v, make_params(eps, alpha, beta, max_iter, **kw), u0=u0, s0=s0, t0=t0)
+    params = make_params(eps, alpha, beta, max_iter, **kw)
+    sv = Solver(n1, n2, n3, k1, k2, device=v.device, regularizer=params.regularizer)
+    return sv.solve(v, params, u0=u0, s0=s0, t0=t0)
 
 
 # ---------------------------------------------------------------- operator entry points

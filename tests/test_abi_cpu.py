@@ -86,7 +86,7 @@ def test_shape_validation(shape, code):
 @pytest.mark.parametrize("bad", [dict(eps=0.0), dict(alpha=-1.0), dict(beta=float("nan")),
                                  dict(mu_min=1.0, mu_max=0.0), dict(max_iter=0),
                                  dict(gammas=dict(gamma_u=0.1)), dict(eig_max_steps=256),
-                                 dict(regularizer=4), dict(regularizer=-1), dict(omega=-0.1),
+                                 dict(regularizer=5), dict(regularizer=-1), dict(omega=-0.1),
                                  dict(omega=float("nan"))])
 def test_param_validation_before_any_gpu_call(bad):
     kw = dict(eps=1.0, alpha=1.0, beta=1.0, max_iter=10)

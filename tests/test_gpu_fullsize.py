@@ -63,9 +63,10 @@ def throughput_case():
     return d, (k1, k2), r
 
 
-# relative L2 / max-abs bounds per mode (FP32: the rounding of 3 iterations; BF16 / FP16: the
-# Gram inputs rounded to 8 / 11 significand bits, then one FP32 refinement step)
-THROUGHPUT_BOUNDS = {"fp32": (1e-5, 2e-5), "bf16": (1e-4, 1e-3), "fp16": (2e-5, 1e-4)}
+# relative L2 / max-abs bounds per mode, about 5-10x the largest value measured on MI355X over
+# u, s, t (FP32: 4.0e-7 / 1.3e-7; BF16 Gram inputs, then one FP32 refinement step: 4.0e-7 /
+# 3.0e-6; FP16: 4.0e-7 / 1.8e-7; without the refinement BF16 was at 7.1e-6 / 4.5e-5)
+THROUGHPUT_BOUNDS = {"fp32": (4e-6, 2e-6), "bf16": (4e-6, 2e-5), "fp16": (4e-6, 2e-6)}
 
 
 @pytest.mark.timeout(900)
@@ -99,7 +100,9 @@ def long_case():
     return d, r
 
 
-LONG_BOUNDS = {"fp32": (1e-4, 1e-4), "bf16": (1e-4, 1e-3), "fp16": (1e-4, 2e-4)}
+# measured: FP32 4.8e-7 / 9.2e-7, BF16 with refinement 6.4e-7 / 1.1e-6 (without: 5.7e-6 /
+# 9.3e-6), FP16 4.7e-7 / 8.7e-7
+LONG_BOUNDS = {"fp32": (5e-6, 1e-5), "bf16": (5e-6, 1e-5), "fp16": (5e-6, 1e-5)}
 
 
 @pytest.mark.timeout(600)

@@ -1,6 +1,6 @@
 """GPU parity of the regulariser variants (s3ttv_params.regularizer) with the FP64 oracle:
-STV, SSTV and HSSTV in place of S3TTV on the P-PDS skeleton of Alg. 1 (Sec. IV-A). Same bar
-as the S3TTV solve: relative L2 <= 1e-4 per output after a fixed iteration count."""
+STV, SSTV, HSSTV and SSST in place of S3TTV on the P-PDS skeleton of Alg. 1 (Sec. IV-A). Same
+bar as the S3TTV solve: relative L2 <= 1e-4 per output after a fixed iteration count."""
 import numpy as np
 import pytest
 import torch
@@ -19,7 +19,7 @@ def _rel(a, b):
 CASES = [((20, 18, 13), (3, 3), 100), ((13, 11, 7), (2, 3), 60), ((16, 16, 16), (4, 4), 40)]
 
 
-@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv"])
+@pytest.mark.parametrize("reg", ["stv", "sstv", "hsstv", "ssst"])
 @pytest.mark.parametrize("shape,k,iters", CASES)
 def test_variant_parity(device, reg, shape, k, iters):
     print(f"variant {reg} shape={shape} k={k} iters={iters}", flush=True)
@@ -45,12 +45,35 @@ def test_variant_parity(device, reg, shape, k, iters):
         assert calls["block"] + calls["gram"] >= iters
 
 
+@pytest.mark.parametrize("shape,k,iters", [((12, 12, 70), (2, 2), 30),    # 3 x 96 columns: separate kernels
+                                           ((14, 12, 33), (4, 4), 30),    # 3 x 64 columns: fused pass
+                                           ((12, 12, 8), (10, 10), 20),   # K = 100: one workgroup per block
+                                           ((11, 9, 5), (5, 4), 25)])     # K = 20
+def test_ssst_parity_while_clipping(device, shape, k, iters):
+    """SSST (blocks of D_v u, D_h u, D_s u: three columns per band) on every block route,
+    started from u0 = v so that the blocks clip from the first iteration."""
+    print(f"ssst shape={shape} k={k} iters={iters}", flush=True)
+    cfg = synth.HSIConfig(*shape, endmembers=3, cells=5, sigma=0.08, p_sp=0.05, p_stripe=0.2,
+                          seed=23)
+    d = synth.make_hsi(cfg)
+    v = torch.from_numpy(d["v"]).to(device)
+    u, s, t, st = nt.solve(v, k[0], k[1], max_iter=iters, regularizer="ssst", u0=v, **d["radii"])
+    r = oracle.solve(d["v64"], k[0], k[1], max_iter=iters, regularizer="ssst", u0=d["v64"],
+                     **d["radii"])
+    errs = {n: _rel(g.cpu().numpy().astype(np.float64), r[n]) for n, g in (("u", u), ("s", s), ("t", t))}
+    print("  rel L2 vs oracle:", errs, "eig steps", st["eig_avg_steps"], "blocks solved",
+          st["eig_blocks"], flush=True)
+    for n, e in errs.items():
+        assert e <= 1e-4, (n, e)
+    assert st["iters"] == iters and st["eig_blocks"] > 0
+
+
 def test_variants_batched_identical_to_standalone(device):
-    """One batched call with all four regularisers side by side; each result equals the
+    """One batched call with all five regularisers side by side; each result equals the
     standalone solve bitwise."""
     cfgs = [synth.HSIConfig(24, 20, 16, endmembers=3, cells=5, sigma=0.05, p_sp=0.05,
-                            p_stripe=0.1, seed=30 + i) for i in range(4)]
-    regs = ["s3ttv", "stv", "sstv", "hsstv"]
+                            p_stripe=0.1, seed=30 + i) for i in range(5)]
+    regs = ["s3ttv", "stv", "sstv", "hsstv", "ssst"]
     probs = []
     for cfg, reg in zip(cfgs, regs):
         d = synth.make_hsi(cfg)

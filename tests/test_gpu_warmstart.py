@@ -87,3 +87,35 @@ def test_cold_and_warm_runs_meet(device, trained):
     du, ds, dt = _dist(uw, uc), _dist(sw, sc), _dist(tw, tc)
     print(f"after 30000 iterations: u {du:.2e} s {ds:.2e} t {dt:.2e}", flush=True)
     assert du <= 1e-3 and ds <= 1e-2 and dt <= 1e-2
+
+
+def test_noise_levels_of_the_large_scene_recorded(device, trained):
+    """Held-out 64^3 scenes at the noise levels of the 512 x 512 x 191 warm-start scene
+    (Gaussian 0.1, salt-and-pepper 0.1, stripes 0.1): iterations to rel-tol 1e-4 from zero and
+    from the estimate are recorded. At these levels the learned start does not reliably need
+    fewer iterations (on the large scene it needs more: the stop rule fires at different kinds
+    of points for the two starts), so what is asserted is only what holds: the estimate is
+    closer to the solution than the observation, both runs converge and stay feasible."""
+    tr = trained[0]
+    totals = {"cold": 0, "warm": 0}
+    for i in range(3):
+        cfg = synth.HSIConfig(64, 64, 64, endmembers=8, cells=16, sigma=0.1, p_sp=0.1,
+                              p_stripe=0.1, seed=9200 + i)
+        d = synth.make_hsi(cfg)
+        v = torch.from_numpy(d["v"]).to(device)
+        sv = nt.Solver(*v.shape, 4, 4, device=device)
+        ref = sv.solve(v, nt.make_params(max_iter=20000, rel_tol=1e-7, **d["radii"]))[0].clone()
+        r = ws.solve_cold_warm(v, d["radii"], tr.params, rel_tol=1e-4, max_iter=8000, solver=sv)
+        cold, warm, u0 = r["cold"], r["warm"], r["u0"]
+        print(f"scene {cfg.seed} (noise 0.1 / 0.1 / 0.1): estimate {_dist(u0, ref):.2e} vs "
+              f"observation {_dist(v, ref):.2e}; to rel-tol 1e-4 cold {cold[3]['iters']} "
+              f"(distance {_dist(cold[0], ref):.2e}) warm {warm[3]['iters']} "
+              f"(distance {_dist(warm[0], ref):.2e}) iterations", flush=True)
+        assert _dist(u0, ref) <= 0.5 * _dist(v, ref)
+        assert cold[3]["converged"] and warm[3]["converged"]
+        rad = d["radii"]
+        assert warm[3]["l1_s"] <= rad["alpha"] * (1 + 1e-5)
+        assert warm[3]["l1_t"] <= rad["beta"] * (1 + 1e-5)
+        totals["cold"] += cold[3]["iters"]
+        totals["warm"] += warm[3]["iters"]
+    print(f"total iterations to rel-tol 1e-4 at these noise levels: {totals}", flush=True)
