@@ -280,6 +280,17 @@ int32_t s3ttv_op_dual_blocks(const s3ttv_shape *shape, double gamma_Y, const flo
 int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out, double *tau,
                             void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture or in a serving
+ * loop, harnesses that forbid hipMalloc): s3ttv_op_l1_project without a workspace argument.
+ * Same kernels and result (bitwise) for n <= 2^24 elements; larger n: S3TTV_EUNSUPPORTED.
+ * Its scratch (scalars and histograms, about 8.2 MiB) is a static device array of the
+ * library, one per GPU, held until the process ends; the call allocates nothing. Calls of
+ * one process on one device are serialised by the library (they share that array), so
+ * overlapping calls from several threads run one after another. x, out (device, n floats),
+ * tau (host, nullable). */
+int32_t s3ttv_op_l1_project_noalloc(int64_t n, const float *x, double radius, float *out,
+                                    double *tau, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1282,4 +1282,83 @@ int32_t s3ttv_op_l1_project(int64_t n, const float *x, double radius, float *out
   return S3TTV_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free l1 projection
+
 }  // extern "C"
+
+namespace {
+
+// Scratch of s3ttv_op_l1_project_noalloc: the device scalars, the l1 histograms and the
+// level-2 partial histograms of one projection of at most kNoAllocMaxN elements. Each GPU the
+// library runs on holds one copy until the process ends. In host code the name `scratch` is a
+// host-side stand-in: only the device address from hipGetSymbolAddress may reach a kernel.
+constexpr long long kNoAllocMaxN = 1ll << 24;
+constexpr size_t kNoAllocBytes = ((sizeof(DevScalars) + kAlign - 1) / kAlign * kAlign) +
+                                 ((sizeof(L1Hist) + kAlign - 1) / kAlign * kAlign) +
+                                 (size_t)((kNoAllocMaxN + kL1PartElems - 1) / kL1PartElems) *
+                                     kL1Bins2 * sizeof(unsigned long long);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on the current device, looked up once per device. The mutex
+// also serialises the calls of this process on one device (they share the array).
+struct NoAllocScratch {
+  std::mutex mu;
+  std::map<int, void *> ptr;
+};
+
+NoAllocScratch &noalloc_scratch() {
+  static NoAllocScratch s;
+  return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t s3ttv_op_l1_project_noalloc(int64_t n, const float *x, double radius, float *out,
+                                    double *tau, void *stream) {
+  if (n < 1 || !x || !out || !(radius > 0 && isfinite(radius))) return S3TTV_EINVAL;
+  if (n > kNoAllocMaxN) return S3TTV_EUNSUPPORTED;
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  NoAllocScratch &ns = noalloc_scratch();
+  std::lock_guard<std::mutex> lk(ns.mu);
+  auto it = ns.ptr.find(dev);
+  if (it == ns.ptr.end()) {
+    void *p = nullptr;
+    CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return S3TTV_EHIP;
+    it = ns.ptr.emplace(dev, p).first;
+  }
+  Carver cv{(char *)it->second, 0, false};
+  DevScalars *sc = cv.take<DevScalars>(1);
+  L1Hist *h = cv.take<L1Hist>(1);
+  unsigned long long *part = cv.take<unsigned long long>((size_t)l1_part_blocks(n) * kL1Bins2);
+  if (cv.off > kNoAllocBytes) return S3TTV_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  Plan tmp;
+  memset(&tmp, 0, sizeof(tmp));
+  tmp.sc = sc;
+  // the array keeps the previous call's contents: the scalars and the histograms that are
+  // accumulated start from zero (the level-2 partials are written whole by their pass)
+  CK(launch_init_scalars(tmp, 0.0, 0, st));
+  CK(launch_zero_bytes(h, sizeof(L1Hist), st));
+  for (int level = 1; level <= 3; ++level) {
+    if (level == 2) {
+      CK(launch_l1_hist_part(x, nullptr, n, 1, part, sc, st));
+      CK(launch_l1_part_reduce(1, n, part, h, sc, st));
+    } else {
+      CK(launch_l1_hist(x, nullptr, n, 1, level, h, sc, st));
+    }
+    CK(launch_l1_select(1, level, radius, radius, h, sc, st));
+  }
+  CK(launch_l1_apply(x, out, n, 0, sc, st));
+  DevScalars hs;
+  CK(hipMemcpyAsync(&hs, sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (tau) *tau = hs.active[0] ? hs.tau[0] : 0.0;
+  return S3TTV_OK;
+}
+
+}  // extern "C"
+

@@ -26,7 +26,8 @@ OP_GRAD, OP_GRAD_ADJ, OP_CLIP, OP_DUAL_BLOCKS, OP_L1 = range(5)
 EXPORTS = ["s3ttv_workspace_bytes", "s3ttv_solve", "s3ttv_solve_from", "s3ttv_solve_continue",
            "s3ttv_strerror", "s3ttv_op_workspace_bytes",
            "s3ttv_op_grad", "s3ttv_op_grad_adj", "s3ttv_op_spectral_clip",
-           "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_batch_workspace_bytes",
+           "s3ttv_op_dual_blocks", "s3ttv_op_l1_project", "s3ttv_op_l1_project_noalloc",
+           "s3ttv_batch_workspace_bytes",
            "s3ttv_solve_batched", "s3ttv_cnn_param_count", "s3ttv_cnn_workspace_bytes",
            "s3ttv_cnn_forward", "s3ttv_cnn_grad", "s3ttv_cnn_train_step"]
 
@@ -104,6 +105,8 @@ def lib():
                                            vp, vp, sz, vp]
         L.s3ttv_op_l1_project.argtypes = [ctypes.c_int64, vp, ctypes.c_double, vp,
                                           ctypes.POINTER(ctypes.c_double), vp, sz, vp]
+        L.s3ttv_op_l1_project_noalloc.argtypes = [ctypes.c_int64, vp, ctypes.c_double, vp,
+                                                  ctypes.POINTER(ctypes.c_double), vp]
         L.s3ttv_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
                                                   ctypes.POINTER(Params), ctypes.POINTER(sz)]
         L.s3ttv_solve_batched.argtypes = [ctypes.c_int32, ctypes.POINTER(Shape),
@@ -398,6 +401,19 @@ def op_l1_project(x, radius):
                                      _dev_ptr(out, "out"), ctypes.byref(tau),
                                      ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
                                      _stream()), "s3ttv_op_l1_project")
+    return out, tau.value
+
+
+def op_l1_project_noalloc(x, radius, out=None):
+    """s3ttv_op_l1_project_noalloc: the same projection with the library's static scratch
+    (no workspace; x.numel() <= 2^24)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    tau = ctypes.c_double()
+    _check(lib().s3ttv_op_l1_project_noalloc(x.numel(), _dev_ptr(x, "x"), float(radius),
+                                             _dev_ptr(out, "out"), ctypes.byref(tau), _stream()),
+           "s3ttv_op_l1_project_noalloc")
     return out, tau.value
 
 

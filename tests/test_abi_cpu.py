@@ -119,6 +119,18 @@ def test_continue_rejects_invalid_arguments_before_any_gpu_call():
     assert rc == nt.EWORKSPACE
 
 
+def test_l1_noalloc_validates_before_any_gpu_call():
+    """The allocation-free l1 projection rejects sizes beyond its static scratch (2^24
+    elements) and invalid arguments on the host."""
+    L = nt.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.s3ttv_op_l1_project_noalloc((1 << 24) + 1, dummy, 1.0, dummy, None, None) == nt.EUNSUPPORTED
+    assert L.s3ttv_op_l1_project_noalloc(0, dummy, 1.0, dummy, None, None) == nt.EINVAL
+    assert L.s3ttv_op_l1_project_noalloc(10, None, 1.0, dummy, None, None) == nt.EINVAL
+    assert L.s3ttv_op_l1_project_noalloc(10, dummy, 0.0, dummy, None, None) == nt.EINVAL
+    assert L.s3ttv_op_l1_project_noalloc(10, dummy, float("inf"), dummy, None, None) == nt.EINVAL
+
+
 def test_null_pointers_rejected():
     p = nt.make_params(1.0, 1.0, 1.0, 10)
     rc = nt.lib().s3ttv_solve(ctypes.byref(nt.Shape(8, 8, 4, 2, 2)), ctypes.byref(p), None, None,
