@@ -141,27 +141,33 @@ PAPER_SCENES = {"100x100x198": ("paper10", PAPER_SECONDS_100x100x198),
                 "120x120x98": ("paper10_120x120x98", 2.05e4),
                 "100x100x128": ("paper10_100x100x128", 1.74e4)}
 # The same table's rows for the compared regularisers this library runs on the P-PDS
-# skeleton (HSSTV in its l1 form, the paper's HSSTV1; STV with 10 x 10 blocks).
+# skeleton (HSSTV in its l1 form, the paper's HSSTV1; STV and SSST with 10 x 10 blocks).
 PAPER_SECONDS_COMPARED = {
     "sstv": {"100x100x198": 1.92e2, "120x120x98": 2.39e2, "100x100x128": 2.47e2},
     "hsstv": {"100x100x198": 2.03e2, "120x120x98": 2.05e2, "100x100x128": 1.81e2},
     "stv": {"100x100x198": 1.82e4, "120x120x98": 1.83e4, "100x100x128": 9.66e3},
+    "ssst": {"100x100x198": 6.95e4, "120x120x98": 1.47e4, "100x100x128": 9.01e4},
 }
 
 
-def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float) -> float:
+def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float,
+                          sim_steps: float = 0.0) -> float:
     """FP32 flops of the dense products of one launch of the large-block pass: the symmetric
     Gram (K (K + 1) / 2 dot products of length 2 n3) of every block and, for the blocks that
-    needed the eigen-solve, V^T G V and the Newton-Schulz step (four K x K x K products) and
-    the Rayleigh quotients (a K x K x 2 n3 product). The Jacobi rotations and the low-rank
-    clip are not counted, so the figure is a lower bound on the work done."""
+    needed the eigen-solve, V^T G V and the Newton-Schulz step (four K x K x K products), the
+    Rayleigh quotients (a K x K x 2 n3 product) and, per simultaneous rotation step
+    (`sim_steps` per such block on average), at least four K x K x K products (K^T K, V J and
+    two for the rotated A). The cyclic Jacobi rotations, extra Newton-Schulz steps and the
+    low-rank clip are not counted, so the figure is a lower bound on the work done."""
     c = 2 * n3
-    return nblk * K * (K + 1) * c + eig_blocks * (8 * K ** 3 + 2 * K * K * c)
+    return nblk * K * (K + 1) * c + eig_blocks * (8 * K ** 3 + 2 * K * K * c
+                                                  + 8 * K ** 3 * sim_steps)
 
 
 def bench_paper_shape(nt, synth, torch, args) -> int:
     """The paper's experimental shape: a 100 x 100 x 198 scene with 10 x 10 windows (K = 100),
-    throughput over a run from zero and the time to the paper's stop rule (1e-5)."""
+    throughput over iterations that continue a solve from zero after a pre-roll (as the default
+    workload: the clipping phase) and the time to the paper's stop rule (1e-5) from zero."""
     wname, paper_seconds = PAPER_SCENES[args.scene]
     reg = args.regularizer
     if reg != "s3ttv":
@@ -178,15 +184,18 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
     v = torch.from_numpy(d["v"]).to(dev)
     rad = d["radii"]
     solver = nt.Solver(n1, n2, n3, k1, k2, device=dev)
-    solver.solve(v, nt.make_params(max_iter=max(min(args.warmup, 20), 1), regularizer=reg, **rad))
+    first = args.preroll + max(args.warmup, 1)
+    print(f"[bench] pre-roll {first} iterations from zero ({reg})", file=sys.stderr, flush=True)
+    solver.solve(v, nt.make_params(max_iter=first, regularizer=reg, **rad))
     torch.cuda.synchronize()
     steps = args.paper_steps
-    print(f"[bench] timed {steps} iterations ({reg})", file=sys.stderr, flush=True)
+    print(f"[bench] timed {steps} iterations (iterations {first + 1}-{first + steps})",
+          file=sys.stderr, flush=True)
     cls = nt.K_DUAL if l1_reg else nt.K_BLOCK
     params = nt.make_params(max_iter=steps, timing_mask=1 << cls, regularizer=reg, **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, _, _, st = solver.solve(v, params)
+    _, _, _, st = solver.resume(v, params)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     name = nt.KERNEL_NAMES[cls]
@@ -205,7 +214,8 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
                     "traffic": None, "avg_launch_ms": block_ms, "launches_timed": calls,
                     "algorithmic_bytes_per_launch": dbytes}
     else:
-        flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls)
+        flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls,
+                                      st["eig_avg_sweeps"])
         achieved = flops / (block_ms * 1e-3) / 1e12
         roofline = {"kernel": "k_big_block", "bound": "alu", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -218,7 +228,7 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": max(min(args.warmup, 20), 1),
+        "warmup": max(args.warmup, 1),
         "ms_per_step": 1e3 * wall / steps,
         "higher_is_better": True,
         "scaling": "weak",
@@ -231,7 +241,9 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
                    "n1": n1, "n2": n2, "n3": n3, "k1": k1, "k2": k2, "seed": cfg.seed,
                    "regularizer": reg},
         "roofline": roofline,
+        "timed_iterations": [first + 1, first + steps],
         "eig_blocks_per_launch": st["eig_blocks"] / calls,
+        "eig_sim_steps_per_solved_block": st["eig_avg_sweeps"],
         "eig_avg_sweeps_per_solved_block": st["eig_avg_steps"],
         "eig_max_sweeps": st["eig_max_sweeps"],
         "eig_uncertified_blocks": st["eig_fallback_blocks"],
@@ -512,11 +524,12 @@ def main() -> int:
                          "c5: learned initial estimate vs zero start on 512x512x191; cnn: the "
                          "network kernels alone; paper10: the paper's 100x100x198 shape with "
                          "10x10 windows")
-    ap.add_argument("--paper-steps", type=int, default=300,
-                    help="paper10: timed iterations (a run from zero)")
+    ap.add_argument("--paper-steps", type=int, default=100,
+                    help="paper10: timed iterations (continuing a solve after the pre-roll)")
     ap.add_argument("--scene", choices=sorted(PAPER_SCENES), default="100x100x198",
                     help="paper10: the shape of one of the paper's scenes")
-    ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv"], default="s3ttv",
+    ap.add_argument("--regularizer", choices=["s3ttv", "stv", "sstv", "hsstv", "ssst"],
+                    default="s3ttv",
                     help="c2, paper10: term minimised on the P-PDS skeleton (S3TTV is the paper's)")
     ap.add_argument("--pairs", type=int, default=2000, help="c5: training pairs (64^3 scenes)")
     ap.add_argument("--train-steps", type=int, default=2500, help="c5: Adam steps (batch 8)")
@@ -574,9 +587,20 @@ def main() -> int:
 
     print(f"[bench] timed {args.steps} iterations (iterations {first + 1}-{first + args.steps})",
           file=sys.stderr, flush=True)
-    cls = nt.K_DUAL if l1_reg else nt.K_BLOCK
-    params = nt.make_params(max_iter=args.steps, timing_mask=1 << cls, gram_precision=prec,
-                            regularizer=reg, **rad)
+    # blocks of at most 16 rows and 16 column tiles take the fused block pass; more columns
+    # (SSST's three components at N3 > 64) the separate Gram / eigen / apply kernels
+    comps = 3 if reg == "ssst" else 2
+    bq = 32 if comps == 3 else 16
+    fused = k1 * k2 <= 16 and comps * ((n3 + bq - 1) // bq * bq) <= 256
+    if l1_reg:
+        classes = [nt.K_DUAL]
+    elif fused:
+        classes = [nt.K_BLOCK]
+    else:
+        classes = [nt.K_GRAM, nt.K_EIG, nt.K_APPLY]
+    cls = classes[0]
+    params = nt.make_params(max_iter=args.steps, timing_mask=sum(1 << c for c in classes),
+                            gram_precision=prec, regularizer=reg, **rad)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     u, s, t, st = solver.resume(v, params)
@@ -588,7 +612,8 @@ def main() -> int:
     if block_calls < 1:
         print(f"bench.py: the timed kernel ({name}) did not run", file=sys.stderr)
         return 3
-    block_ms = st["kernel_ms"][name] / block_calls
+    # average time of the pass per iteration (the separate route: its three kernels together)
+    block_ms = sum(st["kernel_ms"][nt.KERNEL_NAMES[c]] for c in classes) / block_calls
     design_bytes = None
     if l1_reg:
         # the dual sweep is the largest pass of the l1 variants: 36 B read and 16 B written per
@@ -596,12 +621,13 @@ def main() -> int:
         kname = "k_dual_grad"
         block_bytes = n1 * n2 * n3 * (52 + 16 * (2 if reg == "hsstv" else 1))
     else:
-        kname = "k_block_fused"
-        block_bytes = block_pass_algorithmic_bytes(n1, n2, n3, k1, k2)
-        design_bytes = block_pass_design_bytes(n1, n2, n3, k1, k2)
+        kname = "k_block_fused" if fused else "k_gram + k_eig + k_apply"
+        # steps 9-10 read and write every block once: K x comps N3 floats
+        block_bytes = block_pass_algorithmic_bytes(n1, n2, n3, k1, k2) * comps // 2
+        design_bytes = block_pass_design_bytes(n1, n2, n3, k1, k2) if comps == 2 and fused else None
     achieved = block_bytes / (block_ms * 1e-3) / 1e9
 
-    traffic = measured_traffic(kname) if reg == "s3ttv" else None
+    traffic = measured_traffic(kname) if reg == "s3ttv" and fused else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -641,8 +667,8 @@ def main() -> int:
         # (the stage shares the launch with the eigen-solve, the clip and the overlap-add, so
         # this is a lower bound of the stage's own rate), and the matrix-pipe busy fraction of
         # the whole launch from the committed counter summary while the source is unchanged
-        gf = gram_flops(n1, n2, n3, k1, k2)
-        busy = measured_counter("mfma_busy_frac", kname) if reg == "s3ttv" else None
+        gf = gram_flops(n1, n2, n3, k1, k2) * comps // 2
+        busy = measured_counter("mfma_busy_frac", kname) if reg == "s3ttv" and fused else None
         peak = MFMA_PEAK_TFLOPS[args.gram_precision]
         out["gram_mfma"] = {"flops_per_launch": gf, "achieved_tflops": gf / (block_ms * 1e-3) / 1e12,
                             "peak_tflops": peak,

@@ -157,11 +157,13 @@ typedef struct {
   int64_t eig_fallback_blocks; /* blocks of iterations 2..iters the MFMA rotations could not
                                   certify, finished by the per-lane Jacobi (iteration 1 always
                                   solves every block with the per-lane Jacobi) */
-  /* For K = k1 k2 > 16 (one workgroup per block, cyclic Jacobi on the block Gram in the basis
-     kept from the previous iteration): eig_max_sweeps is the largest sweep count of a block,
-     eig_avg_steps the sweeps per block that needed the eigen-solve (blocks whose Gram passes
-     the Gershgorin test skip it), eig_fallback_blocks the blocks that used up the sweep limit
-     without the certificate; eig_avg_sweeps and eig_max_steps stay 0. */
+  /* For K = k1 k2 > 16 (one workgroup per block: simultaneous rotation steps on MFMA, then
+     cyclic Jacobi sweeps, on the block Gram in the basis kept from the previous iteration):
+     eig_avg_sweeps is the simultaneous rotation steps per block that needed the eigen-solve
+     (blocks whose Gram passes the Gershgorin test skip it), eig_avg_steps the cyclic sweeps
+     per such block, eig_max_sweeps the largest cyclic sweep count of a block,
+     eig_fallback_blocks the blocks that used up the sweep limit without the certificate;
+     eig_max_steps stays 0. */
   float ms;             /* wall time of the iteration loop (HIP events; batched: of the batch) */
   float kernel_ms[S3TTV_K_COUNT];     /* summed durations of timed classes */
   int32_t kernel_calls[S3TTV_K_COUNT];

@@ -160,7 +160,9 @@ void make_plan(Plan &pl, const s3ttv_shape *sh, char *base, int reg, int forceTA
   // one extra all-zero slot at the end (named by the primal step's slot table for absent terms)
   pl.zpart = cv.take<int>((size_t)pl.zslots_n * pl.ncol);
   pl.zslot = cv.take<int>((size_t)pl.P * 4);
-  pl.G = cv.take<float>((size_t)pl.P * 256);
+  // K <= 16: the rotated Gram of blocks left to the per-lane Jacobi; K > 16: a copy of every
+  // block's Gram (the large-block kernel re-derives V^T G V from it after its rotation steps)
+  pl.G = cv.take<float>((size_t)pl.P * (pl.big ? (size_t)pl.K * pl.K : 256));
   pl.W = cv.take<float>((size_t)pl.P * 256);
   pl.V = cv.take<float>((size_t)pl.P * (pl.big ? (size_t)pl.K * pl.K : 256));
   pl.eflag = cv.take<int>((size_t)pl.P);
@@ -456,7 +458,7 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
     BigArgs ba;
     ba.n1 = pl.n1; ba.n2 = pl.n2; ba.k1 = pl.k1; ba.k2 = pl.k2; ba.K = pl.K; ba.ncol = pl.ncol;
     ba.nblk = pl.P; ba.gradf = pl.gradf; ba.gY = pl.g_Y; ba.Y = pl.Y; ba.V = pl.V;
-    ba.first = it == 0; ba.max_sweeps = kBigMaxSweeps; ba.sc = pl.sc;
+    ba.Gg = pl.G; ba.first = it == 0; ba.max_sweeps = kBigMaxSweeps; ba.sc = pl.sc;
     TIMED(S3TTV_K_BLOCK, launch_big_block(ba, st));
     TIMED(S3TTV_K_ZSUM, launch_big_overlap(ba, pl.Z, st));
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));

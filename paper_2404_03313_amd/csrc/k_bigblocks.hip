@@ -7,7 +7,9 @@
 //   G  = Y' Y'^T                                    (K x K, FP32 sums, 32-column chunks)
 //   if every Gershgorin row bound of G is <= 1, no singular value of Y' exceeds 1 and step 10
 //   leaves Y' unchanged; otherwise
-//   A = V^T G V from the stored (orthonormal) eigenbasis V of the previous iteration,
+//   A = V^T G V from the stored (orthonormal) eigenbasis V of the previous iteration; from the
+//   second iteration on, up to kSimSteps simultaneous rotation steps on MFMA (all pairs at
+//   once, J = I + K + K^2/2, see below) usually reach the certificate; then
 //   parallel cyclic Jacobi on A (round-robin pair order, all K/2 rotations of a step at once:
 //   a row pass and a column pass, accumulated into V) until a certificate holds: every off-diagonal entry in a row or column
 //   whose diagonal exceeds 0.999 is at most 1e-6 ||A||_F (about the FP32 rounding level of
@@ -147,6 +149,51 @@ __device__ inline void mfma_kk(const float *A, int as, const float *B, int bs, i
   }
 }
 
+// C = op(A) B as in mfma_kk, but each wave keeps its bands (at most kHold of four tiles) in
+// registers, so that after a barrier the result may overwrite one of the operands.
+constexpr int kHold = 2;
+static_assert(7 * 2 <= kHold * kNW, "K <= 112: 7 row tiles x 2 bands of four column tiles");
+template <bool TA>
+__device__ inline void mfma_kk_hold(const float *A, int as, const float *B, int bs, int K,
+                                    int wave, int i16, int g4, f4 acc[kHold][4]) {
+  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
+#pragma unroll
+  for (int m = 0; m < kHold; ++m) {
+    const int t = wave + kNW * m;
+    if (t < nt * nh) {
+      const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
+      mfma_band<TA, 4>(A, as, B, bs, K, K, K, I, J0, i16, g4, acc[m]);
+    }
+  }
+}
+
+template <typename Out>
+__device__ inline void hold_release(int K, int wave, int i16, int g4, const f4 acc[kHold][4],
+                                    Out out) {
+  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
+#pragma unroll
+  for (int m = 0; m < kHold; ++m) {
+    const int t = wave + kNW * m;
+    if (t < nt * nh) {
+      const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int cc = 16 * (J0 + j) + i16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * I + 4 * g4 + v;
+          if (r < K && cc < K) out(r, cc, acc[m][j][v]);
+        }
+      }
+    }
+  }
+}
+
+// Simultaneous rotation steps before the cyclic sweeps (warm-started iterations): at most this
+// many, each damped to ||K||_F <= kSimCap.
+constexpr int kSimSteps = 12;
+constexpr float kSimCap = 0.7f;
+
 // One rotation of a Jacobi step: J = [[c, s], [-s, c]] on the index pair p < q.
 struct __align__(16) Rot {
   float c, s;
@@ -168,6 +215,11 @@ __device__ inline void store_chunk(const float y[kStage], int K, int srow, int s
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
     if (srow + kRowStep * k < K) T[(srow + kRowStep * k) * ts + scol] = y[k];
+}
+
+// The block's copy of its Gram matrix (K x K, row-major) in a.Gg.
+__device__ inline const float *Ggb_all(const BigArgs &a, long long blk, int K) {
+  return a.Gg + blk * (long long)K * K;
 }
 
 }  // namespace
@@ -265,7 +317,9 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
         }
       }
     }
-    // result layout: lane i + 16 g, register v holds tile entry (4 g + v, i)
+    // result layout: lane i + 16 g, register v holds tile entry (4 g + v, i); a copy of the
+    // Gram goes to the block's slot of a.Gg (when given) for the re-derivation of A below
+    float *Ggb = a.Gg ? a.Gg + blk * (long long)K * K : nullptr;
 #pragma unroll
     for (int m = 0; m < kGramTiles; ++m) {
       if (wave + kNW * m < ntiles) {
@@ -276,6 +330,10 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           if (r < K && c < K) {
             G[r * KS + c] = gacc[m][v];
             if (tI[m] != tJ[m]) G[c * KS + r] = gacc[m][v];
+            if (Ggb) {
+              Ggb[r * K + c] = gacc[m][v];
+              if (tI[m] != tJ[m]) Ggb[c * K + r] = gacc[m][v];
+            }
           }
         }
       }
@@ -329,9 +387,10 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   const int wpg = (K + 63) >> 6, ngV = kNW / wpg, cpw = (K + wpg - 1) / wpg;
   const int vkg = wave / wpg, vi = (wave - vkg * wpg) * cpw + lane, viK = vi * KS;
   const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
-  int sweeps = 0;
-  for (; sweeps < a.max_sweeps; ++sweeps) {
-    // certificate (see the header): one thread per row
+  // certificate (see the header): four threads per row; marks the rows that fail it (all rows
+  // once `all_hot`) and returns whether any does, with the tolerance in `tol`
+  float tol = 0.f;
+  auto certify = [&](bool all_hot) -> bool {
     float fro = 0.f;
 #pragma unroll 4
     for (int e = tid; e < K * K; e += kBT) {
@@ -345,7 +404,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     float fsum = 0.f;
 #pragma unroll
     for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
-    const float tol = 1e-6f * sqrtf(fsum);
+    tol = 1e-6f * sqrtf(fsum);
     if (tid < 4 * K) {  // four consecutive lanes per row, columns interleaved
       const int r = tid >> 2, part = tid & 3;
       const float dr = G[r * KS + r];
@@ -363,13 +422,116 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       if (part == 0) {
         const bool fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
         if (fail) atomicOr(&flag, 1);
-        hot[r] = fail || sweeps >= kRestricted;
+        hot[r] = fail || all_hot;
       }
     }
     __syncthreads();
     const int notyet = flag;
     __syncthreads();
-    if (!notyet) break;
+    return notyet != 0;
+  };
+
+  // ---- simultaneous rotations on MFMA (warm-started iterations). With the previous basis
+  // the off-diagonal entries of A are small, and one step with the angles of all pairs at
+  // once removes them to second order: K_ij = tan(theta_ij) of the 2 x 2 rotation that zeroes
+  // A_ij, for the pairs with a row that fails the certificate (K exactly skew), damped to
+  // ||K||_F <= kSimCap; J = I + K + K^2 / 2; A <- J^T A J, V <- V J. J^T A J and V J
+  // transform together, so A stays V^T G V; only V drifts from orthonormal, by K^4 / 4 per step
+  // (J^T J = I + K^4 / 4). After a step with ||K||_F > 0.01 (drift above 2.5e-9) V is
+  // re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4) and A
+  // re-derived from the Gram copy, so the certificate is always judged on V^T G V of an
+  // orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
+  int ssteps = 0;
+  if (!a.first && a.Gg) {
+    const float *Gb = Ggb_all(a, blk, K);
+    for (; ssteps < kSimSteps; ++ssteps) {
+      if (!certify(false)) break;
+      float kf2 = 0.f;
+      for (int e = tid; e < K * K; e += kBT) {
+        const int r = e / K, c = e - r * K;
+        float t = 0.f;
+        if (r != c && (hot[r] || hot[c])) {
+          const float arc = G[r * KS + c], den = G[c * KS + c] - G[r * KS + r];
+          const float sg = (den > 0.f || (den == 0.f && r < c)) ? 1.f : -1.f;
+          const float q = fabsf(den) + sqrtf(fmaf(den, den, 4.f * arc * arc));
+          t = q > 0.f ? 2.f * arc * sg / q : 0.f;
+        }
+        T3[r * KS + c] = t;
+        kf2 = fmaf(t, t, kf2);
+      }
+      for (int mm = 32; mm >= 1; mm >>= 1) kf2 += __shfl_xor(kf2, mm);
+      __syncthreads();  // red[] is free again (the certificate has read it)
+      if ((tid & 63) == 0) red[tid >> 6] = kf2;
+      __syncthreads();
+      float ksum = 0.f;
+#pragma unroll
+      for (int w = 0; w < kNW; ++w) ksum += red[w];
+      const float sc = ksum > kSimCap * kSimCap ? kSimCap * rsqrtf(ksum) : 1.f;
+      const bool rough = ksum * sc * sc > 1e-4f;
+      f4 acc[kHold][4];
+      // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K
+      mfma_kk_hold<true>(T3, KS, T3, KS, K, wave, i16, g4, acc);
+      __syncthreads();
+      hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) {
+        T3[r * KS + c] = (r == c ? 1.f : 0.f) + sc * T3[r * KS + c] - 0.5f * sc * sc * x;
+      });
+      __syncthreads();
+      mfma_kk_hold<false>(V, KS, T3, KS, K, wave, i16, g4, acc);  // V J
+      __syncthreads();
+      hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { V[r * KS + c] = x; });
+      __syncthreads();
+      if (rough) {
+        // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound ||K||_F^4 / 4, mapped by
+        // e -> 3 e^2 / 4 per step, is below 1e-8, then A = V^T G V from the Gram copy
+        const float kk = ksum * sc * sc;
+        float drift = 0.75f * (0.25f * kk * kk) * (0.25f * kk * kk);
+        int nns = 1;
+        while (drift > 1e-8f && nns < 4) {
+          drift = 0.75f * drift * drift;
+          ++nns;
+        }
+        for (int ns = 0; ns < nns; ++ns) {
+          mfma_kk<true>(V, KS, V, KS, K, wave, i16, g4,
+                        [&](int r, int c, float x) { T3[r * KS + c] = x; });
+          __syncthreads();
+          mfma_kk_hold<false>(V, KS, T3, KS, K, wave, i16, g4, acc);
+          __syncthreads();
+          hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) {
+            V[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x;
+          });
+          __syncthreads();
+        }
+        mfma_kk<false>(Gb, K, V, KS, K, wave, i16, g4,
+                       [&](int r, int c, float x) { T3[r * KS + c] = x; });
+        __syncthreads();
+        mfma_kk<true>(V, KS, T3, KS, K, wave, i16, g4,
+                      [&](int r, int c, float x) { G[r * KS + c] = x; });
+        __syncthreads();
+      } else {
+        mfma_kk_hold<false>(G, KS, T3, KS, K, wave, i16, g4, acc);  // A J
+        __syncthreads();
+        hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { G[r * KS + c] = x; });
+        __syncthreads();
+        mfma_kk_hold<true>(T3, KS, G, KS, K, wave, i16, g4, acc);   // J^T (A J)
+        __syncthreads();
+        hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { G[r * KS + c] = x; });
+        __syncthreads();
+      }
+      for (int e = tid; e < K * K; e += kBT) {  // symmetrise exactly
+        const int r = e / K, c = e - r * K;
+        if (r < c) {
+          const float mv = 0.5f * (G[r * KS + c] + G[c * KS + r]);
+          G[r * KS + c] = mv;
+          G[c * KS + r] = mv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  int sweeps = 0;
+  for (; sweeps < a.max_sweeps; ++sweeps) {
+    if (!certify(sweeps >= kRestricted)) break;
     const float skip = 0.1f * tol;
     for (int s = 0; s < m - 1; ++s) {
       // rotation angles; a pair rotates only if a row of it failed the certificate at the
@@ -471,6 +633,8 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     atomicMax(&a.sc->max_sweeps, sweeps);
     atomicAdd(&a.sc->step_sum, (unsigned long long)sweeps);  // sweeps per clipped block
     atomicAdd(&a.sc->step_blocks, 1ull);
+    atomicAdd(&a.sc->sweep_sum, (unsigned long long)ssteps);  // simultaneous steps
+    atomicAdd(&a.sc->sweep_waves, 1ull);
     if (sweeps == a.max_sweeps) atomicAdd(&a.sc->fallback_blocks, 1ull);  // not certified
   }
   __syncthreads();

@@ -195,6 +195,8 @@ struct BigArgs {
   float gY;
   float *Y;   // [block][K][ncol]
   float *V;   // [block][K][K] eigenbasis, kept across iterations
+  float *Gg;  // [block][K][K] copy of each block's Gram matrix (nullable: no simultaneous
+              // rotation steps before the cyclic sweeps)
   int first;  // V is still the identity
   int max_sweeps;
   DevScalars *sc;
