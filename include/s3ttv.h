@@ -87,10 +87,11 @@ typedef struct {
  *    certified by the warm start to the Jacobi. The result does not depend on it beyond
  *    rounding; it only moves work between the two solvers. At most 255.
  *  gram_precision: S3TTV_GRAM_FP32 (default), S3TTV_GRAM_BF16 or S3TTV_GRAM_FP16: input
- *    precision of the per-block Gram products Y' Y'^T on MFMA from the second iteration on
- *    (accumulation is FP32; the eigen-solve, the clip W Y' and every update stay FP32). The
- *    reduced modes trade the accuracy of W (inputs rounded to 8 or 11 significand bits) for
- *    fewer MFMA instructions; see the error report of the tests.
+ *    precision of the per-block Gram products Y' Y'^T on MFMA in the one-pass block kernel
+ *    (blocks of at most 16 rows, N3 <= 128; other shapes always sum in FP32). Accumulation is
+ *    FP32, followed by one FP32 refinement of the eigenvectors; the clip W Y' and every update
+ *    stay FP32. The reduced modes round the Gram inputs to 8 or 11 significand bits for fewer
+ *    MFMA instructions; see the error report of the tests.
  *  regularizer: the term minimised in place of S3TTV on the same P-PDS skeleton (Sec. IV-A
  *    compares methods this way): S3TTV_REG_S3TTV (default, Prob. (18)),
  *    S3TTV_REG_STV (sum_l ||P_l D u||_*, blocks of first-order differences),
@@ -138,7 +139,7 @@ enum {
                          cannot read them itself */
   S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) and the gradient field */
   S3TTV_K_FINAL = 8,  /* scalar reductions, stop rule */
-  S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks for iterations 2.. (N3 <= 128): steps 9-10
+  S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks per iteration (N3 <= 128): steps 9-10
                          (Gram, eigen-solve, clip) and the overlap-add on MFMA */
   S3TTV_K_COUNT = 10
 };
@@ -152,11 +153,11 @@ typedef struct {
   double dv_t;          /* ||D_v t||_2 of the result */
   int32_t eig_max_sweeps; /* largest per-lane Jacobi sweep count of any wavefront of blocks */
   float eig_avg_sweeps;   /* per-lane Jacobi sweeps per wavefront that ran them, averaged */
-  float eig_avg_steps;    /* MFMA rotation steps per block, averaged over iterations 2..iters */
+  float eig_avg_steps;    /* MFMA rotation steps per block, averaged over the iterations */
   int32_t eig_max_steps;  /* largest MFMA rotation step count of one block */
-  int64_t eig_fallback_blocks; /* blocks of iterations 2..iters the MFMA rotations could not
-                                  certify, finished by the per-lane Jacobi (iteration 1 always
-                                  solves every block with the per-lane Jacobi) */
+  int64_t eig_fallback_blocks; /* blocks the MFMA rotations could not certify, summed over
+                                  the iterations, finished by the per-lane Jacobi (the first
+                                  iteration starts the rotations from the identity basis) */
   /* For K = k1 k2 > 16 (one workgroup per block: simultaneous rotation steps on MFMA, then
      cyclic Jacobi sweeps, on the block Gram in the basis kept from the previous iteration):
      eig_avg_sweeps is the simultaneous rotation steps per block that needed the eigen-solve

@@ -325,7 +325,7 @@ struct Timer {
 // One problem of a solve: plan, kernel arguments and the caller's buffers.
 struct Problem {
   Plan pl;
-  BlockArgs ba, bw;  // block-pass arguments: cold (first iteration) and warm
+  BlockArgs bw;  // block-pass arguments (MFMA eigen-solve from the stored basis)
   bool fused = false;
   const s3ttv_params *prm = nullptr;
   const float *v = nullptr, *u0 = nullptr, *s0 = nullptr, *t0 = nullptr;
@@ -366,10 +366,9 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
   pr.u = u;
   pr.s = s;
   pr.t = t;
-  // First iteration: the stored basis is the identity, so every block is solved by the
-  // per-lane Jacobi (cold). Later iterations diagonalise on MFMA from the previous basis.
-  pr.ba = block_args(pl);
-  pr.bw = pr.ba;
+  // Every iteration diagonalises on MFMA from the stored basis (the identity before the
+  // first); blocks the rotations cannot certify go to the per-lane Jacobi.
+  pr.bw = block_args(pl);
   pr.bw.eflag = pl.eflag;
   pr.bw.estat = pl.estat;
   pr.bw.gram_prec = params->gram_precision;
@@ -383,7 +382,6 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
 // Scalars and block arguments point at sc (the batched solve keeps them side by side).
 void set_scalars(Problem &pr, DevScalars *sc) {
   pr.pl.sc = sc;
-  pr.ba.sc = sc;
   pr.bw.sc = sc;
 }
 
@@ -464,18 +462,19 @@ int32_t enqueue_iteration(const Problem &pr, int it, Timer &tm, hipStream_t st) 
     TIMED(S3TTV_K_FINAL, launch_finalize(pl, false, st));
     return S3TTV_OK;
   }
-  if (it > 0 && pr.fused) {
+  // every iteration diagonalises on MFMA from the stored basis (the identity before the first),
+  // the per-lane Jacobi taking only the blocks that rotation cannot certify
+  if (pr.fused) {
     TIMED(S3TTV_K_BLOCK, launch_block_fused(pr.bw, st));
     TIMED(S3TTV_K_EIG, launch_eig(pr.bw, st));
     TIMED(S3TTV_K_EIG, launch_fixup(pr.bw, st));
   } else {
-    const BlockArgs &bk = it == 0 ? pr.ba : pr.bw;
-    TIMED(S3TTV_K_GRAM, launch_gram(bk, st));
-    TIMED(S3TTV_K_EIG, launch_eig(bk, st));
-    TIMED(S3TTV_K_APPLY, launch_apply(bk, st));
+    TIMED(S3TTV_K_GRAM, launch_gram(pr.bw, st));
+    TIMED(S3TTV_K_EIG, launch_eig(pr.bw, st));
+    TIMED(S3TTV_K_APPLY, launch_apply(pr.bw, st));
   }
   if (!pl.zfold) TIMED(S3TTV_K_ZSUM, launch_zsum(pl, st));
-  TIMED(S3TTV_K_FINAL, launch_finalize(pl, it > 0, st));
+  TIMED(S3TTV_K_FINAL, launch_finalize(pl, true, st));
   return S3TTV_OK;
 }
 
@@ -975,7 +974,7 @@ int32_t s3ttv_solve_batched(int32_t n, const s3ttv_shape *shapes, const s3ttv_pa
 
   int32_t r = S3TTV_OK;
   if (!active.empty() && max_iter > 0) {
-    // iteration 1 (cold block pass) directly, then graphs of kBatchSpan iterations each (an
+    // iteration 1 directly, then graphs of kBatchSpan iterations each (an
     // even span keeps the buffer parity of the captured launches); problems stop on the
     // device (stop rule or their own max_iter), their later launches exit at once
     r = enqueue_span(0, 1);

@@ -89,100 +89,130 @@ __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
   q = max(x, y);
 }
 
-// A band of NJ 16 x 16 tiles (rows 16 I .., columns 16 (J0 + j) ..) of C = op(A) B over
-// k < kd on v_mfma_f32_16x16x4_f32, with op(A)[r][k] = TA ? A[k * as + r] : A[r * as + k] and
-// B[k][c] = B[k * bs + c]. Lane i + 16 g supplies op(A)[16 I + i][k0 + g] (shared by the
-// band) and B[k0 + g][16 (J0 + j) + i]; result lane i + 16 g, register v of tile j holds
-// C[16 I + 4 g + v][16 (J0 + j) + i]. Row and column indices are clamped to nr - 1, nc - 1
-// (those outputs are not used) and k >= kd contributes zero, so every load is unconditional.
+// A band of NJ 16 x 16 tiles (rows 16 I .., columns 16 (J0 + j) .., j < nj <= NJ) of
+// C = op(A) B over k < kd on v_mfma_f32_16x16x4_f32, with op(A)[r][k] = TA ? A[k * as + r] :
+// A[r * as + k] and B[k][c] = B[k * bs + c]. Lane i + 16 g supplies op(A)[16 I + i][k0 + g]
+// (shared by the band) and B[k0 + g][16 (J0 + j) + i]; result lane i + 16 g, register v of
+// tile j holds C[16 I + 4 g + v][16 (J0 + j) + i]. Row and column indices are clamped to
+// nr - 1, nc - 1 (those outputs are not used) and k >= kd contributes zero, so every load is
+// unconditional. The loop is software-pipelined by hand (two register sets): the compiler does
+// not unroll loops around MFMA.
 template <bool TA, int NJ>
-__device__ inline void mfma_band(const float *A, int as, const float *B, int bs, int kd, int nr,
-                                 int nc, int I, int J0, int i16, int g4, f4 acc[NJ]) {
+__device__ __forceinline__ void mfma_band(const float *A, int as, const float *B, int bs, int kd, int nr,
+                                 int nc, int I, int J0, int nj, int i16, int g4, f4 acc[NJ]) {
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
   const int r = min(16 * I + i16, nr - 1);
   int c[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) c[j] = min(16 * (J0 + j) + i16, nc - 1);
-  // k in groups of 16 (four MFMA steps unrolled by hand: the compiler does not partially
-  // unroll loops around MFMA), the tail past kd masked to zero
-  for (int k16 = 0; k16 < kd; k16 += 16) {
-    float av[4], bv[4][NJ];
+  // one MFMA k-step (k0 .. k0 + 3) per load; the next step's operands are loaded while the
+  // current step's MFMAs run
+  const int nk = (kd + 3) >> 2;
+  float a0, a1, b0[NJ], b1[NJ];
+  auto load = [&](int k4, float &av, float (&bv)[NJ]) {
+    const int kk = 4 * k4 + g4;
+    const int k = min(kk, kd - 1);
+    const float x = TA ? A[k * as + r] : A[r * as + k];
+    av = kk < kd ? x : 0.f;
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int kk = k16 + 4 * st + g4;
-      const int k = min(kk, kd - 1);
-      const float a0 = TA ? A[k * as + r] : A[r * as + k];
-      av[st] = kk < kd ? a0 : 0.f;
+    for (int j = 0; j < NJ; ++j)
+      if (j < nj) bv[j] = B[k * bs + c[j]];
+  };
+  auto step = [&](float av, const float (&bv)[NJ]) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) bv[st][j] = B[k * bs + c[j]];
-    }
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int j = 0; j < NJ; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][j], acc[j], 0, 0, 0);
+    for (int j = 0; j < NJ; ++j)
+      if (j < nj) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[j], acc[j], 0, 0, 0);
+  };
+  load(0, a0, b0);
+  for (int k4 = 0; k4 < nk; k4 += 2) {
+    const bool more = k4 + 1 < nk;
+    if (more) load(k4 + 1, a1, b1);
+    step(a0, b0);
+    if (k4 + 2 < nk) load(k4 + 2, a0, b0);
+    if (more) step(a1, b1);
   }
 }
 
-// C = op(A) B for K x K operands (row strides as, bs): bands of four tiles (row tile I,
-// column tiles 4 h .. 4 h + 3) dealt round-robin to the waves; out(r, c, value) is
-// applied to every entry in range.
-template <bool TA, typename Out>
-__device__ inline void mfma_kk(const float *A, int as, const float *B, int bs, int K, int wave,
-                               int i16, int g4, Out out) {
-  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
-#pragma unroll 1
-  for (int t = wave; t < nt * nh; t += kNW) {
-    const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
-    f4 acc[4];
-    mfma_band<TA, 4>(A, as, B, bs, K, K, K, I, J0, i16, g4, acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cc = 16 * (J0 + j) + i16;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 16 * I + 4 * g4 + v;
-        if (r < K && cc < K) out(r, cc, acc[j][v]);
-      }
-    }
-  }
-}
+// K x K products C = op(A) B (K <= 112, so at most kMaxT = 7 tiles of 16 per side), computed
+// into registers and written by a separate release call, so that after a barrier the result
+// may overwrite one of its operands.
+constexpr int kMaxT = 7;
+static_assert(kBigMax <= 16 * kMaxT && kMaxT <= kNW, "one row of tiles per wave");
 
-// C = op(A) B as in mfma_kk, but each wave keeps its bands (at most kHold of four tiles) in
-// registers, so that after a barrier the result may overwrite one of the operands.
-constexpr int kHold = 2;
-static_assert(7 * 2 <= kHold * kNW, "K <= 112: 7 row tiles x 2 bands of four column tiles");
+// General product: wave w < nt computes row tile I = w against every column tile (the A
+// operand is read once per row).
 template <bool TA>
-__device__ inline void mfma_kk_hold(const float *A, int as, const float *B, int bs, int K,
-                                    int wave, int i16, int g4, f4 acc[kHold][4]) {
-  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
+__device__ __forceinline__ void prod_rows(const float *A, int as, const float *B, int bs, int K, int wave,
+                                 int i16, int g4, f4 acc[kMaxT]) {
+  const int nt = (K + 15) >> 4;
+  if (wave < nt) mfma_band<TA, kMaxT>(A, as, B, bs, K, K, K, wave, 0, nt, i16, g4, acc);
+}
+
+template <typename Out>
+__device__ __forceinline__ void release_rows(int K, int wave, int i16, int g4, const f4 acc[kMaxT],
+                                    Out out) {
+  const int nt = (K + 15) >> 4;
+  if (wave >= nt) return;
 #pragma unroll
-  for (int m = 0; m < kHold; ++m) {
+  for (int j = 0; j < kMaxT; ++j) {
+    const int cc = 16 * j + i16;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * wave + 4 * g4 + v;
+      if (j < nt && r < K && cc < K) out(r, cc, acc[j][v]);
+    }
+  }
+}
+
+// Product with a symmetric result (V^T V, V^T G V, K^T K, J^T A J): only the tiles on and
+// above the diagonal are formed, dealt round-robin to the waves (at most kSymHold each), and
+// each entry above the diagonal is written to both (r, c) and (c, r), so the result is exactly
+// symmetric.
+constexpr int kSymHold = (kMaxT * (kMaxT + 1) / 2 + kNW - 1) / kNW;
+
+// Upper tile number t (row-major over I <= J) -> (I, J).
+__device__ inline void upper_tile(int t, int nt, int &I, int &J) {
+  I = 0;
+  while (t >= nt - I) {
+    t -= nt - I;
+    ++I;
+  }
+  J = I + t;
+}
+
+template <bool TA>
+__device__ __forceinline__ void prod_sym(const float *A, int as, const float *B, int bs, int K, int wave,
+                                int i16, int g4, f4 acc[kSymHold]) {
+  const int nt = (K + 15) >> 4, nup = nt * (nt + 1) / 2;
+#pragma unroll
+  for (int m = 0; m < kSymHold; ++m) {
     const int t = wave + kNW * m;
-    if (t < nt * nh) {
-      const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
-      mfma_band<TA, 4>(A, as, B, bs, K, K, K, I, J0, i16, g4, acc[m]);
+    if (t < nup) {
+      int I, J;
+      upper_tile(t, nt, I, J);
+      mfma_band<TA, 1>(A, as, B, bs, K, K, K, I, J, 1, i16, g4, &acc[m]);
     }
   }
 }
 
 template <typename Out>
-__device__ inline void hold_release(int K, int wave, int i16, int g4, const f4 acc[kHold][4],
-                                    Out out) {
-  const int nt = (K + 15) >> 4, nh = (nt + 3) >> 2;
+__device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4, const f4 acc[kSymHold],
+                                   Out out) {
+  const int nt = (K + 15) >> 4, nup = nt * (nt + 1) / 2;
 #pragma unroll
-  for (int m = 0; m < kHold; ++m) {
+  for (int m = 0; m < kSymHold; ++m) {
     const int t = wave + kNW * m;
-    if (t < nt * nh) {
-      const int I = t / nh, J0 = 4 * (t - (t / nh) * nh);
+    if (t < nup) {
+      int I, J;
+      upper_tile(t, nt, I, J);
+      const int cc = 16 * J + i16;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int cc = 16 * (J0 + j) + i16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * I + 4 * g4 + v;
-          if (r < K && cc < K) out(r, cc, acc[m][j][v]);
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * I + 4 * g4 + v;
+        if (r < K && cc < K && r <= cc) {
+          out(r, cc, acc[m][v]);
+          if (r != cc) out(cc, r, acc[m][v]);
         }
       }
     }
@@ -361,23 +391,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     V[r * KS + c] = a.first ? (r == c ? 1.f : 0.f) : Vg[e];
   }
   __syncthreads();
-  // ---- A = V^T (G V): H = G V into T3, then A into G
-  mfma_kk<false>(G, KS, V, KS, K, wave, i16, g4,
-                 [&](int r, int c, float x) { T3[r * KS + c] = x; });
-  __syncthreads();
-  mfma_kk<true>(V, KS, T3, KS, K, wave, i16, g4,
-                [&](int r, int c, float x) { G[r * KS + c] = x; });
-  __syncthreads();
-  // symmetrise exactly
-  for (int e = tid; e < K * K; e += kBT) {
-    const int r = e / K, c = e - r * K;
-    if (r < c) {
-      const float m = 0.5f * (G[r * KS + c] + G[c * KS + r]);
-      G[r * KS + c] = m;
-      G[c * KS + r] = m;
-    }
+  // ---- A = V^T (G V): H = G V into T3, then A into G (exactly symmetric). G is symmetric, so
+  // its operand is read as G^T (16 consecutive entries of a row per lane group)
+  {
+    f4 hr[kMaxT];
+    prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
+    release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+    __syncthreads();
+    f4 hs[kSymHold];
+    prod_sym<true>(V, KS, T3, KS, K, wave, i16, g4, hs);
+    release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
+    __syncthreads();
   }
-  __syncthreads();
 
   // ---- parallel cyclic Jacobi
   const int m = (K + 1) & ~1;  // even; index K (if m > K) is a dummy whose rotation is identity
@@ -468,17 +493,17 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       for (int w = 0; w < kNW; ++w) ksum += red[w];
       const float sc = ksum > kSimCap * kSimCap ? kSimCap * rsqrtf(ksum) : 1.f;
       const bool rough = ksum * sc * sc > 1e-4f;
-      f4 acc[kHold][4];
+      f4 hr[kMaxT], hs[kSymHold];
       // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K
-      mfma_kk_hold<true>(T3, KS, T3, KS, K, wave, i16, g4, acc);
+      prod_sym<true>(T3, KS, T3, KS, K, wave, i16, g4, hs);
       __syncthreads();
-      hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) {
+      release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) {
         T3[r * KS + c] = (r == c ? 1.f : 0.f) + sc * T3[r * KS + c] - 0.5f * sc * sc * x;
       });
       __syncthreads();
-      mfma_kk_hold<false>(V, KS, T3, KS, K, wave, i16, g4, acc);  // V J
+      prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);  // V J
       __syncthreads();
-      hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { V[r * KS + c] = x; });
+      release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { V[r * KS + c] = x; });
       __syncthreads();
       if (rough) {
         // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound ||K||_F^4 / 4, mapped by
@@ -491,41 +516,40 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           ++nns;
         }
         for (int ns = 0; ns < nns; ++ns) {
-          mfma_kk<true>(V, KS, V, KS, K, wave, i16, g4,
-                        [&](int r, int c, float x) { T3[r * KS + c] = x; });
+          prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);  // V^T V
+          release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { T3[r * KS + c] = x; });
           __syncthreads();
-          mfma_kk_hold<false>(V, KS, T3, KS, K, wave, i16, g4, acc);
+          prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);
           __syncthreads();
-          hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) {
+          release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) {
             V[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x;
           });
           __syncthreads();
         }
-        mfma_kk<false>(Gb, K, V, KS, K, wave, i16, g4,
-                       [&](int r, int c, float x) { T3[r * KS + c] = x; });
+        // the Gram copy back into LDS (A is re-derived, its old value is not needed), then
+        // H = G V (G symmetric, read as G^T) and A = V^T H
+        for (int e = tid; e < K * K; e += kBT) {
+          const int r = e / K, c = e - r * K;
+          G[r * KS + c] = Gb[e];
+        }
         __syncthreads();
-        mfma_kk<true>(V, KS, T3, KS, K, wave, i16, g4,
-                      [&](int r, int c, float x) { G[r * KS + c] = x; });
+        prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
+        release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+        __syncthreads();
+        prod_sym<true>(V, KS, T3, KS, K, wave, i16, g4, hs);
+        release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
         __syncthreads();
       } else {
-        mfma_kk_hold<false>(G, KS, T3, KS, K, wave, i16, g4, acc);  // A J
+        prod_rows<true>(G, KS, T3, KS, K, wave, i16, g4, hr);  // A J (A symmetric)
         __syncthreads();
-        hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { G[r * KS + c] = x; });
+        release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { G[r * KS + c] = x; });
         __syncthreads();
-        mfma_kk_hold<true>(T3, KS, G, KS, K, wave, i16, g4, acc);   // J^T (A J)
+        prod_sym<true>(T3, KS, G, KS, K, wave, i16, g4, hs);  // J^T (A J)
         __syncthreads();
-        hold_release(K, wave, i16, g4, acc, [&](int r, int c, float x) { G[r * KS + c] = x; });
+        release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
         __syncthreads();
       }
-      for (int e = tid; e < K * K; e += kBT) {  // symmetrise exactly
-        const int r = e / K, c = e - r * K;
-        if (r < c) {
-          const float mv = 0.5f * (G[r * KS + c] + G[c * KS + r]);
-          G[r * KS + c] = mv;
-          G[c * KS + r] = mv;
-        }
-      }
-      __syncthreads();
+      // A is exactly symmetric again (written from the upper tiles only)
     }
   }
 
@@ -638,17 +662,22 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     if (sweeps == a.max_sweeps) atomicAdd(&a.sc->fallback_blocks, 1ull);  // not certified
   }
   __syncthreads();
-  // ---- Newton-Schulz: M = V^T V (T3), V <- 1.5 V - 0.5 V M (via G)
-  mfma_kk<true>(V, KS, V, KS, K, wave, i16, g4,
-                [&](int r, int c, float x) { T3[r * KS + c] = x; });
-  __syncthreads();
-  mfma_kk<false>(V, KS, T3, KS, K, wave, i16, g4,
-                 [&](int r, int c, float x) { G[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x; });
-  __syncthreads();
+  // ---- Newton-Schulz: M = V^T V (T3), V <- 1.5 V - 0.5 V M, stored for the next iteration
+  {
+    f4 hr[kMaxT], hs[kSymHold];
+    prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);
+    release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+    __syncthreads();
+    prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);
+    __syncthreads();
+    release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) {
+      V[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x;
+    });
+    __syncthreads();
+  }
   for (int e = tid; e < K * K; e += kBT) {
     const int r = e / K, c = e - r * K;
-    V[r * KS + c] = G[r * KS + c];
-    Vg[e] = G[r * KS + c];
+    Vg[e] = V[r * KS + c];
   }
   // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks: P = V^T Y' per
   // chunk on MFMA tiles; wave w owns the row tiles I = w, w + 4 (both column tiles of each),
@@ -668,7 +697,8 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
         const int I = wave + kNW * m;
         if (I < nt) {
           f4 acc[kChunk / 16];
-          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
+          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, kChunk / 16, i16, g4,
+                                       acc);
 #pragma unroll
           for (int J = 0; J < kChunk / 16; ++J) {
 #pragma unroll

@@ -7,10 +7,12 @@
 // the projection of Y'_l onto the unit spectral-norm ball. With K <= 2B rows this is
 //   Y+_l = W_l Y'_l,   W_l = I - sum_{lambda_k > 1} (1 - lambda_k^{-1/2}) v_k v_k^T,
 // where (lambda_k, v_k) are the eigenpairs of the K x K Gram matrix G_l = Y'_l Y'_l^T.
-// Three kernels: Gram on MFMA (k_gram), which in the warm-started solver also diagonalises the
-// Gram matrix on MFMA (simultaneous Jacobi rotations from the previous eigenbasis) and forms
-// W_l; a per-lane cyclic Jacobi eigen-solve (k_eig) for cold starts and for the blocks the MFMA
-// rotations cannot certify; and W_l Y'_l on MFMA with a deterministic overlap-add (k_apply).
+// Three kernels: Gram on MFMA (k_gram), which in the solver also diagonalises the Gram matrix
+// on MFMA (simultaneous Jacobi rotations from the previous eigenbasis, the identity before the
+// first iteration) and forms W_l; a per-lane cyclic Jacobi eigen-solve (k_eig) for the
+// stand-alone block operator and for the blocks the MFMA rotations cannot certify; and
+// W_l Y'_l on MFMA with a deterministic overlap-add (k_apply). With N3 <= 128 the solver runs
+// all of it in one pass (k_block_fused).
 //
 // Block storage ("apply layout", 16 rows x ncol columns per block, ncol = 2*Bp, column
 // c = comp*Bp + band): column tile t holds columns 16t..16t+15 as 64 lanes x 4 floats,
@@ -713,7 +715,10 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   const int zs = a.ncol + 16;
   // this wavefront's two transpose tiles (row stride 20 floats)
   float *tbw = zacc_f + (size_t)next * zs + wave * 640;
-  for (int e = threadIdx.x; e < next * zs; e += kFW * 64) zacc[e] = 0;
+  // zs and ncol are multiples of 4 (ncol of 32), so the accumulators are cleared and copied
+  // out 16 bytes per lane
+  int4 *zacc4 = reinterpret_cast<int4 *>(zacc_f);
+  for (int e = threadIdx.x; e < (next * zs) >> 2; e += kFW * 64) zacc4[e] = int4{0, 0, 0, 0};
   if (threadIdx.x == 0) next_anchor = kFW;
   // rows 4g+s of this lane: window offsets (fixed for the kernel); rows >= K are padding
   int ar[4], cr[4];
@@ -831,9 +836,16 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
         acc = mfma4(W[2], y[t][2], acc);
         acc = mfma4(W[3], y[t][3], acc);
         __builtin_nontemporal_store(acc, (f4 *)(Yl + t * 256));
+        // rows >= K are padding (their zo names the anchor pixel) and add nothing; the test
+        // is uniform over the wave when every row is real
+        if (a.K == kRows) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-          if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed_bounded(acc[s]));
+          for (int s = 0; s < 4; ++s) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed_bounded(acc[s]));
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (4 * g + s < a.K) atomicAdd(&zacc[zo[s] + 16 * t], to_fixed_bounded(acc[s]));
+        }
       }
     } else {
       // left to k_eig / k_fixup: keep Y'
@@ -846,10 +858,22 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   }
   flag_nonfinite(a.sc, bad);
   __syncthreads();
-  int *zp = a.zpart + (size_t)tile * next * a.ncol;
-  for (int e = threadIdx.x; e < next * a.ncol; e += kFW * 64) {
-    const int px = e / a.ncol, c = e - px * a.ncol;
-    zp[e] = zacc[px * zs + c];
+  // the tile's partial: a pixel row (ncol <= 16 NT <= 256 columns) per wave and trip, 16 bytes
+  // per lane, four rows in flight
+  int4 *zp4 = reinterpret_cast<int4 *>(a.zpart + (size_t)tile * next * a.ncol);
+  const int nc4 = a.ncol >> 2, zs4 = zs >> 2;
+  if (lane < nc4) {
+    for (int px = wave; px < next; px += 4 * kFW) {
+      // rows past the end read row 0 again and are not stored
+      const int p1 = px + kFW < next ? px + kFW : 0, p2 = px + 2 * kFW < next ? px + 2 * kFW : 0;
+      const int p3 = px + 3 * kFW < next ? px + 3 * kFW : 0;
+      const int4 v0 = zacc4[px * zs4 + lane], v1 = zacc4[p1 * zs4 + lane];
+      const int4 v2 = zacc4[p2 * zs4 + lane], v3 = zacc4[p3 * zs4 + lane];
+      zp4[(size_t)px * nc4 + lane] = v0;
+      if (p1) zp4[(size_t)p1 * nc4 + lane] = v1;
+      if (p2) zp4[(size_t)p2 * nc4 + lane] = v2;
+      if (p3) zp4[(size_t)p3 * nc4 + lane] = v3;
+    }
   }
 }
 
