@@ -376,6 +376,9 @@ int32_t prepare(Problem &pr, const s3ttv_shape *shape, const s3ttv_params *param
                         ? kDefaultEigSteps
                         : (params->eig_max_steps < 0 ? 0 : params->eig_max_steps);
   pr.fused = !pl.big && fused_supported(pr.bw) && fused_lds_bytes(pr.bw) <= kMaxLds;
+  // the separate Gram kernel sums in FP32 whatever was asked: its certificate takes the FP32
+  // tolerance
+  if (!pr.fused) pr.bw.gram_prec = 0;
   return S3TTV_OK;
 }
 

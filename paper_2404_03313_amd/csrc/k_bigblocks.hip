@@ -89,7 +89,7 @@ __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
   q = max(x, y);
 }
 
-// A band of NJ 16 x 16 tiles (rows 16 I .., columns 16 (J0 + j) .., j < nj <= NJ) of
+// A band of NJ 16 x 16 tiles (rows 16 I .., columns 16 (J0 + j) ..) of
 // C = op(A) B over k < kd on v_mfma_f32_16x16x4_f32, with op(A)[r][k] = TA ? A[k * as + r] :
 // A[r * as + k] and B[k][c] = B[k * bs + c]. Lane i + 16 g supplies op(A)[16 I + i][k0 + g]
 // (shared by the band) and B[k0 + g][16 (J0 + j) + i]; result lane i + 16 g, register v of
@@ -98,8 +98,9 @@ __device__ inline void rr_pair(int m, int s, int k, int &p, int &q) {
 // unconditional. The loop is software-pipelined by hand (two register sets): the compiler does
 // not unroll loops around MFMA.
 template <bool TA, int NJ>
-__device__ __forceinline__ void mfma_band(const float *A, int as, const float *B, int bs, int kd, int nr,
-                                 int nc, int I, int J0, int nj, int i16, int g4, f4 acc[NJ]) {
+__device__ __forceinline__ void mfma_band(const float *A, int as, const float *B, int bs, int kd,
+                                          int nr, int nc, int I, int J0, int i16, int g4,
+                                          f4 acc[NJ]) {
 #pragma unroll
   for (int j = 0; j < NJ; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
   const int r = min(16 * I + i16, nr - 1);
@@ -107,30 +108,29 @@ __device__ __forceinline__ void mfma_band(const float *A, int as, const float *B
 #pragma unroll
   for (int j = 0; j < NJ; ++j) c[j] = min(16 * (J0 + j) + i16, nc - 1);
   // one MFMA k-step (k0 .. k0 + 3) per load; the next step's operands are loaded while the
-  // current step's MFMAs run
+  // current step's MFMAs run. k past kd reads row kd - 1 and is zeroed at the MFMA (not at
+  // the load, which would make the loads wait)
   const int nk = (kd + 3) >> 2;
   float a0, a1, b0[NJ], b1[NJ];
   auto load = [&](int k4, float &av, float (&bv)[NJ]) {
-    const int kk = 4 * k4 + g4;
-    const int k = min(kk, kd - 1);
-    const float x = TA ? A[k * as + r] : A[r * as + k];
-    av = kk < kd ? x : 0.f;
+    const int k = min(4 * k4 + g4, kd - 1);
+    av = TA ? A[k * as + r] : A[r * as + k];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (j < nj) bv[j] = B[k * bs + c[j]];
+    for (int j = 0; j < NJ; ++j) bv[j] = B[k * bs + c[j]];
   };
-  auto step = [&](float av, const float (&bv)[NJ]) {
+  auto step = [&](int k4, float av, const float (&bv)[NJ]) {
+    const float a = 4 * k4 + g4 < kd ? av : 0.f;
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
-      if (j < nj) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[j], acc[j], 0, 0, 0);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[j], acc[j], 0, 0, 0);
   };
   load(0, a0, b0);
   for (int k4 = 0; k4 < nk; k4 += 2) {
     const bool more = k4 + 1 < nk;
     if (more) load(k4 + 1, a1, b1);
-    step(a0, b0);
+    step(k4, a0, b0);
     if (k4 + 2 < nk) load(k4 + 2, a0, b0);
-    if (more) step(a1, b1);
+    if (more) step(k4 + 1, a1, b1);
   }
 }
 
@@ -146,7 +146,8 @@ template <bool TA>
 __device__ __forceinline__ void prod_rows(const float *A, int as, const float *B, int bs, int K, int wave,
                                  int i16, int g4, f4 acc[kMaxT]) {
   const int nt = (K + 15) >> 4;
-  if (wave < nt) mfma_band<TA, kMaxT>(A, as, B, bs, K, K, K, wave, 0, nt, i16, g4, acc);
+  // tiles past nt (K <= 96) read clamped columns and are not released
+  if (wave < nt) mfma_band<TA, kMaxT>(A, as, B, bs, K, K, K, wave, 0, i16, g4, acc);
 }
 
 template <typename Out>
@@ -182,17 +183,44 @@ __device__ inline void upper_tile(int t, int nt, int &I, int &J) {
 }
 
 template <bool TA>
-__device__ __forceinline__ void prod_sym(const float *A, int as, const float *B, int bs, int K, int wave,
-                                int i16, int g4, f4 acc[kSymHold]) {
+__device__ __forceinline__ void prod_sym(const float *A, int as, const float *B, int bs, int K,
+                                         int wave, int i16, int g4, f4 acc[kSymHold]) {
   const int nt = (K + 15) >> 4, nup = nt * (nt + 1) / 2;
+  // all of the wave's tiles advance together, so their MFMA chains are independent; a tile
+  // past nup repeats tile 0 and is not released
+  int r[kSymHold], c[kSymHold];
 #pragma unroll
   for (int m = 0; m < kSymHold; ++m) {
+    int I, J;
     const int t = wave + kNW * m;
-    if (t < nup) {
-      int I, J;
-      upper_tile(t, nt, I, J);
-      mfma_band<TA, 1>(A, as, B, bs, K, K, K, I, J, 1, i16, g4, &acc[m]);
+    upper_tile(t < nup ? t : 0, nt, I, J);
+    r[m] = min(16 * I + i16, K - 1);
+    c[m] = min(16 * J + i16, K - 1);
+    acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int nk = (K + 3) >> 2;
+  float a0[kSymHold], b0[kSymHold], a1[kSymHold], b1[kSymHold];
+  auto load = [&](int k4, float (&av)[kSymHold], float (&bv)[kSymHold]) {
+    const int k = min(4 * k4 + g4, K - 1);
+#pragma unroll
+    for (int m = 0; m < kSymHold; ++m) {
+      av[m] = TA ? A[k * as + r[m]] : A[r[m] * as + k];
+      bv[m] = B[k * bs + c[m]];
     }
+  };
+  auto step = [&](int k4, const float (&av)[kSymHold], const float (&bv)[kSymHold]) {
+    const bool in = 4 * k4 + g4 < K;
+#pragma unroll
+    for (int m = 0; m < kSymHold; ++m)
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? av[m] : 0.f, bv[m], acc[m], 0, 0, 0);
+  };
+  load(0, a0, b0);
+  for (int k4 = 0; k4 < nk; k4 += 2) {
+    const bool more = k4 + 1 < nk;
+    if (more) load(k4 + 1, a1, b1);
+    step(k4, a0, b0);
+    if (k4 + 2 < nk) load(k4 + 2, a0, b0);
+    if (more) step(k4 + 1, a1, b1);
   }
 }
 
@@ -414,22 +442,34 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
   // certificate (see the header): four threads per row; marks the rows that fail it (all rows
   // once `all_hot`) and returns whether any does, with the tolerance in `tol`
-  float tol = 0.f;
+  float tol = -1.f;
   auto certify = [&](bool all_hot) -> bool {
-    float fro = 0.f;
+    if (tol < 0.f) {
+      // ||A||_F on the first call; rotations and the re-derivation of A from an orthonormal
+      // basis keep it (to rounding), so later calls reuse the tolerance
+      float fro = 0.f;
+      int r = tid / K, c = tid - (tid / K) * K;
+      const int dr = kBT / K, dc = kBT - (kBT / K) * K;
 #pragma unroll 4
-    for (int e = tid; e < K * K; e += kBT) {
-      const int r = e / K, c = e - r * K;
-      fro = fmaf(G[r * KS + c], G[r * KS + c], fro);
+      for (int e = tid; e < K * K; e += kBT) {
+        fro = fmaf(G[r * KS + c], G[r * KS + c], fro);
+        r += dr;
+        c += dc;
+        if (c >= K) {
+          c -= K;
+          ++r;
+        }
+      }
+      for (int mm = 32; mm >= 1; mm >>= 1) fro += __shfl_xor(fro, mm);
+      if ((tid & 63) == 0) red[tid >> 6] = fro;
+      __syncthreads();
+      float fsum = 0.f;
+#pragma unroll
+      for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
+      tol = 1e-6f * sqrtf(fsum);
     }
-    for (int mm = 32; mm >= 1; mm >>= 1) fro += __shfl_xor(fro, mm);
-    if ((tid & 63) == 0) red[tid >> 6] = fro;
     if (tid == 0) flag = 0;
     __syncthreads();
-    float fsum = 0.f;
-#pragma unroll
-    for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
-    tol = 1e-6f * sqrtf(fsum);
     if (tid < 4 * K) {  // four consecutive lanes per row, columns interleaved
       const int r = tid >> 2, part = tid & 3;
       const float dr = G[r * KS + r];
@@ -472,17 +512,29 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     for (; ssteps < kSimSteps; ++ssteps) {
       if (!certify(false)) break;
       float kf2 = 0.f;
-      for (int e = tid; e < K * K; e += kBT) {
-        const int r = e / K, c = e - r * K;
-        float t = 0.f;
-        if (r != c && (hot[r] || hot[c])) {
-          const float arc = G[r * KS + c], den = G[c * KS + c] - G[r * KS + r];
-          const float sg = (den > 0.f || (den == 0.f && r < c)) ? 1.f : -1.f;
-          const float q = fabsf(den) + sqrtf(fmaf(den, den, 4.f * arc * arc));
-          t = q > 0.f ? 2.f * arc * sg / q : 0.f;
+      {
+        // entry e = r K + c of this thread, stepped without divisions
+        int r = tid / K, c = tid - (tid / K) * K;
+        const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+#pragma unroll 4
+        for (int e = tid; e < K * K; e += kBT) {
+          float t = 0.f;
+          if (r != c && (hot[r] || hot[c])) {
+            // hardware square root and reciprocal: (c, r) gets exactly -t, so K stays skew
+            const float arc = G[r * KS + c], den = G[c * KS + c] - G[r * KS + r];
+            const float sg = (den > 0.f || (den == 0.f && r < c)) ? 1.f : -1.f;
+            const float q = fabsf(den) + __builtin_sqrtf(fmaf(den, den, 4.f * arc * arc));
+            t = q > 0.f ? (2.f * arc * sg) * __builtin_amdgcn_rcpf(q) : 0.f;
+          }
+          T3[r * KS + c] = t;
+          kf2 = fmaf(t, t, kf2);
+          r += dr;
+          c += dc;
+          if (c >= K) {
+            c -= K;
+            ++r;
+          }
         }
-        T3[r * KS + c] = t;
-        kf2 = fmaf(t, t, kf2);
       }
       for (int mm = 32; mm >= 1; mm >>= 1) kf2 += __shfl_xor(kf2, mm);
       __syncthreads();  // red[] is free again (the certificate has read it)
@@ -528,9 +580,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
         }
         // the Gram copy back into LDS (A is re-derived, its old value is not needed), then
         // H = G V (G symmetric, read as G^T) and A = V^T H
-        for (int e = tid; e < K * K; e += kBT) {
-          const int r = e / K, c = e - r * K;
-          G[r * KS + c] = Gb[e];
+        {
+          int r = tid / K, c = tid - (tid / K) * K;
+          const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+          for (int e = tid; e < K * K; e += kBT) {
+            G[r * KS + c] = Gb[e];
+            r += dr;
+            c += dc;
+            if (c >= K) {
+              c -= K;
+              ++r;
+            }
+          }
         }
         __syncthreads();
         prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
@@ -697,8 +758,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
         const int I = wave + kNW * m;
         if (I < nt) {
           f4 acc[kChunk / 16];
-          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, kChunk / 16, i16, g4,
-                                       acc);
+          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
 #pragma unroll
           for (int J = 0; J < kChunk / 16; ++J) {
 #pragma unroll

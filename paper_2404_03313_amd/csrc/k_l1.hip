@@ -186,7 +186,22 @@ __global__ __launch_bounds__(kNT) void k_l1_select(int level, double r0, double 
   unsigned long long *gs = hist->sig[ball][level - 1];
   const int nb = level_bins(level), shift = level_shift(level);
   const int per = nb / kNT;  // 8 or 2 bins per thread
-  const bool skip = sc->done || (level > 1 && !sc->active[ball]);
+  // thread t owns bins [nb - per*(t+1), nb - per*t), i.e. thread 0 the highest bins. Every
+  // global value the kernel needs is requested first, so their latencies overlap.
+  const int hi = nb - per * threadIdx.x;
+  unsigned long long sraw[8];
+  uint32_t craw[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+    if (m < per) {
+      sraw[m] = gs[hi - 1 - m];
+      craw[m] = gc[hi - 1 - m];
+    }
+  const int done = sc->done, act = sc->active[ball];
+  const uint32_t pfx = sc->prefix[ball];
+  const double S_carry = level == 1 ? 0.0 : sc->S_above[ball];
+  const double C_carry = level == 1 ? 0.0 : (double)sc->C_above[ball];
+  const bool skip = done || (level > 1 && !act);
   if (skip) {
     for (int k = threadIdx.x; k < nb; k += kNT) {
       gc[k] = 0u;
@@ -194,20 +209,20 @@ __global__ __launch_bounds__(kNT) void k_l1_select(int level, double r0, double 
     }
     return;
   }
-  const uint32_t parent = level == 1 ? 0u : (sc->prefix[ball] >> parent_shift(level)) << parent_shift(level);
-  // thread t owns bins [nb - per*(t+1), nb - per*t), i.e. thread 0 the highest bins
-  const int hi = nb - per * threadIdx.x;
+  const uint32_t parent = level == 1 ? 0u : (pfx >> parent_shift(level)) << parent_shift(level);
   double val[8];
   double cnt[8];
   double lo_edge[8];
   double S = 0, C = 0;
-  for (int m = 0; m < per; ++m) {
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    if (m >= per) break;
     const int k = hi - 1 - m;  // descending
     const uint32_t bits = parent | ((uint32_t)k << shift);
     const int ex = (int)(bits >> 23);
     const double scale = ldexp(1.0, (ex > 0 ? ex : 1) - 150);
-    val[m] = (double)gs[k] * scale;
-    cnt[m] = (double)gc[k];
+    val[m] = (double)sraw[m] * scale;
+    cnt[m] = (double)craw[m];
     lo_edge[m] = (double)__uint_as_float(bits);
     S += val[m];
     C += cnt[m];
@@ -227,8 +242,6 @@ __global__ __launch_bounds__(kNT) void k_l1_select(int level, double r0, double 
     sC[threadIdx.x] += c2;
     __syncthreads();
   }
-  const double S_carry = level == 1 ? 0.0 : sc->S_above[ball];
-  const double C_carry = level == 1 ? 0.0 : (double)sc->C_above[ball];
   double Sx = S_carry + (threadIdx.x ? sS[threadIdx.x - 1] : 0.0);
   double Cx = C_carry + (threadIdx.x ? sC[threadIdx.x - 1] : 0.0);
   const double total = S_carry + sS[kNT - 1];
