@@ -587,11 +587,11 @@ def main() -> int:
 
     print(f"[bench] timed {args.steps} iterations (iterations {first + 1}-{first + args.steps})",
           file=sys.stderr, flush=True)
-    # blocks of at most 16 rows and 16 column tiles take the fused block pass; more columns
-    # (SSST's three components at N3 > 64) the separate Gram / eigen / apply kernels
+    # blocks of at most 16 rows and 24 column tiles take the fused block pass; more columns
+    # (SSST's three components at N3 > 128) the separate Gram / eigen / apply kernels
     comps = 3 if reg == "ssst" else 2
     bq = 32 if comps == 3 else 16
-    fused = k1 * k2 <= 16 and comps * ((n3 + bq - 1) // bq * bq) <= 256
+    fused = k1 * k2 <= 16 and comps * ((n3 + bq - 1) // bq * bq) <= 384
     if l1_reg:
         classes = [nt.K_DUAL]
     elif fused:

@@ -88,7 +88,8 @@ typedef struct {
  *    rounding; it only moves work between the two solvers. At most 255.
  *  gram_precision: S3TTV_GRAM_FP32 (default), S3TTV_GRAM_BF16 or S3TTV_GRAM_FP16: input
  *    precision of the per-block Gram products Y' Y'^T on MFMA in the one-pass block kernel
- *    (blocks of at most 16 rows, N3 <= 128; other shapes always sum in FP32). Accumulation is
+ *    (blocks of at most 16 rows and at most 24 column tiles of 16: N3 <= 192, SSST N3 <= 128;
+ *    other shapes always sum in FP32). Accumulation is
  *    FP32, followed by one FP32 refinement of the eigenvectors; the clip W Y' and every update
  *    stay FP32. The reduced modes round the Gram inputs to 8 or 11 significand bits for fewer
  *    MFMA instructions; see the error report of the tests.
@@ -139,7 +140,7 @@ enum {
                          cannot read them itself */
   S3TTV_K_DUAL = 7,   /* s+, t+, y2, y3 updates (steps 3-7, 12-14) and the gradient field */
   S3TTV_K_FINAL = 8,  /* scalar reductions, stop rule */
-  S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks per iteration (N3 <= 128): steps 9-10
+  S3TTV_K_BLOCK = 9,  /* one pass over the dual blocks per iteration (N3 <= 192): steps 9-10
                          (Gram, eigen-solve, clip) and the overlap-add on MFMA */
   S3TTV_K_COUNT = 10
 };

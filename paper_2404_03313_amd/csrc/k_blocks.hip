@@ -11,8 +11,8 @@
 // on MFMA (simultaneous Jacobi rotations from the previous eigenbasis, the identity before the
 // first iteration) and forms W_l; a per-lane cyclic Jacobi eigen-solve (k_eig) for the
 // stand-alone block operator and for the blocks the MFMA rotations cannot certify; and
-// W_l Y'_l on MFMA with a deterministic overlap-add (k_apply). With N3 <= 128 the solver runs
-// all of it in one pass (k_block_fused).
+// W_l Y'_l on MFMA with a deterministic overlap-add (k_apply). With at most 24 column tiles
+// (S3TTV and STV: N3 <= 192) the solver runs all of it in one pass (k_block_fused).
 //
 // Block storage ("apply layout", 16 rows x ncol columns per block, ncol = 2*Bp, column
 // c = comp*Bp + band): column tile t holds columns 16t..16t+15 as 64 lanes x 4 floats,
@@ -687,8 +687,10 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
 
 // ---------------------------------------------------------------- fused warm-iteration pass
 
-// Steps 9-10 and the overlap-add of the next step 2 in one pass over Y (warm iterations, at
-// most kFusedTiles column tiles, i.e. N3 <= 128). Workgroup = one TA x TB anchor tile with kFW
+// Steps 9-10 and the overlap-add of the next step 2 in one pass over Y (at most kFusedTiles
+// column tiles: N3 <= 192 for the two-component field, N3 <= 128 for SSST's three; beyond 16
+// tiles the accumulators of an 8 x 8 anchor tile outgrow the LDS and the tile shrinks to
+// 8 x 4). Workgroup = one TA x TB anchor tile with kFW
 // wavefronts; each wavefront takes anchors from a shared counter and keeps Y'_l (16 x ncol)
 // in registers in the apply layout: loads Y_l and T_l, forms the Gram matrix (column tiles
 // transposed in pairs through LDS into the Gram operand layout), diagonalises it on MFMA
@@ -697,7 +699,7 @@ __global__ __launch_bounds__(1024) void k_apply(BlockArgs a) {
 // does not depend on their order. Blocks eigen_mfma cannot certify keep Y'_l in Y and are
 // finished by k_eig and k_fixup.
 constexpr int kFW = 8;
-constexpr int kFusedTiles = 16;
+constexpr int kFusedTiles = 24;
 
 template <int NT>
 __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
@@ -858,21 +860,21 @@ __global__ __launch_bounds__(kFW * 64) void k_block_fused(BlockArgs a) {
   }
   flag_nonfinite(a.sc, bad);
   __syncthreads();
-  // the tile's partial: a pixel row (ncol <= 16 NT <= 256 columns) per wave and trip, 16 bytes
-  // per lane, four rows in flight
+  // the tile's partial: a pixel row per wave and trip (ncol / 4 <= 96 quads: one or two per
+  // lane), 16 bytes per lane, four rows in flight
   int4 *zp4 = reinterpret_cast<int4 *>(a.zpart + (size_t)tile * next * a.ncol);
   const int nc4 = a.ncol >> 2, zs4 = zs >> 2;
-  if (lane < nc4) {
+  for (int c = lane; c < nc4; c += 64) {
     for (int px = wave; px < next; px += 4 * kFW) {
       // rows past the end read row 0 again and are not stored
       const int p1 = px + kFW < next ? px + kFW : 0, p2 = px + 2 * kFW < next ? px + 2 * kFW : 0;
       const int p3 = px + 3 * kFW < next ? px + 3 * kFW : 0;
-      const int4 v0 = zacc4[px * zs4 + lane], v1 = zacc4[p1 * zs4 + lane];
-      const int4 v2 = zacc4[p2 * zs4 + lane], v3 = zacc4[p3 * zs4 + lane];
-      zp4[(size_t)px * nc4 + lane] = v0;
-      if (p1) zp4[(size_t)p1 * nc4 + lane] = v1;
-      if (p2) zp4[(size_t)p2 * nc4 + lane] = v2;
-      if (p3) zp4[(size_t)p3 * nc4 + lane] = v3;
+      const int4 v0 = zacc4[px * zs4 + c], v1 = zacc4[p1 * zs4 + c];
+      const int4 v2 = zacc4[p2 * zs4 + c], v3 = zacc4[p3 * zs4 + c];
+      zp4[(size_t)px * nc4 + c] = v0;
+      if (p1) zp4[(size_t)p1 * nc4 + c] = v1;
+      if (p2) zp4[(size_t)p2 * nc4 + c] = v2;
+      if (p3) zp4[(size_t)p3 * nc4 + c] = v3;
     }
   }
 }
@@ -1036,6 +1038,10 @@ hipError_t configure_block_kernels() {
   if (e == hipSuccess) e = allow_lds_nt<12>(bytes);
   if (e == hipSuccess) e = allow_lds_nt<14>(bytes);
   if (e == hipSuccess) e = allow_lds_nt<16>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<18>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<20>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<22>(bytes);
+  if (e == hipSuccess) e = allow_lds_nt<24>(bytes);
   if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
   return e;
 }
@@ -1051,6 +1057,10 @@ hipError_t launch_block_fused(const BlockArgs &a, hipStream_t st) {
     case 12: return launch_fused_nt<12>(a, lds, st);
     case 14: return launch_fused_nt<14>(a, lds, st);
     case 16: return launch_fused_nt<16>(a, lds, st);
+    case 18: return launch_fused_nt<18>(a, lds, st);
+    case 20: return launch_fused_nt<20>(a, lds, st);
+    case 22: return launch_fused_nt<22>(a, lds, st);
+    case 24: return launch_fused_nt<24>(a, lds, st);
     default: return hipErrorInvalidValue;
   }
 }

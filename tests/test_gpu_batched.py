@@ -31,9 +31,10 @@ def _problem(device, shape, k, seed, **kw):
     return dict(v=_t(d["v"], device), k1=k[0], k2=k[1], params=prm)
 
 
-# fused pass (k 3x3, 2x3), separate kernels (N3 > 128), separate overlap-add sum (ragged tiles)
+# fused pass (k 3x3, 2x3; 20 column tiles at N3 = 150), separate kernels (N3 > 192), separate
+# overlap-add sum (ragged tiles)
 SHAPES = [((24, 20, 16), (3, 3)), ((13, 11, 7), (2, 3)), ((12, 10, 150), (2, 2)),
-          ((10, 10, 8), (4, 4))]
+          ((12, 10, 200), (2, 2)), ((10, 10, 8), (4, 4))]
 
 
 def _standalone(p):

@@ -9,8 +9,9 @@ exercised):
     BF16 / FP16 Gram of the reduced-precision mode;
   * 200 iterations from zero on 32 x 32 x 128 (the same fused kernel instance), long enough for
     the blocks to clip, in FP32 / BF16 / FP16;
-  * one batched call with shapes on both block-pass routes (N3 > 128 takes the separate Gram /
-    eigen / apply kernels) compared with the oracle, not with standalone GPU solves.
+  * one batched call with shapes on both block-pass routes (N3 > 192 takes the separate Gram /
+    eigen / apply kernels, 128 < N3 <= 192 the fused pass with an 8 x 4 anchor tile) compared
+    with the oracle, not with standalone GPU solves.
 
 Relative L2 is ||a - b|| / ||b|| per output; max-abs is max |a - b|. The FP32 bounds are the
 spec bar (1e-4 relative L2) or tighter; the reduced-precision bounds are stated with
@@ -130,7 +131,7 @@ def test_batched_mix_against_oracle(device):
     """One s3ttv_solve_batched call with uneven shapes on both block-pass routes, all started
     from u0 = v so that every block clips from the first iteration; each result against the
     oracle after 30 iterations."""
-    shapes = [(72, 64, 150), (40, 52, 40), (33, 29, 128)]
+    shapes = [(72, 64, 150), (40, 52, 40), (33, 29, 128), (24, 20, 200)]
     probs, refs = [], []
     for i, sh in enumerate(shapes):
         cfg = synth.HSIConfig(*sh, endmembers=4, cells=8, sigma=0.05 * (1 + i % 2), p_sp=0.05,

@@ -132,13 +132,22 @@ def test_solve_parity_reduced_precision_gram(device, prec, tol):
     _parity(device, d, w["k"], w["iters"], tol=tol, gram_precision=prec)
 
 
-def test_solve_parity_many_bands(device):
-    """N3 > 128: the warm iterations take the separate Gram / eigen / apply kernels."""
-    _say("solve 12x10x150")
-    cfg = synth.HSIConfig(12, 10, 150, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=14)
+@pytest.mark.parametrize("n3,route", [(150, "block"), (180, "block"), (200, "gram")])
+def test_solve_parity_many_bands(device, n3, route):
+    """Many bands: up to 24 column tiles (N3 <= 192) the fused pass (an 8 x 4 anchor tile, the
+    accumulators of 8 x 8 no longer fit the LDS), beyond it the separate Gram / eigen / apply
+    kernels."""
+    _say(f"solve 12x10x{n3}")
+    cfg = synth.HSIConfig(12, 10, n3, endmembers=3, cells=4, sigma=0.05, p_sp=0.05, p_stripe=0.2, seed=14)
     d = synth.make_hsi(cfg)
     u, s, t, st, r = _parity(device, d, (2, 2), 40)
     assert st["eig_avg_steps"] > 0
+    # the route shows in which kernels run (a timed solve counts their launches)
+    prm = nt.make_params(max_iter=3, timing_mask=(1 << nt.K_BLOCK) | (1 << nt.K_GRAM), **d["radii"])
+    _, _, _, st3 = nt.Solver(12, 10, n3, 2, 2, device=device).solve(_t(d["v"], device), prm)
+    assert st3["kernel_calls"][route] == 3, st3["kernel_calls"]
+    other = "gram" if route == "block" else "block"
+    assert st3["kernel_calls"][other] == 0, st3["kernel_calls"]
 
 
 def test_solve_stop_rule_matches_oracle(device):

@@ -45,7 +45,8 @@ def test_variant_parity(device, reg, shape, k, iters):
         assert calls["block"] + calls["gram"] >= iters
 
 
-@pytest.mark.parametrize("shape,k,iters", [((12, 12, 70), (2, 2), 30),    # 3 x 96 columns: separate kernels
+@pytest.mark.parametrize("shape,k,iters", [((12, 12, 150), (2, 2), 30),   # 3 x 160 columns: separate kernels
+                                           ((12, 12, 70), (2, 2), 30),    # 3 x 96 columns: fused pass
                                            ((14, 12, 33), (4, 4), 30),    # 3 x 64 columns: fused pass
                                            ((12, 12, 8), (10, 10), 20),   # K = 100: one workgroup per block
                                            ((11, 9, 5), (5, 4), 25)])     # K = 20
