@@ -184,7 +184,10 @@ __device__ inline void upper_tile(int t, int nt, int &I, int &J) {
 
 template <bool TA>
 __device__ __forceinline__ void prod_sym(const float *A, int as, const float *B, int bs, int K,
-                                         int wave, int i16, int g4, f4 acc[kSymHold]) {
+                                         int wave, int i16, int g4, f4 acc[kSymHold],
+                                         int kd = 0) {
+  // K x K result; the contraction runs over kd (K when 0)
+  if (kd <= 0) kd = K;
   const int nt = (K + 15) >> 4, nup = nt * (nt + 1) / 2;
   // all of the wave's tiles advance together, so their MFMA chains are independent; a tile
   // past nup repeats tile 0 and is not released
@@ -198,10 +201,10 @@ __device__ __forceinline__ void prod_sym(const float *A, int as, const float *B,
     c[m] = min(16 * J + i16, K - 1);
     acc[m] = f4{0.f, 0.f, 0.f, 0.f};
   }
-  const int nk = (K + 3) >> 2;
+  const int nk = (kd + 3) >> 2;
   float a0[kSymHold], b0[kSymHold], a1[kSymHold], b1[kSymHold];
   auto load = [&](int k4, float (&av)[kSymHold], float (&bv)[kSymHold]) {
-    const int k = min(4 * k4 + g4, K - 1);
+    const int k = min(4 * k4 + g4, kd - 1);
 #pragma unroll
     for (int m = 0; m < kSymHold; ++m) {
       av[m] = TA ? A[k * as + r[m]] : A[r[m] * as + k];
@@ -209,7 +212,7 @@ __device__ __forceinline__ void prod_sym(const float *A, int as, const float *B,
     }
   };
   auto step = [&](int k4, const float (&av)[kSymHold], const float (&bv)[kSymHold]) {
-    const bool in = 4 * k4 + g4 < K;
+    const bool in = 4 * k4 + g4 < kd;
 #pragma unroll
     for (int m = 0; m < kSymHold; ++m)
       acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? av[m] : 0.f, bv[m], acc[m], 0, 0, 0);
@@ -798,69 +801,36 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   }
   __syncthreads();
   const int R = nr;
-  // ---- Y+ = Y' - V_R diag(f) V_R^T Y', by column chunks on MFMA tiles (T3: Y' chunk,
-  // G: P = diag(f) V_R^T Y', R x 32). V_R is read through ridx, so it is never compacted.
+  // ---- Y+ = Y' - M Y' with M = V_R diag(f) V_R^T (K x K, symmetric), formed once per block:
+  // the clipped directions scaled by sqrt(f) are gathered as the rows of Ut (T3, R x K), so
+  // M = Ut^T Ut; then every column chunk of Y' is staged in T3 and each wave updates its row
+  // tile of the chunk (M in G, read as its own transpose).
   if (R > 0) {
-    const int nR = (R + 15) >> 4, nt = (K + 15) >> 4;
+    for (int e = tid; e < R * K; e += kBT) {
+      const int n = e / K, r = e - (e / K) * K;
+      const int i = ridx[n];
+      T3[n * KS + r] = V[r * KS + i] * sqrtf(lam[i]);
+    }
+    __syncthreads();
+    {
+      f4 hs[kSymHold];
+      prod_sym<true>(T3, KS, T3, KS, K, wave, i16, g4, hs, R);
+      release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
+    }
+    const int nt = (K + 15) >> 4;
     float yv[kStage];
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
-      __syncthreads();
+      __syncthreads();  // M is complete (first chunk); the previous chunk's products are done
       store_chunk(yv, K, srow, scol, T3, CS);
       if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
-      // P: row tile I over the clipped directions n (lane supplies V[k][ridx[n]]), k over K
-      for (int I = wave; I < nR; I += kNW) {
-        const int vc = ridx[min(16 * I + i16, R - 1)];
-        f4 acc[kChunk / 16] = {};
-        for (int k16 = 0; k16 < K; k16 += 16) {  // four MFMA steps per trip, tail masked
-          float av[4], bv[4][kChunk / 16];
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const int kk = k16 + 4 * st + g4, k = min(kk, K - 1);
-            av[st] = kk < K ? V[k * KS + vc] : 0.f;
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J) bv[st][J] = T3[k * CS + 16 * J + i16];
-          }
-#pragma unroll
-          for (int st = 0; st < 4; ++st)
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J)
-              acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][J], acc[J], 0, 0, 0);
-        }
+      if (wave < nt) {
+        f4 acc[kChunk / 16];
+        mfma_band<true, kChunk / 16>(G, KS, T3, CS, K, K, kChunk, wave, 0, i16, g4, acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int n = 16 * I + 4 * g4 + v;
-          if (n < R) {
-            const float f = lam[ridx[n]];
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J) G[n * CS + 16 * J + i16] = f * acc[J][v];
-          }
-        }
-      }
-      __syncthreads();
-      // Y+ = Y' - V_R P: row tile I over the block rows, k over the clipped directions
-      for (int I = wave; I < nt; I += kNW) {
-        const int r = min(16 * I + i16, K - 1);
-        f4 acc[kChunk / 16] = {};
-        for (int k16 = 0; k16 < R; k16 += 16) {  // four MFMA steps per trip, tail masked
-          float av[4], bv[4][kChunk / 16];
-#pragma unroll
-          for (int st = 0; st < 4; ++st) {
-            const int kk = k16 + 4 * st + g4, k = min(kk, R - 1);
-            av[st] = kk < R ? V[r * KS + ridx[k]] : 0.f;
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J) bv[st][J] = G[k * CS + 16 * J + i16];
-          }
-#pragma unroll
-          for (int st = 0; st < 4; ++st)
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J)
-              acc[J] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], bv[st][J], acc[J], 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = 16 * I + 4 * g4 + v;
+          const int rr = 16 * wave + 4 * g4 + v;
           if (rr < K) {
 #pragma unroll
             for (int J = 0; J < kChunk / 16; ++J) {
