@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   __shared__ bool hot[112];
   __shared__ int nact;
   __shared__ float red[kNW];
-  __shared__ int flag;
+  __shared__ int wfail[kNW];
   if (a.sc->done) return;
   const int tid = threadIdx.x;
   const long long blk = blockIdx.x;
@@ -365,18 +365,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           if (srow + kRowStep * k < K) gv[k] = hasg ? a.gradf[goff[k] + c0 + kChunk + scol] : 0.f;
       }
       __syncthreads();
+      // every tile slot of the wave runs (a slot past ntiles has rows past K, which read as
+      // zero, and is not stored), so the chains of the slots interleave
 #pragma unroll
-      for (int m = 0; m < kGramTiles; ++m) {
-        if (wave + kNW * m < ntiles) {
+      for (int st = 0; st < kChunk / 4; ++st)
+#pragma unroll
+        for (int m = 0; m < kGramTiles; ++m) {
           const int ra = 16 * tI[m] + i16, rb = 16 * tJ[m] + i16;
-          const float *pa = T3 + ra * kGS + g4, *pb = T3 + rb * kGS + g4;
-#pragma unroll
-          for (int st = 0; st < kChunk / 4; ++st) {
-            const float av = ra < K ? pa[4 * st] : 0.f, bv = rb < K ? pb[4 * st] : 0.f;
-            gacc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, gacc[m], 0, 0, 0);
-          }
+          const float av = T3[min(ra, K - 1) * kGS + g4 + 4 * st];
+          const float bv = T3[min(rb, K - 1) * kGS + g4 + 4 * st];
+          gacc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra < K ? av : 0.f, rb < K ? bv : 0.f,
+                                                         gacc[m], 0, 0, 0);
         }
-      }
     }
     // result layout: lane i + 16 g, register v holds tile entry (4 g + v, i); a copy of the
     // Gram goes to the block's slot of a.Gg (when given) for the re-derivation of A below
@@ -400,15 +400,23 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       }
     }
   }
-  if (tid == 0) flag = 0;
   __syncthreads();
   // ---- finiteness and the Gershgorin bound: max_i sum_j |G_ij| <= 1 => nothing to clip
-  for (int r = tid; r < K; r += kBT) {
-    float s = 0.f;
-    for (int c = 0; c < K; ++c) s += fabsf(G[r * KS + c]);
-    if (!(s <= 1.f)) atomicOr(&flag, isfinite(s) ? 1 : 2);
+  {
+    bool over = false, nonfin = false;
+    for (int r = tid; r < K; r += kBT) {
+      float s = 0.f;
+      for (int c = 0; c < K; ++c) s += fabsf(G[r * KS + c]);
+      over |= !(s <= 1.f);
+      nonfin |= !isfinite(s);
+    }
+    const bool wo = __any(over), wn = __any(nonfin);
+    if ((tid & 63) == 0) wfail[tid >> 6] = (wo ? 1 : 0) | (wn ? 2 : 0);
   }
   __syncthreads();
+  int flag = 0;
+#pragma unroll
+  for (int w = 0; w < kNW; ++w) flag |= wfail[w];
   if (flag & 2) {
     if (tid == 0) atomicExch(&a.sc->nonfinite, 1);
     return;
@@ -417,9 +425,19 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
 
   // ---- basis: identity on the first use, else the stored one (orthonormal to rounding)
   float *Vg = a.V + blk * (long long)K * K;
-  for (int e = tid; e < K * K; e += kBT) {
-    const int r = e / K, c = e - r * K;
-    V[r * KS + c] = a.first ? (r == c ? 1.f : 0.f) : Vg[e];
+  {
+    int r = tid / K, c = tid - (tid / K) * K;
+    const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+#pragma unroll 4
+    for (int e = tid; e < K * K; e += kBT) {
+      V[r * KS + c] = a.first ? (r == c ? 1.f : 0.f) : Vg[e];
+      r += dr;
+      c += dc;
+      if (c >= K) {
+        c -= K;
+        ++r;
+      }
+    }
   }
   __syncthreads();
   // ---- A = V^T (G V): H = G V into T3, then A into G (exactly symmetric). G is symmetric, so
@@ -471,8 +489,8 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
       tol = 1e-6f * sqrtf(fsum);
     }
-    if (tid == 0) flag = 0;
-    __syncthreads();
+    __syncthreads();  // the previous call's readers of wfail are done
+    bool fail = false;
     if (tid < 4 * K) {  // four consecutive lanes per row, columns interleaved
       const int r = tid >> 2, part = tid & 3;
       const float dr = G[r * KS + r];
@@ -488,15 +506,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       mx = fmaxf(mx, __shfl_xor(mx, 1));
       mx = fmaxf(mx, __shfl_xor(mx, 2));
       if (part == 0) {
-        const bool fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
-        if (fail) atomicOr(&flag, 1);
+        fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
         hot[r] = fail || all_hot;
       }
     }
+    // one flag per wave (no atomics on a shared word)
+    const bool wf = __any(fail);
+    if ((tid & 63) == 0) wfail[tid >> 6] = wf;
     __syncthreads();
-    const int notyet = flag;
-    __syncthreads();
-    return notyet != 0;
+    bool notyet = false;
+#pragma unroll
+    for (int w = 0; w < kNW; ++w) notyet |= wfail[w] != 0;
+    return notyet;
   };
 
   // ---- simultaneous rotations on MFMA (warm-started iterations). With the previous basis
@@ -739,9 +760,19 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     });
     __syncthreads();
   }
-  for (int e = tid; e < K * K; e += kBT) {
-    const int r = e / K, c = e - r * K;
-    Vg[e] = V[r * KS + c];
+  {
+    int r = tid / K, c = tid - (tid / K) * K;
+    const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+#pragma unroll 4
+    for (int e = tid; e < K * K; e += kBT) {
+      Vg[e] = V[r * KS + c];
+      r += dr;
+      c += dc;
+      if (c >= K) {
+        c -= K;
+        ++r;
+      }
+    }
   }
   // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks: P = V^T Y' per
   // chunk on MFMA tiles; wave w owns the row tiles I = w, w + 4 (both column tiles of each),
@@ -749,6 +780,23 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   {
     const int nt = (K + 15) >> 4;
     float lacc[kRqTiles][4] = {};
+    auto rq_chunk = [&]() {
+#pragma unroll
+      for (int m = 0; m < kRqTiles; ++m) {
+        const int I = wave + kNW * m;
+        if (I < nt) {
+          f4 acc[kChunk / 16];
+          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
+          // each lane sums the squares of its own column over the chunks; the 16 columns of
+          // a tile (lanes i16 of one g4 group) are summed once after the last chunk
+#pragma unroll
+          for (int J = 0; J < kChunk / 16; ++J)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) lacc[m][v] = fmaf(acc[J][v], acc[J][v], lacc[m][v]);
+        }
+      }
+    };
+    // the loads of chunk c0 + 32 are issued before the products of chunk c0
     float yv[kStage];
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
@@ -756,36 +804,21 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       store_chunk(yv, K, srow, scol, T3, CS);
       if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
-#pragma unroll
-      for (int m = 0; m < kRqTiles; ++m) {
-        const int I = wave + kNW * m;
-        if (I < nt) {
-          f4 acc[kChunk / 16];
-          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
-#pragma unroll
-          for (int J = 0; J < kChunk / 16; ++J) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              // sum over the 16 columns of the tile (lanes i16 of one g4 group), fixed order
-              float sq = acc[J][v] * acc[J][v];
-              sq += __shfl_xor(sq, 1);
-              sq += __shfl_xor(sq, 2);
-              sq += __shfl_xor(sq, 4);
-              sq += __shfl_xor(sq, 8);
-              lacc[m][v] += sq;
-            }
-          }
-        }
-      }
+      rq_chunk();
     }
 #pragma unroll
     for (int m = 0; m < kRqTiles; ++m) {
       const int I = wave + kNW * m;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        float sq = lacc[m][v];  // fixed order over the 16 lanes of the group
+        sq += __shfl_xor(sq, 1);
+        sq += __shfl_xor(sq, 2);
+        sq += __shfl_xor(sq, 4);
+        sq += __shfl_xor(sq, 8);
         const int i = 16 * I + 4 * g4 + v;
         if (I < nt && i16 == 0 && i < K)
-          lam[i] = lacc[m][v] > 1.f ? 1.f - 1.f / sqrtf(lacc[m][v]) : 0.f;  // f_i of the clip
+          lam[i] = sq > 1.f ? 1.f - 1.f / sqrtf(sq) : 0.f;  // f_i of the clip
       }
     }
   }
@@ -818,13 +851,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
     }
     const int nt = (K + 15) >> 4;
-    float yv[kStage];
-    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
-    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
-      __syncthreads();  // M is complete (first chunk); the previous chunk's products are done
-      store_chunk(yv, K, srow, scol, T3, CS);
-      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
-      __syncthreads();
+    auto clip_chunk = [&](int c0) {
       if (wave < nt) {
         f4 acc[kChunk / 16];
         mfma_band<true, kChunk / 16>(G, KS, T3, CS, K, K, kChunk, wave, 0, i16, g4, acc);
@@ -840,6 +867,17 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           }
         }
       }
+    };
+    // the loads of chunk c0 + 32 (a column range this pass has not written) are issued before
+    // the products of chunk c0
+    float yv[kStage];
+    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      __syncthreads();  // M is complete (first chunk); the previous chunk's products are done
+      store_chunk(yv, K, srow, scol, T3, CS);
+      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
+      __syncthreads();
+      clip_chunk(c0);
     }
   }
 }
