@@ -155,10 +155,10 @@ def big_block_dense_flops(n3: int, K: int, nblk: int, eig_blocks: float,
     """FP32 flops of the dense products of one launch of the large-block pass: the symmetric
     Gram (K (K + 1) / 2 dot products of length 2 n3) of every block and, for the blocks that
     needed the eigen-solve, V^T G V and the Newton-Schulz step (four K x K x K products), the
-    Rayleigh quotients (a K x K x 2 n3 product) and, per simultaneous rotation step
-    (`sim_steps` per such block on average), at least four K x K x K products (K^T K, V J and
-    two for the rotated A). The cyclic Jacobi rotations, extra Newton-Schulz steps and the
-    low-rank clip are not counted, so the figure is a lower bound on the work done."""
+    clip M Y' (a K x K x 2 n3 product) and, per simultaneous rotation step (`sim_steps` per
+    such block on average), at least four K x K x K products (K^T K, V J and two for the
+    rotated A). The cyclic Jacobi rotations, extra Newton-Schulz steps and the forming of M
+    are not counted, so the figure is a lower bound on the work done."""
     c = 2 * n3
     return nblk * K * (K + 1) * c + eig_blocks * (8 * K ** 3 + 2 * K * K * c
                                                   + 8 * K ** 3 * sim_steps)

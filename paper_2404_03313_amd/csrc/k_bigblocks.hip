@@ -14,16 +14,17 @@
 //   a row pass and a column pass, accumulated into V) until a certificate holds: every off-diagonal entry in a row or column
 //   whose diagonal exceeds 0.999 is at most 1e-6 ||A||_F (about the FP32 rounding level of
 //   the rotations), and every other row has a Gershgorin bound <= 1, so no eigenvalue above 1
-//   hides among them (the clip factor 1 - lambda^-1/2 is continuous at 1 and uses the
-//   Rayleigh quotients below, so eigenvalues next to 1 need no separation). A sweep rotates
+//   hides among them (the clip factor 1 - lambda^-1/2 is continuous at 1, so eigenvalues
+//   next to 1 need no separation). A sweep rotates
 //   only pairs with a row that failed this test when the sweep began (a pair of two certified
 //   rows needs nothing; from the fifth sweep on, every pair), so with the warm basis a step
 //   touches a few rows and columns of A instead of all of them;
+//   lambda_i = A_ii, the diagonal of the certified A (the rows with A_ii > 1 are among those
+//   whose off-diagonal entries passed the test, so A_ii is their eigenvalue to second order);
 //   one Newton-Schulz step V <- V (3 I - V^T V) / 2 restores orthonormality lost to rounding;
-//   lambda_i = ||v_i^T Y'||^2 (Rayleigh quotients, more accurate than the rotated diagonal);
-//   Y+ = Y' - V_R diag(1 - lambda^-1/2) V_R^T Y'   over R = {i : lambda_i > 1}
-// which is the spectral clip of step 10 (eqs. ProxConjugate, prox_nuclear_norm), formed as a
-// low-rank correction. The basis is kept for the next iteration.
+//   Y+ = Y' - M Y',  M = V_R diag(1 - lambda^-1/2) V_R^T   over R = {i : lambda_i > 1}
+// which is the spectral clip of step 10 (eqs. ProxConjugate, prox_nuclear_norm). The basis is
+// kept for the next iteration.
 //
 // The overlap-add sum_l P_l^T Y_l is a gather (each pixel reads its K windows in a fixed
 // order), so results are reproducible.
@@ -43,8 +44,6 @@ constexpr int kChunk = 32;
 constexpr int kGS = kChunk + 2;
 // 16 x 16 Gram tiles per wave: ceil(28 / kNW) for K <= 112 (7 x 7 tiles, upper triangle).
 constexpr int kGramTiles = (28 + kNW - 1) / kNW;
-// Row tiles (of 16 rows, at most 7) per wave in the Rayleigh-quotient pass.
-constexpr int kRqTiles = (7 + kNW - 1) / kNW;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -57,13 +56,11 @@ constexpr float kNearOne = 0.999f;
 // Sweeps that rotate only pairs touching a row that failed the certificate; later sweeps
 // rotate every pair above the skip threshold.
 constexpr int kRestricted = 4;
-// Pairs a wave rotates per batch of a rotation pass: a group of pairs has at most
-// ceil((kBigMax / 2) / (kNW / 2)) = 13 of them, so one batch (the pass loops over batches).
+// Pairs a wave rotates in a rotation pass: a group of pairs has at most
+// ceil((kBigMax / 2) / (kNW / 2)) = 13 of them. The K / 2 <= 50 rotations of a step fit the
+// lanes of one wavefront.
 constexpr int kBatch = 13;
-// Rotation records of a step (K / 2 <= 50 used; reads past the active ones are clamped here
-// and their values ignored).
-constexpr int kRotSlots = 64;
-static_assert(kBigMax <= 128 && kBT % 128 == 0 && kBatch * (kNW / 2) >= kBigMax / 2,
+static_assert(kBigMax <= 100 && kBT % 128 == 0 && kBatch * (kNW / 2) >= kBigMax / 2,
               "rotation pass mapping: one batch covers a wave's pairs");
 static_assert(4 * kBigMax <= kBT, "certificate: four threads per row");
 
@@ -250,16 +247,14 @@ __device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4, co
   }
 }
 
+// Row stride of the two K x K arrays: odd, and above the Gram chunk stride kGS (the chunks are
+// staged in the basis array before the basis is loaded).
+__host__ __device__ constexpr int big_stride(int K) { return K + 1 > kGS + 1 ? K + 1 : kGS + 1; }
+
 // Simultaneous rotation steps before the cyclic sweeps (warm-started iterations): at most this
 // many, each damped to ||K||_F <= kSimCap.
 constexpr int kSimSteps = 12;
 constexpr float kSimCap = 0.7f;
-
-// One rotation of a Jacobi step: J = [[c, s], [-s, c]] on the index pair p < q.
-struct __align__(16) Rot {
-  float c, s;
-  int p, q;
-};
 
 // The K x 32 chunk of Y at column c0 (row stride ncol) into registers: thread t holds rows
 // srow + kRowStep k, column scol. Loading the next chunk before working on the current one hides
@@ -285,17 +280,17 @@ __device__ inline const float *Ggb_all(const BigArgs &a, long long blk, int K) {
 
 }  // namespace
 
-__global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
+// Two workgroups share a CU (four wavefronts per SIMD): the dynamic LDS is two K x KS arrays
+// (80 800 bytes at K = 100) and the static part about 1 KB, within half of the 160 KB.
+__global__ __launch_bounds__(kBT) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_big_block(BigArgs a) {
   extern __shared__ float lds[];
-  const int K = a.K, KS = a.K + 1;
-  const int GS = KS > kGS ? KS : kGS;
-  float *G = lds;                 // K x GS: Gram, then A, then projections of a chunk
-  float *V = G + K * GS;          // K x KS: eigenbasis, column c = vector c
-  float *T3 = V + K * KS;         // K x GS: H = G V, V^T V, or a Y' column chunk
-  __shared__ Rot rot[kRotSlots];
+  const int K = a.K, KS = big_stride(K);
+  // Each product result is held in registers until a barrier, so it may overwrite an operand.
+  float *G = lds;       // Gram, A, the rotation generator and J, V^T V, U_R^T, a Y' chunk
+  float *V = G + K * KS;  // Gram chunks, then the eigenbasis (column c = vector c), then M
   __shared__ float lam[112];
   __shared__ bool hot[112];
-  __shared__ int nact;
   __shared__ float red[kNW];
   __shared__ int wfail[kNW];
   if (a.sc->done) return;
@@ -356,7 +351,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
         if (srow + kRowStep * k < K) {
           const float y = yv[k] + a.gY * gv[k];
           Yb[(long long)(srow + kRowStep * k) * ncol + c0 + scol] = y;
-          T3[(srow + kRowStep * k) * kGS + scol] = y;
+          V[(srow + kRowStep * k) * kGS + scol] = y;
         }
       if (c0 + kChunk < ncol) {
         load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
@@ -372,8 +367,8 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
 #pragma unroll
         for (int m = 0; m < kGramTiles; ++m) {
           const int ra = 16 * tI[m] + i16, rb = 16 * tJ[m] + i16;
-          const float av = T3[min(ra, K - 1) * kGS + g4 + 4 * st];
-          const float bv = T3[min(rb, K - 1) * kGS + g4 + 4 * st];
+          const float av = V[min(ra, K - 1) * kGS + g4 + 4 * st];
+          const float bv = V[min(rb, K - 1) * kGS + g4 + 4 * st];
           gacc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra < K ? av : 0.f, rb < K ? bv : 0.f,
                                                          gacc[m], 0, 0, 0);
         }
@@ -440,15 +435,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     }
   }
   __syncthreads();
-  // ---- A = V^T (G V): H = G V into T3, then A into G (exactly symmetric). G is symmetric, so
-  // its operand is read as G^T (16 consecutive entries of a row per lane group)
-  {
+  // ---- A = V^T (G V): H = G V over G, then A over H (exactly symmetric). G is symmetric, so
+  // its operand is read as G^T (16 consecutive entries of a row per lane group). From the
+  // identity basis A = G exactly, and the products are skipped.
+  if (!a.first) {
     f4 hr[kMaxT];
     prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
-    release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+    __syncthreads();
+    release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { G[r * KS + c] = x; });
     __syncthreads();
     f4 hs[kSymHold];
-    prod_sym<true>(V, KS, T3, KS, K, wave, i16, g4, hs);
+    prod_sym<true>(V, KS, G, KS, K, wave, i16, g4, hs);
+    __syncthreads();
     release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
     __syncthreads();
   }
@@ -508,6 +506,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       if (part == 0) {
         fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
         hot[r] = fail || all_hot;
+        lam[r] = dr;  // the diagonal, for the rotation generator of a simultaneous step
       }
     }
     // one flag per wave (no atomics on a shared word)
@@ -524,17 +523,18 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   // the off-diagonal entries of A are small, and one step with the angles of all pairs at
   // once removes them to second order: K_ij = tan(theta_ij) of the 2 x 2 rotation that zeroes
   // A_ij, for the pairs with a row that fails the certificate (K exactly skew), damped to
-  // ||K||_F <= kSimCap; J = I + K + K^2 / 2; A <- J^T A J, V <- V J. J^T A J and V J
-  // transform together, so A stays V^T G V; only V drifts from orthonormal, by K^4 / 4 per step
-  // (J^T J = I + K^4 / 4). After a step with ||K||_F > 0.01 (drift above 2.5e-9) V is
-  // re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4) and A
-  // re-derived from the Gram copy, so the certificate is always judged on V^T G V of an
-  // orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
+  // ||K||_F <= kSimCap; J = I + K + K^2 / 2; V <- V J, which drifts from orthonormal by K^4 / 4
+  // per step (J^T J = I + K^4 / 4). After a step with ||K||_F > 0.01 (drift above 2.5e-9) V is
+  // re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4); after every
+  // step A is re-derived from the Gram copy, so the certificate is always judged on V^T G V of
+  // an orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
   int ssteps = 0;
   if (!a.first && a.Gg) {
     const float *Gb = Ggb_all(a, blk, K);
     for (; ssteps < kSimSteps; ++ssteps) {
       if (!certify(false)) break;
+      // the generator K (tangents) over A: entry (r, c) needs A_rc and the diagonal (copied by
+      // the certificate), so each thread overwrites only what it read
       float kf2 = 0.f;
       {
         // entry e = r K + c of this thread, stepped without divisions
@@ -545,12 +545,12 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           float t = 0.f;
           if (r != c && (hot[r] || hot[c])) {
             // hardware square root and reciprocal: (c, r) gets exactly -t, so K stays skew
-            const float arc = G[r * KS + c], den = G[c * KS + c] - G[r * KS + r];
+            const float arc = G[r * KS + c], den = lam[c] - lam[r];
             const float sg = (den > 0.f || (den == 0.f && r < c)) ? 1.f : -1.f;
             const float q = fabsf(den) + __builtin_sqrtf(fmaf(den, den, 4.f * arc * arc));
             t = q > 0.f ? (2.f * arc * sg) * __builtin_amdgcn_rcpf(q) : 0.f;
           }
-          T3[r * KS + c] = t;
+          G[r * KS + c] = t;
           kf2 = fmaf(t, t, kf2);
           r += dr;
           c += dc;
@@ -570,20 +570,20 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       const float sc = ksum > kSimCap * kSimCap ? kSimCap * rsqrtf(ksum) : 1.f;
       const bool rough = ksum * sc * sc > 1e-4f;
       f4 hr[kMaxT], hs[kSymHold];
-      // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K
-      prod_sym<true>(T3, KS, T3, KS, K, wave, i16, g4, hs);
+      // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K, over K
+      prod_sym<true>(G, KS, G, KS, K, wave, i16, g4, hs);
       __syncthreads();
       release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) {
-        T3[r * KS + c] = (r == c ? 1.f : 0.f) + sc * T3[r * KS + c] - 0.5f * sc * sc * x;
+        G[r * KS + c] = (r == c ? 1.f : 0.f) + sc * G[r * KS + c] - 0.5f * sc * sc * x;
       });
       __syncthreads();
-      prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);  // V J
+      prod_rows<false>(V, KS, G, KS, K, wave, i16, g4, hr);  // V J
       __syncthreads();
       release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { V[r * KS + c] = x; });
       __syncthreads();
       if (rough) {
         // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound ||K||_F^4 / 4, mapped by
-        // e -> 3 e^2 / 4 per step, is below 1e-8, then A = V^T G V from the Gram copy
+        // e -> 3 e^2 / 4 per step, is below 1e-8
         const float kk = ksum * sc * sc;
         float drift = 0.75f * (0.25f * kk * kk) * (0.25f * kk * kk);
         int nns = 1;
@@ -592,48 +592,41 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
           ++nns;
         }
         for (int ns = 0; ns < nns; ++ns) {
-          prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);  // V^T V
-          release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+          prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);  // V^T V over J (no longer read)
+          release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
           __syncthreads();
-          prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);
+          prod_rows<false>(V, KS, G, KS, K, wave, i16, g4, hr);
           __syncthreads();
           release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) {
             V[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x;
           });
           __syncthreads();
         }
-        // the Gram copy back into LDS (A is re-derived, its old value is not needed), then
-        // H = G V (G symmetric, read as G^T) and A = V^T H
-        {
-          int r = tid / K, c = tid - (tid / K) * K;
-          const int dr = kBT / K, dc = kBT - (kBT / K) * K;
-          for (int e = tid; e < K * K; e += kBT) {
-            G[r * KS + c] = Gb[e];
-            r += dr;
-            c += dc;
-            if (c >= K) {
-              c -= K;
-              ++r;
-            }
+      }
+      // A = V^T G V from the Gram copy: G back into LDS, H = G V over it (G symmetric, read as
+      // G^T), then A over H
+      {
+        int r = tid / K, c = tid - (tid / K) * K;
+        const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+        for (int e = tid; e < K * K; e += kBT) {
+          G[r * KS + c] = Gb[e];
+          r += dr;
+          c += dc;
+          if (c >= K) {
+            c -= K;
+            ++r;
           }
         }
-        __syncthreads();
-        prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
-        release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { T3[r * KS + c] = x; });
-        __syncthreads();
-        prod_sym<true>(V, KS, T3, KS, K, wave, i16, g4, hs);
-        release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
-        __syncthreads();
-      } else {
-        prod_rows<true>(G, KS, T3, KS, K, wave, i16, g4, hr);  // A J (A symmetric)
-        __syncthreads();
-        release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { G[r * KS + c] = x; });
-        __syncthreads();
-        prod_sym<true>(T3, KS, G, KS, K, wave, i16, g4, hs);  // J^T (A J)
-        __syncthreads();
-        release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
-        __syncthreads();
       }
+      __syncthreads();
+      prod_rows<true>(G, KS, V, KS, K, wave, i16, g4, hr);
+      __syncthreads();
+      release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { G[r * KS + c] = x; });
+      __syncthreads();
+      prod_sym<true>(V, KS, G, KS, K, wave, i16, g4, hs);
+      __syncthreads();
+      release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
+      __syncthreads();
       // A is exactly symmetric again (written from the upper tiles only)
     }
   }
@@ -645,95 +638,98 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     for (int s = 0; s < m - 1; ++s) {
       // rotation angles; a pair rotates only if a row of it failed the certificate at the
       // start of the sweep (pairs of two certified rows need nothing) and its entry exceeds
-      // the skip threshold. The active pairs are stored first, in pair order.
-      if (tid < 64) {
-        int p = 0, q = 0;
-        float c = 1.f, sv = 0.f;
-        if (tid < H) {
-          rr_pair(m, s, tid, p, q);
-          const int qq = q < K ? q : p;
-          const float apq = G[p * KS + qq], app = G[p * KS + p], aqq = G[qq * KS + qq];
-          if (q < K && (hot[p] || hot[q]) && fabsf(apq) > skip) {
-            // tan of the rotation angle, |t| <= 1 (hardware reciprocal and square roots: the
-            // rotation stays orthogonal to about 1e-7 and the basis is re-orthonormalised)
-            const float zeta = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
-            const float az = fabsf(zeta);
-            const float t = az > 1e15f ? 0.5f * __builtin_amdgcn_rcpf(zeta)
-                                       : copysignf(__builtin_amdgcn_rcpf(az + __builtin_sqrtf(fmaf(zeta, zeta, 1.f))), zeta);
-            c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
-            sv = t * c;
-          }
+      // the skip threshold. Every wave derives the step's rotations itself (lane k: pair k) and
+      // permutes the active ones, in pair order, to lanes 0 .. na - 1, so no record passes
+      // through LDS. The angles are read before the barrier, the updates come after it.
+      int p = 0, q = 0;
+      float c = 1.f, sv = 0.f;
+      if (lane < H) {
+        rr_pair(m, s, lane, p, q);
+        const int qq = q < K ? q : p;
+        const float apq = G[p * KS + qq], app = G[p * KS + p], aqq = G[qq * KS + qq];
+        if (q < K && (hot[p] || hot[q]) && fabsf(apq) > skip) {
+          // tan of the rotation angle, |t| <= 1 (hardware reciprocal and square roots: the
+          // rotation stays orthogonal to about 1e-7 and the basis is re-orthonormalised)
+          const float zeta = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
+          const float az = fabsf(zeta);
+          const float t = az > 1e15f ? 0.5f * __builtin_amdgcn_rcpf(zeta)
+                                     : copysignf(__builtin_amdgcn_rcpf(az + __builtin_sqrtf(fmaf(zeta, zeta, 1.f))), zeta);
+          c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
+          sv = t * c;
         }
-        const unsigned long long act = __ballot(sv != 0.f);
-        const int na = __popcll(act);
-        const int before = __popcll(act & ((1ull << tid) - 1ull));
-        if (tid < H) rot[sv != 0.f ? before : na + tid - before] = Rot{c, sv, p, q};
-        if (tid == 0) nact = na;
       }
+      const unsigned long long act = __ballot(sv != 0.f);
+      const int na = __popcll(act);
+      const int before = __popcll(act & ((1ull << lane) - 1ull));
+      // a permutation of the 64 lanes: active pairs first, then the rest, each in lane order
+      const int to = 4 * (sv != 0.f ? before : na + lane - before);
+      const int pc = __builtin_amdgcn_ds_permute(to, __float_as_int(c));
+      const int ps = __builtin_amdgcn_ds_permute(to, __float_as_int(sv));
+      const int pp0 = __builtin_amdgcn_ds_permute(to, p);
+      const int pq0 = __builtin_amdgcn_ds_permute(to, q);
+      // this wave's items: active pairs vkg + u ngV (u < kBatch covers them all); lane u
+      // fetches item u, and readlane broadcasts it below
+      const int from = 4 * min(vkg + lane * ngV, 63);
+      const float mc = __int_as_float(__builtin_amdgcn_ds_bpermute(from, pc));
+      const float ms = __int_as_float(__builtin_amdgcn_ds_bpermute(from, ps));
+      const int mp = __builtin_amdgcn_ds_bpermute(from, pp0);
+      const int mq = __builtin_amdgcn_ds_bpermute(from, pq0);
       __syncthreads();
-      const int na = __builtin_amdgcn_readfirstlane(nact);
       // rows: A <- J^T A over the active pairs. Each wave serves one group of pairs (every
-      // ngV-th active pair, kBatch at a time) and its lanes cover a run of columns; the
-      // rotation is wave-uniform and held in scalar registers
-      if (von) {
-        for (int k0 = vkg; k0 < na; k0 += kBatch * ngV) {
-          float c[kBatch], sn[kBatch], ap[kBatch], aq[kBatch];
-          int pK[kBatch], qK[kBatch];
-          // lane u (< kBatch, always active) loads the record of item u; readlane broadcasts
-          const Rot mine = rot[min(k0 + lane * ngV, kRotSlots - 1)];
+      // ngV-th active pair) and its lanes cover a run of columns; the rotation is wave-uniform
+      // and held in scalar registers
+      if (von && vkg < na) {
+        float cu[kBatch], sn[kBatch], ap[kBatch], aq[kBatch];
+        int pK[kBatch], qK[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            c[u] = lane_value(mine.c, u);
-            sn[u] = lane_value(mine.s, u);
-            pK[u] = __builtin_amdgcn_readlane(mine.p, u) * KS;
-            qK[u] = __builtin_amdgcn_readlane(mine.q, u) * KS;
+        for (int u = 0; u < kBatch; ++u) {
+          cu[u] = lane_value(mc, u);
+          sn[u] = lane_value(ms, u);
+          pK[u] = __builtin_amdgcn_readlane(mp, u) * KS;
+          qK[u] = __builtin_amdgcn_readlane(mq, u) * KS;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (vkg + u * ngV < na) {
+            ap[u] = G[pK[u] + vi];
+            aq[u] = G[qK[u] + vi];
           }
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u)
-            if (k0 + u * ngV < na) {
-              ap[u] = G[pK[u] + vi];
-              aq[u] = G[qK[u] + vi];
-            }
-#pragma unroll
-          for (int u = 0; u < kBatch; ++u)
-            if (k0 + u * ngV < na) {
-              G[pK[u] + vi] = c[u] * ap[u] - sn[u] * aq[u];
-              G[qK[u] + vi] = sn[u] * ap[u] + c[u] * aq[u];
-            }
-        }
+        for (int u = 0; u < kBatch; ++u)
+          if (vkg + u * ngV < na) {
+            G[pK[u] + vi] = cu[u] * ap[u] - sn[u] * aq[u];
+            G[qK[u] + vi] = sn[u] * ap[u] + cu[u] * aq[u];
+          }
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J, lanes over rows (row stride K + 1 is odd, so they hit
+      // columns: A <- A J, V <- V J, lanes over rows (row stride KS is odd, so they hit
       // distinct banks); the entry the rotation annihilates is set to 0
-      if (von) {
-        for (int k0 = vkg; k0 < na; k0 += kBatch * ngV) {
-          float c[kBatch], sn[kBatch], ap[kBatch], aq[kBatch], vp[kBatch], vq[kBatch];
-          int pp[kBatch], qq[kBatch];
-          const Rot mine = rot[min(k0 + lane * ngV, kRotSlots - 1)];
+      if (von && vkg < na) {
+        float cu[kBatch], sn[kBatch], ap[kBatch], aq[kBatch], vp[kBatch], vq[kBatch];
+        int pp[kBatch], qq[kBatch];
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u) {
-            c[u] = lane_value(mine.c, u);
-            sn[u] = lane_value(mine.s, u);
-            pp[u] = __builtin_amdgcn_readlane(mine.p, u);
-            qq[u] = __builtin_amdgcn_readlane(mine.q, u);
+        for (int u = 0; u < kBatch; ++u) {
+          cu[u] = lane_value(mc, u);
+          sn[u] = lane_value(ms, u);
+          pp[u] = __builtin_amdgcn_readlane(mp, u);
+          qq[u] = __builtin_amdgcn_readlane(mq, u);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (vkg + u * ngV < na) {
+            ap[u] = G[viK + pp[u]];
+            aq[u] = G[viK + qq[u]];
+            vp[u] = V[viK + pp[u]];
+            vq[u] = V[viK + qq[u]];
           }
 #pragma unroll
-          for (int u = 0; u < kBatch; ++u)
-            if (k0 + u * ngV < na) {
-              ap[u] = G[viK + pp[u]];
-              aq[u] = G[viK + qq[u]];
-              vp[u] = V[viK + pp[u]];
-              vq[u] = V[viK + qq[u]];
-            }
-#pragma unroll
-          for (int u = 0; u < kBatch; ++u)
-            if (k0 + u * ngV < na) {
-              G[viK + pp[u]] = vi == qq[u] ? 0.f : c[u] * ap[u] - sn[u] * aq[u];
-              G[viK + qq[u]] = vi == pp[u] ? 0.f : sn[u] * ap[u] + c[u] * aq[u];
-              V[viK + pp[u]] = c[u] * vp[u] - sn[u] * vq[u];
-              V[viK + qq[u]] = sn[u] * vp[u] + c[u] * vq[u];
-            }
-        }
+        for (int u = 0; u < kBatch; ++u)
+          if (vkg + u * ngV < na) {
+            G[viK + pp[u]] = vi == qq[u] ? 0.f : cu[u] * ap[u] - sn[u] * aq[u];
+            G[viK + qq[u]] = vi == pp[u] ? 0.f : sn[u] * ap[u] + cu[u] * aq[u];
+            V[viK + pp[u]] = cu[u] * vp[u] - sn[u] * vq[u];
+            V[viK + qq[u]] = sn[u] * vp[u] + cu[u] * vq[u];
+          }
       }
       __syncthreads();
     }
@@ -747,13 +743,22 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     if (sweeps == a.max_sweeps) atomicAdd(&a.sc->fallback_blocks, 1ull);  // not certified
   }
   __syncthreads();
-  // ---- Newton-Schulz: M = V^T V (T3), V <- 1.5 V - 0.5 V M, stored for the next iteration
+  // ---- clip factors from the diagonal of the certified A = V^T G V: a row of A whose
+  // diagonal exceeds 1 passed the off-diagonal test, so its diagonal is its eigenvalue to
+  // second order in the residual; every other row has a Gershgorin bound <= 1 and no clip
+  for (int i = tid; i < K; i += kBT) {
+    const float d = G[i * KS + i];
+    lam[i] = d > 1.f ? 1.f - 1.f / sqrtf(d) : 0.f;  // f_i of the clip
+  }
+  __syncthreads();
+  // ---- Newton-Schulz: V^T V over A, V <- 1.5 V - 0.5 V (V^T V), stored for the next
+  // iteration
   {
     f4 hr[kMaxT], hs[kSymHold];
     prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);
-    release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { T3[r * KS + c] = x; });
+    release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
     __syncthreads();
-    prod_rows<false>(V, KS, T3, KS, K, wave, i16, g4, hr);
+    prod_rows<false>(V, KS, G, KS, K, wave, i16, g4, hr);
     __syncthreads();
     release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) {
       V[r * KS + c] = 1.5f * V[r * KS + c] - 0.5f * x;
@@ -774,55 +779,6 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
       }
     }
   }
-  // ---- Rayleigh quotients lambda_i = ||v_i^T Y'||^2 over the column chunks: P = V^T Y' per
-  // chunk on MFMA tiles; wave w owns the row tiles I = w, w + 4 (both column tiles of each),
-  // so every lambda_i is summed by one wave in a fixed order
-  {
-    const int nt = (K + 15) >> 4;
-    float lacc[kRqTiles][4] = {};
-    auto rq_chunk = [&]() {
-#pragma unroll
-      for (int m = 0; m < kRqTiles; ++m) {
-        const int I = wave + kNW * m;
-        if (I < nt) {
-          f4 acc[kChunk / 16];
-          mfma_band<true, kChunk / 16>(V, KS, T3, CS, K, K, kChunk, I, 0, i16, g4, acc);
-          // each lane sums the squares of its own column over the chunks; the 16 columns of
-          // a tile (lanes i16 of one g4 group) are summed once after the last chunk
-#pragma unroll
-          for (int J = 0; J < kChunk / 16; ++J)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) lacc[m][v] = fmaf(acc[J][v], acc[J][v], lacc[m][v]);
-        }
-      }
-    };
-    // the loads of chunk c0 + 32 are issued before the products of chunk c0
-    float yv[kStage];
-    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
-    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
-      __syncthreads();
-      store_chunk(yv, K, srow, scol, T3, CS);
-      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
-      __syncthreads();
-      rq_chunk();
-    }
-#pragma unroll
-    for (int m = 0; m < kRqTiles; ++m) {
-      const int I = wave + kNW * m;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float sq = lacc[m][v];  // fixed order over the 16 lanes of the group
-        sq += __shfl_xor(sq, 1);
-        sq += __shfl_xor(sq, 2);
-        sq += __shfl_xor(sq, 4);
-        sq += __shfl_xor(sq, 8);
-        const int i = 16 * I + 4 * g4 + v;
-        if (I < nt && i16 == 0 && i < K)
-          lam[i] = sq > 1.f ? 1.f - 1.f / sqrtf(sq) : 0.f;  // f_i of the clip
-      }
-    }
-  }
-  __syncthreads();
   // indices of the clipped directions, in order
   __shared__ int ridx[112];
   __shared__ int nr;
@@ -835,26 +791,27 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
   __syncthreads();
   const int R = nr;
   // ---- Y+ = Y' - M Y' with M = V_R diag(f) V_R^T (K x K, symmetric), formed once per block:
-  // the clipped directions scaled by sqrt(f) are gathered as the rows of Ut (T3, R x K), so
-  // M = Ut^T Ut; then every column chunk of Y' is staged in T3 and each wave updates its row
-  // tile of the chunk (M in G, read as its own transpose).
+  // the clipped directions scaled by sqrt(f) are gathered as the rows of Ut (over V^T V, R x K),
+  // so M = Ut^T Ut (over the basis, which is stored); then every column chunk of Y' is staged
+  // over Ut and each wave updates its row tile of the chunk (M read as its own transpose).
   if (R > 0) {
     for (int e = tid; e < R * K; e += kBT) {
       const int n = e / K, r = e - (e / K) * K;
       const int i = ridx[n];
-      T3[n * KS + r] = V[r * KS + i] * sqrtf(lam[i]);
+      G[n * KS + r] = V[r * KS + i] * sqrtf(lam[i]);
     }
     __syncthreads();
     {
       f4 hs[kSymHold];
-      prod_sym<true>(T3, KS, T3, KS, K, wave, i16, g4, hs, R);
-      release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
+      prod_sym<true>(G, KS, G, KS, K, wave, i16, g4, hs, R);
+      __syncthreads();
+      release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { V[r * KS + c] = x; });
     }
     const int nt = (K + 15) >> 4;
     auto clip_chunk = [&](int c0) {
       if (wave < nt) {
         f4 acc[kChunk / 16];
-        mfma_band<true, kChunk / 16>(G, KS, T3, CS, K, K, kChunk, wave, 0, i16, g4, acc);
+        mfma_band<true, kChunk / 16>(V, KS, G, CS, K, K, kChunk, wave, 0, i16, g4, acc);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = 16 * wave + 4 * g4 + v;
@@ -862,7 +819,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
 #pragma unroll
             for (int J = 0; J < kChunk / 16; ++J) {
               const int cc = 16 * J + i16;
-              Yb[(long long)rr * ncol + c0 + cc] = T3[rr * CS + cc] - acc[J][v];
+              Yb[(long long)rr * ncol + c0 + cc] = G[rr * CS + cc] - acc[J][v];
             }
           }
         }
@@ -874,7 +831,7 @@ __global__ __launch_bounds__(kBT) void k_big_block(BigArgs a) {
     load_chunk(Yb, ncol, 0, K, srow, scol, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();  // M is complete (first chunk); the previous chunk's products are done
-      store_chunk(yv, K, srow, scol, T3, CS);
+      store_chunk(yv, K, srow, scol, G, CS);
       if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
       __syncthreads();
       clip_chunk(c0);
@@ -938,11 +895,7 @@ __global__ __launch_bounds__(kNT) void k_big_unpack(const float *Y, float *dst, 
   }
 }
 
-size_t big_lds_bytes(int K) {
-  const int KS = K + 1;
-  const int GS = KS > kGS ? KS : kGS;
-  return (size_t)(2 * K * GS + K * KS) * sizeof(float);
-}
+size_t big_lds_bytes(int K) { return (size_t)(2 * K * big_stride(K)) * sizeof(float); }
 
 hipError_t launch_big_block(const BigArgs &a, hipStream_t st) {
   // the dynamic-LDS limit, raised once per device (a bit per device id)
