@@ -57,7 +57,9 @@ enum {
 };
 
 /* Image and block geometry. n1, n2, n3 >= 2; 1 <= k1 <= n1; 1 <= k2 <= n2; k1*k2 <= 100
- * (larger blocks: S3TTV_EUNSUPPORTED); n1*n2*n3 < 2^31. */
+ * (larger blocks: S3TTV_EUNSUPPORTED); n1*n2*n3 < 2^31; for k1*k2 > 16 also fewer than 2^32
+ * entries in the block-column field, n1*n2 times 2 (3 for SSST) bands rounded up to 16
+ * (32 for SSST). */
 typedef struct {
   int32_t n1, n2, n3, k1, k2;
 } s3ttv_shape;

@@ -74,6 +74,10 @@ int32_t supported_shape(const s3ttv_shape *sh, int reg) {
     const size_t ncol = (size_t)block_comps(reg) * padded_bands(sh->n3, reg);
     if ((size_t)sh->k1 * sh->k2 * (ncol + 16) * sizeof(float) > kMaxLds)
       return S3TTV_EUNSUPPORTED;
+  } else {
+    // the large-block kernel addresses the gradient field by 32-bit entry offsets
+    const long long ncol = (long long)block_comps(reg) * padded_bands(sh->n3, reg);
+    if ((long long)sh->n1 * sh->n2 * ncol >= (1ll << 32)) return S3TTV_EUNSUPPORTED;
   }
   return S3TTV_OK;
 }

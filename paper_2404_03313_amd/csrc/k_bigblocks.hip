@@ -251,19 +251,53 @@ __device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4, co
 // staged in the basis array before the basis is loaded).
 __host__ __device__ constexpr int big_stride(int K) { return K + 1 > kGS + 1 ? K + 1 : kGS + 1; }
 
+// A K x K row-major matrix from global memory into LDS rows of stride KS, in two rounds of
+// kCopyRegs entries per thread; each round issues all of its loads before its first store.
+constexpr int kCopyRegs = (kBigMax * kBigMax + 2 * kBT - 1) / (2 * kBT);
+__device__ __forceinline__ void copy_in(const float *src, float *dst, int K, int KS, int tid) {
+  int r = tid / K, c = tid - (tid / K) * K;
+  const int dr = kBT / K, dc = kBT - (kBT / K) * K;
+  for (int j0 = 0; j0 < 2 * kCopyRegs; j0 += kCopyRegs) {
+    float x[kCopyRegs];
+#pragma unroll
+    for (int j = 0; j < kCopyRegs; ++j)
+      if ((j0 + j) * kBT < K * K) x[j] = src[min(tid + (j0 + j) * kBT, K * K - 1)];
+#pragma unroll
+    for (int j = 0; j < kCopyRegs; ++j) {
+      if (tid + (j0 + j) * kBT < K * K) dst[r * KS + c] = x[j];
+      r += dr;
+      c += dc;
+      if (c >= K) {
+        c -= K;
+        ++r;
+      }
+    }
+  }
+}
+
 // Simultaneous rotation steps before the cyclic sweeps (warm-started iterations): at most this
 // many, each damped to ||K||_F <= kSimCap.
 constexpr int kSimSteps = 12;
 constexpr float kSimCap = 0.7f;
 
-// The K x 32 chunk of Y at column c0 (row stride ncol) into registers: thread t holds rows
-// srow + kRowStep k, column scol. Loading the next chunk before working on the current one hides
-// the memory latency.
-__device__ inline void load_chunk(const float *Y, int ncol, int c0, int K, int srow, int scol,
-                                  float y[kStage]) {
+// The block's rows of Y (K x ncol, row-major) as a buffer resource: the chunk loops address
+// an entry by one per-lane byte offset (row srow, column scol) plus a wave-uniform one (the
+// chunk's column and the row step), so the staging needs no per-row address registers.
+// 0x00020000: the third descriptor word of a raw 32-bit buffer on gfx9-family chips.
+__device__ inline __amdgpu_buffer_rsrc_t y_rsrc(float *Yb, int K, int ncol) {
+  return __builtin_amdgcn_make_buffer_rsrc(Yb, (short)0, K * ncol * (int)sizeof(float), 0x00020000);
+}
+
+// The K x 32 chunk of Y at column c0 into registers: thread t holds rows srow + kRowStep k,
+// column scol (byte offset yo0 of row srow, column scol; rows kRowStep * ncol * 4 bytes apart).
+// Loading the next chunk before working on the current one hides the memory latency.
+__device__ inline void load_chunk(__amdgpu_buffer_rsrc_t rs, int yo0, int rstep, int c0, int K,
+                                  int srow, float y[kStage]) {
 #pragma unroll
   for (int k = 0; k < kStage; ++k)
-    if (srow + kRowStep * k < K) y[k] = Y[(long long)(srow + kRowStep * k) * ncol + c0 + scol];
+    if (srow + kRowStep * k < K)
+      y[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          rs, yo0, c0 * (int)sizeof(float) + k * rstep, 0));
 }
 
 __device__ inline void store_chunk(const float y[kStage], int K, int srow, int scol, float *T,
@@ -309,6 +343,9 @@ void k_big_block(BigArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int srow = tid >> 5, scol = tid & 31;  // chunk staging: rows srow + kRowStep k
+  const __amdgpu_buffer_rsrc_t yrs = y_rsrc(Yb, K, ncol);
+  const int yo0 = (srow * ncol + scol) * (int)sizeof(float);
+  const int rstep = kRowStep * ncol * (int)sizeof(float);
   {
     const int nt = (K + 15) >> 4, ntiles = nt * (nt + 1) / 2;
     int tI[kGramTiles], tJ[kGramTiles];
@@ -328,36 +365,37 @@ void k_big_block(BigArgs a) {
     // staging: thread t moves rows t / 32 + kRowStep k, column t mod 32 of each chunk; the field
     // offset of each row's pixel is fixed for the block
     // (no gradient field: the blocks are clipped as they are)
+    // (the field has fewer than 2^32 entries, checked at launch; rows past K read the first
+    // pixel's, and their sums are neither staged nor stored)
     const bool hasg = a.gradf != nullptr;
-    long long goff[kStage];
+    unsigned goff[kStage];
 #pragma unroll
     for (int k = 0; k < kStage; ++k) {
       const int r = srow + kRowStep * k;
       const int ra = r / a.k2, rc = r - ra * a.k2;
       goff[k] = hasg && r < K
-                    ? ((long long)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol
-                    : 0;
+                    ? ((unsigned)wrapm(p0 + ra, a.n1) * a.n2 + wrapm(q0 + rc, a.n2)) * ncol + scol
+                    : 0u;
     }
     // the loads of chunk c0 + 32 are issued before the products of chunk c0
     float yv[kStage], gv[kStage];
-    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
+    load_chunk(yrs, yo0, rstep, 0, K, srow, yv);
 #pragma unroll
-    for (int k = 0; k < kStage; ++k)
-      if (srow + kRowStep * k < K) gv[k] = hasg ? a.gradf[goff[k] + scol] : 0.f;
+    for (int k = 0; k < kStage; ++k) gv[k] = hasg ? a.gradf[goff[k]] : 0.f;
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kStage; ++k)
         if (srow + kRowStep * k < K) {
           const float y = yv[k] + a.gY * gv[k];
-          Yb[(long long)(srow + kRowStep * k) * ncol + c0 + scol] = y;
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y), yrs, yo0,
+                                                c0 * (int)sizeof(float) + k * rstep, 0);
           V[(srow + kRowStep * k) * kGS + scol] = y;
         }
       if (c0 + kChunk < ncol) {
-        load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
+        load_chunk(yrs, yo0, rstep, c0 + kChunk, K, srow, yv);
 #pragma unroll
-        for (int k = 0; k < kStage; ++k)
-          if (srow + kRowStep * k < K) gv[k] = hasg ? a.gradf[goff[k] + c0 + kChunk + scol] : 0.f;
+        for (int k = 0; k < kStage; ++k) gv[k] = hasg ? a.gradf[goff[k] + (unsigned)(c0 + kChunk)] : 0.f;
       }
       __syncthreads();
       // every tile slot of the wave runs (a slot past ntiles has rows past K, which read as
@@ -420,12 +458,12 @@ void k_big_block(BigArgs a) {
 
   // ---- basis: identity on the first use, else the stored one (orthonormal to rounding)
   float *Vg = a.V + blk * (long long)K * K;
-  {
+  if (a.first) {
     int r = tid / K, c = tid - (tid / K) * K;
     const int dr = kBT / K, dc = kBT - (kBT / K) * K;
 #pragma unroll 4
     for (int e = tid; e < K * K; e += kBT) {
-      V[r * KS + c] = a.first ? (r == c ? 1.f : 0.f) : Vg[e];
+      V[r * KS + c] = r == c ? 1.f : 0.f;
       r += dr;
       c += dc;
       if (c >= K) {
@@ -433,6 +471,8 @@ void k_big_block(BigArgs a) {
         ++r;
       }
     }
+  } else {
+    copy_in(Vg, V, K, KS, tid);
   }
   __syncthreads();
   // ---- A = V^T (G V): H = G V over G, then A over H (exactly symmetric). G is symmetric, so
@@ -460,58 +500,55 @@ void k_big_block(BigArgs a) {
   const int vkg = wave / wpg, vi = (wave - vkg * wpg) * cpw + lane, viK = vi * KS;
   const bool von = lane < cpw && vi < K;  // lanes 0 .. kBatch - 1 are always on (cpw > 16)
   // certificate (see the header): four threads per row; marks the rows that fail it (all rows
-  // once `all_hot`) and returns whether any does, with the tolerance in `tol`
+  // once `all_hot`) and returns whether any does, with the tolerance in `tol`. The diagonal
+  // is copied to lam[] for the rotation generator of a simultaneous step.
   float tol = -1.f;
   auto certify = [&](bool all_hot) -> bool {
-    if (tol < 0.f) {
-      // ||A||_F on the first call; rotations and the re-derivation of A from an orthonormal
-      // basis keep it (to rounding), so later calls reuse the tolerance
-      float fro = 0.f;
-      int r = tid / K, c = tid - (tid / K) * K;
-      const int dr = kBT / K, dc = kBT - (kBT / K) * K;
-#pragma unroll 4
-      for (int e = tid; e < K * K; e += kBT) {
-        fro = fmaf(G[r * KS + c], G[r * KS + c], fro);
-        r += dr;
-        c += dc;
-        if (c >= K) {
-          c -= K;
-          ++r;
-        }
-      }
-      for (int mm = 32; mm >= 1; mm >>= 1) fro += __shfl_xor(fro, mm);
-      if ((tid & 63) == 0) red[tid >> 6] = fro;
-      __syncthreads();
-      float fsum = 0.f;
-#pragma unroll
-      for (int w = 0; w < kNW; ++w) fsum += red[w];  // fixed order
-      tol = 1e-6f * sqrtf(fsum);
-    }
-    __syncthreads();  // the previous call's readers of wfail are done
-    bool fail = false;
+    // which diagonal entries exceed kNearOne, as two 64-bit masks every wave forms itself
+    const float d0 = G[min(lane, K - 1) * (KS + 1)], d1 = G[min(lane + 64, K - 1) * (KS + 1)];
+    const unsigned long long dm0 = __ballot(lane < K && d0 > kNearOne);
+    const unsigned long long dm1 = __ballot(lane + 64 < K && d1 > kNearOne);
+    const bool first = tol < 0.f;
+    __syncthreads();  // the previous call's readers of wfail and red are done
+    float sum = 0.f, mx = 0.f, fsq = 0.f, dr = 0.f;
+    const int r = tid >> 2, part = tid & 3;
     if (tid < 4 * K) {  // four consecutive lanes per row, columns interleaved
-      const int r = tid >> 2, part = tid & 3;
-      const float dr = G[r * KS + r];
-      float sum = 0.f, mx = 0.f;
+      dr = G[r * KS + r];
+      const bool rnear = dr > kNearOne;
 #pragma unroll 5
       for (int c = part; c < K; c += 4) {
-        const float x = c == r ? 0.f : fabsf(G[r * KS + c]);
+        const float g = G[r * KS + c];
+        const float x = c == r ? 0.f : fabsf(g);
+        fsq = fmaf(g, g, fsq);
         sum += x;
-        if (dr > kNearOne || G[c * KS + c] > kNearOne) mx = fmaxf(mx, x);
+        const bool cnear = ((c < 64 ? dm0 >> c : dm1 >> (c - 64)) & 1ull) != 0;
+        mx = fmaxf(mx, rnear || cnear ? x : 0.f);
       }
       sum += __shfl_xor(sum, 1);  // fixed order within the group of four
       sum += __shfl_xor(sum, 2);
       mx = fmaxf(mx, __shfl_xor(mx, 1));
       mx = fmaxf(mx, __shfl_xor(mx, 2));
-      if (part == 0) {
-        fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
-        hot[r] = fail || all_hot;
-        lam[r] = dr;  // the diagonal, for the rotation generator of a simultaneous step
-      }
+    }
+    if (first) {
+      // ||A||_F on the first call; rotations and the re-derivation of A from an orthonormal
+      // basis keep it (to rounding), so later calls reuse the tolerance
+      for (int mm = 32; mm >= 1; mm >>= 1) fsq += __shfl_xor(fsq, mm);
+      if (lane == 0) red[wave] = fsq;
+      __syncthreads();
+      float fs = 0.f;
+#pragma unroll
+      for (int w = 0; w < kNW; ++w) fs += red[w];  // fixed order
+      tol = 1e-6f * sqrtf(fs);
+    }
+    bool fail = false;
+    if (tid < 4 * K && part == 0) {
+      fail = mx > tol || (dr <= kNearOne && dr + sum > 1.f);
+      hot[r] = fail || all_hot;
+      lam[r] = dr;
     }
     // one flag per wave (no atomics on a shared word)
     const bool wf = __any(fail);
-    if ((tid & 63) == 0) wfail[tid >> 6] = wf;
+    if (lane == 0) wfail[wave] = wf;
     __syncthreads();
     bool notyet = false;
 #pragma unroll
@@ -524,26 +561,34 @@ void k_big_block(BigArgs a) {
   // once removes them to second order: K_ij = tan(theta_ij) of the 2 x 2 rotation that zeroes
   // A_ij, for the pairs with a row that fails the certificate (K exactly skew), damped to
   // ||K||_F <= kSimCap; J = I + K + K^2 / 2; V <- V J, which drifts from orthonormal by K^4 / 4
-  // per step (J^T J = I + K^4 / 4). After a step with ||K||_F > 0.01 (drift above 2.5e-9) V is
-  // re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4); after every
+  // per step (J^T J = I + K^4 / 4). After a step whose drift bound ||K^T K||_F^2 / 4 exceeds
+  // 2.5e-9 V is re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4); after every
   // step A is re-derived from the Gram copy, so the certificate is always judged on V^T G V of
   // an orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
   int ssteps = 0;
+  bool certified = false;  // by the last certificate of the simultaneous steps
   if (!a.first && a.Gg) {
     const float *Gb = Ggb_all(a, blk, K);
     for (; ssteps < kSimSteps; ++ssteps) {
-      if (!certify(false)) break;
+      if (!certify(false)) {
+        certified = true;
+        break;
+      }
       // the generator K (tangents) over A: entry (r, c) needs A_rc and the diagonal (copied by
       // the certificate), so each thread overwrites only what it read
       float kf2 = 0.f;
       {
+        const unsigned long long hm0 = __ballot(lane < K && hot[min(lane, K - 1)]);
+        const unsigned long long hm1 = __ballot(lane + 64 < K && hot[min(lane + 64, K - 1)]);
         // entry e = r K + c of this thread, stepped without divisions
         int r = tid / K, c = tid - (tid / K) * K;
         const int dr = kBT / K, dc = kBT - (kBT / K) * K;
 #pragma unroll 4
         for (int e = tid; e < K * K; e += kBT) {
           float t = 0.f;
-          if (r != c && (hot[r] || hot[c])) {
+          const bool hr_ = ((r < 64 ? hm0 >> r : hm1 >> (r - 64)) & 1ull) != 0;
+          const bool hc_ = ((c < 64 ? hm0 >> c : hm1 >> (c - 64)) & 1ull) != 0;
+          if (r != c && (hr_ || hc_)) {
             // hardware square root and reciprocal: (c, r) gets exactly -t, so K stays skew
             const float arc = G[r * KS + c], den = lam[c] - lam[r];
             const float sg = (den > 0.f || (den == 0.f && r < c)) ? 1.f : -1.f;
@@ -568,24 +613,32 @@ void k_big_block(BigArgs a) {
 #pragma unroll
       for (int w = 0; w < kNW; ++w) ksum += red[w];
       const float sc = ksum > kSimCap * kSimCap ? kSimCap * rsqrtf(ksum) : 1.f;
-      const bool rough = ksum * sc * sc > 1e-4f;
       f4 hr[kMaxT], hs[kSymHold];
-      // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K, over K
+      // J = I + sc K + (sc^2 / 2) K^2, with K^2 = -K^T K, over K; ||K^T K||_F^2 on the way
       prod_sym<true>(G, KS, G, KS, K, wave, i16, g4, hs);
-      __syncthreads();
+      __syncthreads();  // every thread has read red[] (ksum) and K
+      float kt2 = 0.f;
       release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) {
         G[r * KS + c] = (r == c ? 1.f : 0.f) + sc * G[r * KS + c] - 0.5f * sc * sc * x;
+        kt2 = fmaf(x, x, kt2);
       });
+      for (int mm = 32; mm >= 1; mm >>= 1) kt2 += __shfl_xor(kt2, mm);
+      if (lane == 0) red[wave] = kt2;
       __syncthreads();
+      float kts = 0.f;
+#pragma unroll
+      for (int w = 0; w < kNW; ++w) kts += red[w];  // fixed order
+      // V J drifts from orthonormal by J^T J - I = (sc K)^4 / 4, whose norm is
+      // sc^4 ||K^T K||_2^2 / 4 <= sc^4 ||K^T K||_F^2 / 4 (K is skew, so K^4 = (K^T K)^2)
+      const float e0 = 0.25f * (sc * sc) * (sc * sc) * kts;
       prod_rows<false>(V, KS, G, KS, K, wave, i16, g4, hr);  // V J
       __syncthreads();
       release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { V[r * KS + c] = x; });
       __syncthreads();
-      if (rough) {
-        // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound ||K||_F^4 / 4, mapped by
-        // e -> 3 e^2 / 4 per step, is below 1e-8
-        const float kk = ksum * sc * sc;
-        float drift = 0.75f * (0.25f * kk * kk) * (0.25f * kk * kk);
+      if (e0 > 2.5e-9f) {
+        // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound, mapped by e -> 3 e^2 / 4
+        // per step, is below 1e-8
+        float drift = 0.75f * e0 * e0;
         int nns = 1;
         while (drift > 1e-8f && nns < 4) {
           drift = 0.75f * drift * drift;
@@ -632,7 +685,7 @@ void k_big_block(BigArgs a) {
   }
 
   int sweeps = 0;
-  for (; sweeps < a.max_sweeps; ++sweeps) {
+  for (; !certified && sweeps < a.max_sweeps; ++sweeps) {
     if (!certify(sweeps >= kRestricted)) break;
     const float skip = 0.1f * tol;
     for (int s = 0; s < m - 1; ++s) {
@@ -808,6 +861,8 @@ void k_big_block(BigArgs a) {
       release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { V[r * KS + c] = x; });
     }
     const int nt = (K + 15) >> 4;
+    // byte offset of this lane's first output (row 16 wave + 4 g4, column i16 of the chunk)
+    const int co0 = ((16 * wave + 4 * g4) * ncol + i16) * (int)sizeof(float);
     auto clip_chunk = [&](int c0) {
       if (wave < nt) {
         f4 acc[kChunk / 16];
@@ -819,7 +874,9 @@ void k_big_block(BigArgs a) {
 #pragma unroll
             for (int J = 0; J < kChunk / 16; ++J) {
               const int cc = 16 * J + i16;
-              Yb[(long long)rr * ncol + c0 + cc] = G[rr * CS + cc] - acc[J][v];
+              __builtin_amdgcn_raw_buffer_store_b32(
+                  __float_as_uint(G[rr * CS + cc] - acc[J][v]), yrs, co0,
+                  (c0 + v * ncol + 16 * J) * (int)sizeof(float), 0);
             }
           }
         }
@@ -828,11 +885,11 @@ void k_big_block(BigArgs a) {
     // the loads of chunk c0 + 32 (a column range this pass has not written) are issued before
     // the products of chunk c0
     float yv[kStage];
-    load_chunk(Yb, ncol, 0, K, srow, scol, yv);
+    load_chunk(yrs, yo0, rstep, 0, K, srow, yv);
     for (int c0 = 0; c0 < ncol; c0 += kChunk) {
       __syncthreads();  // M is complete (first chunk); the previous chunk's products are done
       store_chunk(yv, K, srow, scol, G, CS);
-      if (c0 + kChunk < ncol) load_chunk(Yb, ncol, c0 + kChunk, K, srow, scol, yv);
+      if (c0 + kChunk < ncol) load_chunk(yrs, yo0, rstep, c0 + kChunk, K, srow, yv);
       __syncthreads();
       clip_chunk(c0);
     }

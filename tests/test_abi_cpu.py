@@ -76,7 +76,12 @@ def test_dual_blocks_workspace_query(k, code):
                                         ((8, 8, 1201, 4, 4), nt.EUNSUPPORTED),
                                         ((8, 8, 3000, 2, 2), 0),
                                         # more rows: one workgroup per block, any band count
-                                        ((12, 12, 3000, 5, 4), 0)])
+                                        ((12, 12, 3000, 5, 4), 0),
+                                        # ... while the gradient field (n1 n2 x 2 Bp) has
+                                        # fewer than 2^32 entries: 11000^2 x 64 does not,
+                                        # the fused path (4 x 4) takes it
+                                        ((11000, 11000, 17, 5, 5), nt.EUNSUPPORTED),
+                                        ((11000, 11000, 17, 4, 4), 0)])
 def test_shape_validation(shape, code):
     sz = ctypes.c_size_t()
     sh = nt.Shape(*shape)
