@@ -247,6 +247,9 @@ __device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4, co
   }
 }
 
+// Entries of U (at most 32 x K) a thread gathers in registers before writing them over the basis.
+constexpr int kUtRegs = (32 * kBigMax + kBT - 1) / kBT;
+
 // Row stride of the two K x K arrays: odd, and above the Gram chunk stride kGS (the chunks are
 // staged in the basis array before the basis is loaded).
 __host__ __device__ constexpr int big_stride(int K) { return K + 1 > kGS + 1 ? K + 1 : kGS + 1; }
@@ -843,11 +846,79 @@ void k_big_block(BigArgs a) {
   }
   __syncthreads();
   const int R = nr;
-  // ---- Y+ = Y' - M Y' with M = V_R diag(f) V_R^T (K x K, symmetric), formed once per block:
-  // the clipped directions scaled by sqrt(f) are gathered as the rows of Ut (over V^T V, R x K),
-  // so M = Ut^T Ut (over the basis, which is stored); then every column chunk of Y' is staged
-  // over Ut and each wave updates its row tile of the chunk (M read as its own transpose).
-  if (R > 0) {
+  const int nt = (K + 15) >> 4;
+  // byte offset of this lane's first output (row 16 wave + 4 g4, column i16 of a chunk)
+  const int co0 = ((16 * wave + 4 * g4) * ncol + i16) * (int)sizeof(float);
+  // Y+ = Y' - acc for this wave's row tile of the chunk staged at stg (stride CS)
+  auto store_out = [&](int c0, const float *stg, const f4 (&acc)[kChunk / 16]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rr = 16 * wave + 4 * g4 + v;
+      if (rr < K) {
+#pragma unroll
+        for (int J = 0; J < kChunk / 16; ++J) {
+          const int cc = 16 * J + i16;
+          __builtin_amdgcn_raw_buffer_store_b32(
+              __float_as_uint(stg[rr * CS + cc] - acc[J][v]), yrs, co0,
+              (c0 + v * ncol + 16 * J) * (int)sizeof(float), 0);
+        }
+      }
+    }
+  };
+  if (R > 0 && R <= 32 && K * (KS - CS) >= 32 * CS) {
+    // ---- Y+ = Y' - U^T (U Y') with U = diag(sqrt f) V_R^T (R x K, over the basis, which is
+    // stored): per column chunk (staged in the first array) P = U Y' (R x 32, after the chunk)
+    // by the waves of its 16 x 16 tiles, then each wave its row tile of Y' - U^T P
+    {
+      float ut[kUtRegs];
+#pragma unroll
+      for (int j = 0; j < kUtRegs; ++j) {
+        const int e = tid + j * kBT;
+        if (e < R * K) {
+          const int n = e / K, r = e - (e / K) * K;
+          const int i = ridx[n];
+          ut[j] = V[r * KS + i] * sqrtf(lam[i]);
+        }
+      }
+      __syncthreads();  // every read of the basis is done
+#pragma unroll
+      for (int j = 0; j < kUtRegs; ++j) {
+        const int e = tid + j * kBT;
+        if (e < R * K) {
+          const int n = e / K, r = e - (e / K) * K;
+          V[n * KS + r] = ut[j];
+        }
+      }
+    }
+    float *P = G + K * CS;
+    const int nR = (R + 15) >> 4;
+    float yv[kStage];
+    load_chunk(yrs, yo0, rstep, 0, K, srow, yv);
+    for (int c0 = 0; c0 < ncol; c0 += kChunk) {
+      __syncthreads();  // U complete (first chunk); the previous chunk's products are done
+      store_chunk(yv, K, srow, scol, G, CS);
+      if (c0 + kChunk < ncol) load_chunk(yrs, yo0, rstep, c0 + kChunk, K, srow, yv);
+      __syncthreads();
+      if (wave < 2 * nR) {
+        f4 acc[1];
+        mfma_band<false, 1>(V, KS, G, CS, K, R, kChunk, wave >> 1, wave & 1, i16, g4, acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          P[(16 * (wave >> 1) + 4 * g4 + v) * CS + 16 * (wave & 1) + i16] = acc[0][v];
+      }
+      __syncthreads();
+      if (wave < nt) {
+        f4 acc[kChunk / 16];
+        mfma_band<true, kChunk / 16>(V, KS, P, CS, R, K, kChunk, wave, 0, i16, g4, acc);
+        store_out(c0, G, acc);
+      }
+    }
+  } else if (R > 0) {
+    // ---- Y+ = Y' - M Y' with M = V_R diag(f) V_R^T (K x K, symmetric), formed once per
+    // block: the clipped directions scaled by sqrt(f) are gathered as the rows of U (over
+    // V^T V, R x K), so M = U^T U (over the basis, which is stored); then every column chunk of
+    // Y' is staged over U and each wave updates its row tile of the chunk (M read as its own
+    // transpose)
     for (int e = tid; e < R * K; e += kBT) {
       const int n = e / K, r = e - (e / K) * K;
       const int i = ridx[n];
@@ -860,28 +931,6 @@ void k_big_block(BigArgs a) {
       __syncthreads();
       release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { V[r * KS + c] = x; });
     }
-    const int nt = (K + 15) >> 4;
-    // byte offset of this lane's first output (row 16 wave + 4 g4, column i16 of the chunk)
-    const int co0 = ((16 * wave + 4 * g4) * ncol + i16) * (int)sizeof(float);
-    auto clip_chunk = [&](int c0) {
-      if (wave < nt) {
-        f4 acc[kChunk / 16];
-        mfma_band<true, kChunk / 16>(V, KS, G, CS, K, K, kChunk, wave, 0, i16, g4, acc);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int rr = 16 * wave + 4 * g4 + v;
-          if (rr < K) {
-#pragma unroll
-            for (int J = 0; J < kChunk / 16; ++J) {
-              const int cc = 16 * J + i16;
-              __builtin_amdgcn_raw_buffer_store_b32(
-                  __float_as_uint(G[rr * CS + cc] - acc[J][v]), yrs, co0,
-                  (c0 + v * ncol + 16 * J) * (int)sizeof(float), 0);
-            }
-          }
-        }
-      }
-    };
     // the loads of chunk c0 + 32 (a column range this pass has not written) are issued before
     // the products of chunk c0
     float yv[kStage];
@@ -891,7 +940,11 @@ void k_big_block(BigArgs a) {
       store_chunk(yv, K, srow, scol, G, CS);
       if (c0 + kChunk < ncol) load_chunk(yrs, yo0, rstep, c0 + kChunk, K, srow, yv);
       __syncthreads();
-      clip_chunk(c0);
+      if (wave < nt) {
+        f4 acc[kChunk / 16];
+        mfma_band<true, kChunk / 16>(V, KS, G, CS, K, K, kChunk, wave, 0, i16, g4, acc);
+        store_out(c0, G, acc);
+      }
     }
   }
 }
