@@ -21,10 +21,12 @@
 //   touches a few rows and columns of A instead of all of them;
 //   lambda_i = A_ii, the diagonal of the certified A (the rows with A_ii > 1 are among those
 //   whose off-diagonal entries passed the test, so A_ii is their eigenvalue to second order);
-//   one Newton-Schulz step V <- V (3 I - V^T V) / 2 restores orthonormality lost to rounding;
+//   one Newton-Schulz step V <- V (3 I - V^T V) / 2 restores orthonormality lost to rounding
+//   (unless Newton-Schulz steps already followed the last change of V);
 //   Y+ = Y' - M Y',  M = V_R diag(1 - lambda^-1/2) V_R^T   over R = {i : lambda_i > 1}
-// which is the spectral clip of step 10 (eqs. ProxConjugate, prox_nuclear_norm). The basis is
-// kept for the next iteration.
+// which is the spectral clip of step 10 (eqs. ProxConjugate, prox_nuclear_norm), formed as
+// Y' - U^T (U Y') with U = diag(1 - lambda^-1/2)^1/2 V_R^T when at most 32 directions clip,
+// else through M. The basis is kept for the next iteration.
 //
 // The overlap-add sum_l P_l^T Y_l is a gather (each pixel reads its K windows in a fixed
 // order), so results are reproducible.
@@ -570,6 +572,9 @@ void k_big_block(BigArgs a) {
   // an orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
   int ssteps = 0;
   bool certified = false;  // by the last certificate of the simultaneous steps
+  // V orthonormal to rounding: as stored (or the identity), or re-orthonormalised after its
+  // last change
+  bool fresh = true;
   if (!a.first && a.Gg) {
     const float *Gb = Ggb_all(a, blk, K);
     for (; ssteps < kSimSteps; ++ssteps) {
@@ -638,6 +643,7 @@ void k_big_block(BigArgs a) {
       __syncthreads();
       release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { V[r * KS + c] = x; });
       __syncthreads();
+      fresh = false;
       if (e0 > 2.5e-9f) {
         // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound, mapped by e -> 3 e^2 / 4
         // per step, is below 1e-8
@@ -658,6 +664,7 @@ void k_big_block(BigArgs a) {
           });
           __syncthreads();
         }
+        fresh = true;
       }
       // A = V^T G V from the Gram copy: G back into LDS, H = G V over it (G symmetric, read as
       // G^T), then A over H
@@ -690,6 +697,7 @@ void k_big_block(BigArgs a) {
   int sweeps = 0;
   for (; !certified && sweeps < a.max_sweeps; ++sweeps) {
     if (!certify(sweeps >= kRestricted)) break;
+    fresh = false;
     const float skip = 0.1f * tol;
     for (int s = 0; s < m - 1; ++s) {
       // rotation angles; a pair rotates only if a row of it failed the certificate at the
@@ -807,9 +815,9 @@ void k_big_block(BigArgs a) {
     lam[i] = d > 1.f ? 1.f - 1.f / sqrtf(d) : 0.f;  // f_i of the clip
   }
   __syncthreads();
-  // ---- Newton-Schulz: V^T V over A, V <- 1.5 V - 0.5 V (V^T V), stored for the next
-  // iteration
-  {
+  // ---- Newton-Schulz: V^T V over A, V <- 1.5 V - 0.5 V (V^T V), unless V is orthonormal to
+  // rounding already; V is stored for the next iteration unless it is the stored one
+  if (!fresh) {
     f4 hr[kMaxT], hs[kSymHold];
     prod_sym<true>(V, KS, V, KS, K, wave, i16, g4, hs);
     release_sym(K, wave, i16, g4, hs, [&](int r, int c, float x) { G[r * KS + c] = x; });
@@ -821,7 +829,7 @@ void k_big_block(BigArgs a) {
     });
     __syncthreads();
   }
-  {
+  if (ssteps > 0 || sweeps > 0) {
     int r = tid / K, c = tid - (tid / K) * K;
     const int dr = kBT / K, dc = kBT - (kBT / K) * K;
 #pragma unroll 4
