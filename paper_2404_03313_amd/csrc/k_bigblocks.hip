@@ -284,6 +284,9 @@ __device__ __forceinline__ void copy_in(const float *src, float *dst, int K, int
 // many, each damped to ||K||_F <= kSimCap.
 constexpr int kSimSteps = 12;
 constexpr float kSimCap = 0.7f;
+// Orthonormality defect ||V^T V - I|| the Newton-Schulz steps of a simultaneous step aim below:
+// the FP32 products that form V J and V^T V leave defects of this order themselves.
+constexpr float kDriftTol = 1e-7f;
 
 // The block's rows of Y (K x ncol, row-major) as a buffer resource: the chunk loops address
 // an entry by one per-lane byte offset (row srow, column scol) plus a wave-uniform one (the
@@ -567,9 +570,10 @@ void k_big_block(BigArgs a) {
   // A_ij, for the pairs with a row that fails the certificate (K exactly skew), damped to
   // ||K||_F <= kSimCap; J = I + K + K^2 / 2; V <- V J, which drifts from orthonormal by K^4 / 4
   // per step (J^T J = I + K^4 / 4). After a step whose drift bound ||K^T K||_F^2 / 4 exceeds
-  // 2.5e-9 V is re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4); after every
-  // step A is re-derived from the Gram copy, so the certificate is always judged on V^T G V of
-  // an orthonormal V. The cyclic sweeps below finish whatever the certificate still rejects.
+  // kDriftTol V is re-orthonormalised by Newton-Schulz steps (each maps a drift e to 3 e^2 / 4);
+  // after every step A is re-derived from the Gram copy, so the certificate is always judged on
+  // V^T G V of an orthonormal V. The cyclic sweeps below finish whatever the certificate still
+  // rejects.
   int ssteps = 0;
   bool certified = false;  // by the last certificate of the simultaneous steps
   // V orthonormal to rounding: as stored (or the identity), or re-orthonormalised after its
@@ -644,12 +648,12 @@ void k_big_block(BigArgs a) {
       release_rows(K, wave, i16, g4, hr, [&](int r, int c, float x) { V[r * KS + c] = x; });
       __syncthreads();
       fresh = false;
-      if (e0 > 2.5e-9f) {
+      if (e0 > kDriftTol) {
         // Newton-Schulz V <- V (3 I - V^T V) / 2 until the drift bound, mapped by e -> 3 e^2 / 4
-        // per step, is below 1e-8
+        // per step, is below kDriftTol
         float drift = 0.75f * e0 * e0;
         int nns = 1;
-        while (drift > 1e-8f && nns < 4) {
+        while (drift > kDriftTol && nns < 4) {
           drift = 0.75f * drift * drift;
           ++nns;
         }

@@ -97,6 +97,36 @@ def test_spectral_clip_large_blocks(device, nblk, K, ncols):
     assert worst < 2e-5   # the bound of the K <= 16 clip; measured 3e-6 at K = 100
 
 
+@pytest.mark.parametrize("R", [1, 16, 32, 33, 100])
+def test_spectral_clip_rank_boundary(device, R):
+    """The clip of K = 100 blocks of 2 x 198 columns (the paper's 10 x 10 windows) with exactly
+    R singular values above 1 (Alg. 1 step 10 by eq. ProxConjugate), against FP64 singular
+    value decompositions. Up to 32 clipped directions the kernel forms Y' - U^T (U Y') with
+    U = diag(f)^1/2 V_R^T, beyond that Y' - M Y' with the K x K matrix M; R = 32 and 33 sit on
+    either side of the switch."""
+    K, ncols, nblk = 100, 396, 6
+    print(f"op_spectral_clip K={K} ncols={ncols} clipped rank {R}", flush=True)
+    rng = np.random.default_rng(100 + R)
+    Y = np.empty((nblk, K, ncols))
+    for b in range(nblk):
+        U, _ = np.linalg.qr(rng.normal(size=(K, K)))
+        W, _ = np.linalg.qr(rng.normal(size=(ncols, K)))
+        sv = np.concatenate([rng.uniform(1.05, 3.0, R), rng.uniform(0.05, 0.95, K - R)])
+        Y[b] = (U * sv) @ W.T
+    Y32 = Y.astype(np.float32)
+    got = nt.op_spectral_clip(torch.from_numpy(Y32).to(device)).cpu().numpy().astype(np.float64)
+    Y64 = Y32.astype(np.float64)
+    worst = 0.0
+    for b in range(nblk):
+        want = oracle.dual_nuclear(Y64[b], 0.25)
+        assert np.sum(np.linalg.svd(Y64[b], compute_uv=False) > 1.0) == R
+        err = np.linalg.norm(got[b] - want) / max(np.linalg.norm(want), 1e-30)
+        worst = max(worst, err)
+        assert np.linalg.norm(got[b], 2) <= 1 + 1e-4
+    print(f"  worst relative L2 error {worst:.2e}", flush=True)
+    assert worst < 2e-5
+
+
 @pytest.mark.timeout(900)
 def test_paper_shape_parity_and_invariants(device):
     """The paper's shape, 100 x 100 x 198 with 10 x 10 windows (K = 100): elementwise parity
