@@ -972,11 +972,26 @@ __global__ __launch_bounds__(kNT) void k_big_overlap(BigArgs a, float *Z) {
     const int col = (int)(idx - pix * ncol);
     const int i = (int)(pix / a.n2), j = (int)(pix - (long long)i * a.n2);
     float s = 0.f;
-    for (int ra = 0; ra < a.k1; ++ra)
-      for (int rc = 0; rc < a.k2; ++rc) {
-        const long long blk = (long long)wrapm(i - ra, a.n1) * a.n2 + wrapm(j - rc, a.n2);
-        s += a.Y[(blk * K + ra * a.k2 + rc) * ncol + col];
+    for (int ra = 0; ra < a.k1; ++ra) {
+      const long long rowb = (long long)wrapm(i - ra, a.n1) * a.n2;
+      const float *Yr = a.Y + (long long)(ra * a.k2) * ncol + col;
+      // five windows' loads in flight, summed in the same order as one at a time
+      int rc = 0;
+      for (; rc + 5 <= a.k2; rc += 5) {
+        float x[5];
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+          const long long blk = rowb + wrapm(j - rc - u, a.n2);
+          x[u] = Yr[(blk * K + rc + u) * ncol];
+        }
+#pragma unroll
+        for (int u = 0; u < 5; ++u) s += x[u];
       }
+      for (; rc < a.k2; ++rc) {
+        const long long blk = rowb + wrapm(j - rc, a.n2);
+        s += Yr[(blk * K + rc) * ncol];
+      }
+    }
     Z[idx] = s;
   }
 }
