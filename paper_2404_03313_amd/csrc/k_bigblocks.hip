@@ -11,14 +11,14 @@
 //   second iteration on, up to kSimSteps simultaneous rotation steps on MFMA (all pairs at
 //   once, J = I + K + K^2/2, see below) usually reach the certificate; then
 //   parallel cyclic Jacobi on A (round-robin pair order, all K/2 rotations of a step at once:
-//   a row pass and a column pass, accumulated into V) until a certificate holds: every off-diagonal entry in a row or column
-//   whose diagonal exceeds 0.999 is at most 1e-6 ||A||_F (about the FP32 rounding level of
-//   the rotations), and every other row has a Gershgorin bound <= 1, so no eigenvalue above 1
-//   hides among them (the clip factor 1 - lambda^-1/2 is continuous at 1, so eigenvalues
-//   next to 1 need no separation). A sweep rotates
-//   only pairs with a row that failed this test when the sweep began (a pair of two certified
-//   rows needs nothing; from the fifth sweep on, every pair), so with the warm basis a step
-//   touches a few rows and columns of A instead of all of them;
+//   a row pass and a column pass, accumulated into V) until a certificate holds: every
+//   off-diagonal entry in a row or column whose diagonal exceeds 0.999 is at most
+//   1e-6 ||A||_F (about the FP32 rounding level of the rotations), and every other row has a
+//   Gershgorin bound <= 1, so no eigenvalue above 1 hides among them (the clip factor
+//   1 - lambda^-1/2 is continuous at 1, so eigenvalues next to 1 need no separation). A sweep
+//   rotates only pairs with a row that failed this test when the sweep began (a pair of two
+//   certified rows needs nothing; from the fifth sweep on, every pair), so with the warm basis
+//   a step touches a few rows and columns of A instead of all of them;
 //   lambda_i = A_ii, the diagonal of the certified A (the rows with A_ii > 1 are among those
 //   whose off-diagonal entries passed the test, so A_ii is their eigenvalue to second order);
 //   one Newton-Schulz step V <- V (3 I - V^T V) / 2 restores orthonormality lost to rounding
@@ -142,8 +142,8 @@ static_assert(kBigMax <= 16 * kMaxT && kMaxT <= kNW, "one row of tiles per wave"
 // General product: wave w < nt computes row tile I = w against every column tile (the A
 // operand is read once per row).
 template <bool TA>
-__device__ __forceinline__ void prod_rows(const float *A, int as, const float *B, int bs, int K, int wave,
-                                 int i16, int g4, f4 acc[kMaxT]) {
+__device__ __forceinline__ void prod_rows(const float *A, int as, const float *B, int bs, int K,
+                                          int wave, int i16, int g4, f4 acc[kMaxT]) {
   const int nt = (K + 15) >> 4;
   // tiles past nt (K <= 96) read clamped columns and are not released
   if (wave < nt) mfma_band<TA, kMaxT>(A, as, B, bs, K, K, K, wave, 0, i16, g4, acc);
@@ -165,7 +165,7 @@ __device__ __forceinline__ void release_rows(int K, int wave, int i16, int g4, c
   }
 }
 
-// Product with a symmetric result (V^T V, V^T G V, K^T K, J^T A J): only the tiles on and
+// Product with a symmetric result (V^T V, V^T G V, K^T K, U^T U): only the tiles on and
 // above the diagonal are formed, dealt round-robin to the waves (at most kSymHold each), and
 // each entry above the diagonal is written to both (r, c) and (c, r), so the result is exactly
 // symmetric.
@@ -227,8 +227,8 @@ __device__ __forceinline__ void prod_sym(const float *A, int as, const float *B,
 }
 
 template <typename Out>
-__device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4, const f4 acc[kSymHold],
-                                   Out out) {
+__device__ __forceinline__ void release_sym(int K, int wave, int i16, int g4,
+                                            const f4 acc[kSymHold], Out out) {
   const int nt = (K + 15) >> 4, nup = nt * (nt + 1) / 2;
 #pragma unroll
   for (int m = 0; m < kSymHold; ++m) {
@@ -403,7 +403,8 @@ void k_big_block(BigArgs a) {
       if (c0 + kChunk < ncol) {
         load_chunk(yrs, yo0, rstep, c0 + kChunk, K, srow, yv);
 #pragma unroll
-        for (int k = 0; k < kStage; ++k) gv[k] = hasg ? a.gradf[goff[k] + (unsigned)(c0 + kChunk)] : 0.f;
+        for (int k = 0; k < kStage; ++k)
+          gv[k] = hasg ? a.gradf[goff[k] + (unsigned)(c0 + kChunk)] : 0.f;
       }
       __syncthreads();
       // every tile slot of the wave runs (a slot past ntiles has rows past K, which read as
@@ -720,8 +721,11 @@ void k_big_block(BigArgs a) {
           // rotation stays orthogonal to about 1e-7 and the basis is re-orthonormalised)
           const float zeta = (aqq - app) * __builtin_amdgcn_rcpf(2.f * apq);
           const float az = fabsf(zeta);
-          const float t = az > 1e15f ? 0.5f * __builtin_amdgcn_rcpf(zeta)
-                                     : copysignf(__builtin_amdgcn_rcpf(az + __builtin_sqrtf(fmaf(zeta, zeta, 1.f))), zeta);
+          const float t =
+              az > 1e15f
+                  ? 0.5f * __builtin_amdgcn_rcpf(zeta)
+                  : copysignf(__builtin_amdgcn_rcpf(az + __builtin_sqrtf(fmaf(zeta, zeta, 1.f))),
+                              zeta);
           c = __builtin_amdgcn_rsqf(fmaf(t, t, 1.f));
           sv = t * c;
         }
