@@ -436,6 +436,11 @@ def bench_warm_start(nt, synth, torch, args) -> int:
                                   "speedup_iters": cold[3]["iters"] / hi},
         "speedup_time": r["t_cold"] / r["t_warm"],
         "speedup_iters": cold[3]["iters"] / max(warm[3]["iters"], 1),
+        "warm_start_result": (
+            "gain: the learned start needs fewer iterations to the stop rule than the zero start"
+            if warm[3]["iters"] < cold[3]["iters"] else
+            "regression: the learned start needs at least as many iterations to the stop rule "
+            "as the zero start"),
         "rel_l2_warm_vs_cold": dist(warm[0], cold[0]),
         "reference": {"rel_tol": 1e-6, "iters": ref[3]["iters"], "converged": ref[3]["converged"],
                       "rel_l2_cold": dist(cold[0], uref), "rel_l2_warm": dist(warm[0], uref),
