@@ -69,12 +69,14 @@ def test_big_blocks_reproducible_and_batched(device):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("nblk,K,ncols", [(24, 100, 396), (9, 17, 45), (13, 55, 33), (5, 64, 70)])
+@pytest.mark.parametrize("nblk,K,ncols", [(24, 100, 396), (9, 17, 45), (13, 55, 33), (5, 64, 70),
+                                          (7, 53, 40), (7, 52, 40)])
 def test_spectral_clip_large_blocks(device, nblk, K, ncols):
     """The projection onto the unit spectral-norm ball (Alg. 1 step 10 by eq. ProxConjugate)
     of K x ncols blocks up to the paper's 10 x 10 windows over 2 x 198 columns, against FP64
     singular value decompositions. Spectral norms are spread around 1 and some blocks get
-    a cluster of singular values just above and below 1."""
+    a cluster of singular values just above and below 1. K = 53 is the smallest block whose
+    kernel has room for the low-rank form of the clip, K = 52 the largest without."""
     print(f"op_spectral_clip nblk={nblk} K={K} ncols={ncols}", flush=True)
     rng = np.random.default_rng(7)
     Y = rng.normal(size=(nblk, K, ncols)) / np.sqrt(ncols)
