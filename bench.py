@@ -217,11 +217,16 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         flops = big_block_dense_flops(n3, K, n1 * n2, st["eig_blocks"] / calls,
                                       st["eig_avg_sweeps"])
         achieved = flops / (block_ms * 1e-3) / 1e12
-        roofline = {"kernel": "k_big_block", "bound": "alu", "achieved": achieved,
+        # the dense products run on v_mfma_f32_16x16x4_f32, whose peak is the FP32 one; the
+        # matrix pipe's busy fraction comes from the committed counter summary of the S3TTV run
+        busy = measured_counter("mfma_busy_frac", "k_big_block") if reg == "s3ttv" else None
+        roofline = {"kernel": "k_big_block", "bound": "mfma", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
                     "avg_launch_ms": block_ms, "launches_timed": calls,
-                    "dense_flops_per_launch": flops}
+                    "dense_flops_per_launch": flops,
+                    "launch_mfma_busy_frac": busy[0] if busy else None,
+                    "busy_source": busy[1] if busy else None}
     out = {
         "metric": f"P-PDS iters/sec + time to the stop rule 1e-5, {n1}x{n2}x{n3} HSI, block 10x10",
         "value": steps / wall,
