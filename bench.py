@@ -220,9 +220,14 @@ def bench_paper_shape(nt, synth, torch, args) -> int:
         # the dense products run on v_mfma_f32_16x16x4_f32, whose peak is the FP32 one; the
         # matrix pipe's busy fraction comes from the committed counter summary of the S3TTV run
         busy = measured_counter("mfma_busy_frac", "k_big_block") if reg == "s3ttv" else None
+        # HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary of this scene
+        traffic = (measured_traffic("k_big_block")
+                   if reg == "s3ttv" and args.scene == "100x100x198" else None)
         roofline = {"kernel": "k_big_block", "bound": "mfma", "achieved": achieved,
                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                    "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                    "traffic": traffic[0] if traffic else None,
+                    "traffic_source": traffic[1] if traffic else None,
                     "avg_launch_ms": block_ms, "launches_timed": calls,
                     "dense_flops_per_launch": flops,
                     "launch_mfma_busy_frac": busy[0] if busy else None,

@@ -33,9 +33,14 @@ def test_traffic_reported_while_source_unchanged(tmp_path, monkeypatch):
 
 
 def test_committed_traffic_line_matches_the_source():
-    # the committed summary belongs to the committed block kernels
+    # the committed summaries belong to the committed block kernels
     got = bench.measured_traffic("k_block_fused")
     assert got is not None and got[0] > 2_000_000_000
+    got = bench.measured_traffic("k_big_block")
+    assert got is not None and got[0] > 3_328_000_000  # at least the dual blocks read and written
+    for kernel in ("k_block_fused", "k_big_block"):
+        busy = bench.measured_counter("mfma_busy_frac", kernel)
+        assert busy is not None and 0.0 < busy[0] < 1.0
 
 
 def test_more_than_one_gpu_is_refused():
